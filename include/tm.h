@@ -1,0 +1,194 @@
+/*
+ * tm.h -- C ABI of the MI355X (gfx950) template matcher.
+ *
+ * The library implements the fast template matching scheme of
+ * "Fast Template Matching by Subsampled Circulant Matrix" (Hsieh, Lu, Pei,
+ * arXiv 1509.04863): given a signal x of length N and a template t of length
+ * K it returns the cyclic shift m^ that the paper's Algorithm 1 selects as
+ * the maximiser of the cross-correlation (Tx)_k = sum_{j<K} t_j x_{(k+j) mod N}
+ * (Eq. (1) with the similarity of Section 3).
+ *
+ * Every step runs on the GPU: the fold of Algorithm 1 step 3 (Eq. (2)), the
+ * correlation of steps 4-6 by FFT, the argmax of step 7 and the candidate
+ * intersection of steps 8-9 (Theorem 4, Chinese remaindering).
+ *
+ * Conventions for every entry point
+ *   - Sizes are element counts.  Device pointers are HIP device addresses
+ *     (memory from hipMalloc or any allocator on the same device).
+ *   - Streams are hipStream_t values passed as void*; NULL is the null stream.
+ *   - Nothing throws across the ABI.  Every call returns a tm_status.  On an
+ *     error nothing has been launched and no output has been written;
+ *     tm_last_error() returns a message for the calling thread.
+ *   - Arguments are validated on the host before any launch.
+ *
+ * Readings of the paper that fix behaviour visible here:
+ *   - shifts range over [0, N) (Eq. (1) prints 0 < k < N);
+ *   - steps 4-6 compute a cross-correlation (step 6 prints a product of
+ *     spectra, which would be a convolution);
+ *   - the fold keeps Algorithm 1's cyclic indices when M does not divide N;
+ *   - each argmax runs over [0, M) and ties go to the lowest index;
+ *   - candidate sets are taken mod N; several common candidates are re-scored
+ *     by (Tx)_c (largest wins, lowest index on ties); none gives shift = -1.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TM_OK = 0,
+  TM_ERR_INVALID = 1,      /* bad argument: sizes, moduli, dtypes, null pointers, alignment */
+  TM_ERR_NOMEM = 2,        /* device or pinned host allocation failed */
+  TM_ERR_DEVICE = 3,       /* a HIP call failed; tm_last_error() has the HIP message */
+  TM_ERR_UNSUPPORTED = 4   /* valid request this build cannot run (e.g. FFT length too large) */
+} tm_status;
+
+typedef enum {
+  TM_I8 = 0,               /* int8_t */
+  TM_F32 = 1,              /* float */
+  TM_BF16 = 2,             /* bfloat16 (storage only; arithmetic in float) */
+  TM_F16 = 3               /* IEEE half (storage only; arithmetic in float) */
+} tm_dtype;
+
+/* plan flags */
+#define TM_F_EXACT      0x1u /* x and t hold integer values: fold in int32, FFT in FP64,
+                                correlations rounded to integers.  Implied when both
+                                dtypes are TM_I8.  Precondition: every partial sum of x
+                                fits in int32 (e.g. |x_i| * ceil(N/M) < 2^31). */
+#define TM_F_REAL       0x2u /* force the real (FP32 FFT) path even for int8 inputs */
+
+/* result flags */
+#define TM_R_NOMATCH    0x1u /* S_M1 and S_M2 share no element: shift = -1 */
+#define TM_R_RESCORED   0x2u /* more than one common candidate; chosen by (Tx)_c */
+#define TM_R_NEAR_TIE   0x4u /* real path: an argmax's top-2 gap is below 1e-5 of its fold's peak */
+#define TM_R_EXACT      0x8u /* exact path and the FP64 FFT error bound is below 1/2, so
+                                every correlation value is the exact integer */
+
+typedef struct {
+  int64_t n;          /* signal length N >= 1 */
+  int32_t k;          /* template length, 1 <= K <= N */
+  int32_t m1, m2;     /* fold lengths; both 0 = automatic rule M1 = max(c*K, m0(N)),
+                         M2 = M1 + 1 where m0(N) is the least m with m(m+1) > N
+                         (Algorithm 1 step 2, with M1 = K, M2 = K + 1 of Section 4
+                         raised when K(K+1) <= N).  Explicit values must satisfy
+                         gcd(M1, M2) = 1, M1 >= K, M2 >= K, M1*M2 >= N (Theorem 4). */
+  int32_t fold_mult;  /* c in {1, 2} for the automatic rule; 0 means 1 */
+  int32_t x_dtype;    /* tm_dtype of x */
+  int32_t t_dtype;    /* tm_dtype of t */
+  int32_t fold_store; /* real path only: storage format of the folded signal fed to
+                         the FFT: TM_F32 (default), TM_BF16 or TM_F16 */
+  uint32_t flags;     /* TM_F_* */
+} tm_plan_desc;
+
+typedef struct tm_plan_s* tm_plan;
+
+typedef struct {
+  int64_t  shift;        /* m^ in [0, N), or -1 with TM_R_NOMATCH */
+  int32_t  m1_tilde;     /* argmax over [0, M1) of the M1-fold correlation (step 7) */
+  int32_t  m2_tilde;     /* argmax over [0, M2) of the M2-fold correlation */
+  int32_t  n_candidates; /* |S_M1 cap S_M2| before re-scoring, 0..3 */
+  uint32_t flags;        /* TM_R_* */
+  double   peak1;        /* r_M1[m1_tilde] (an integer on the exact path) */
+  double   peak2;        /* r_M2[m2_tilde] */
+  double   score;        /* (Tx)_shift: exact integer on the exact path, FP64 sum
+                            otherwise; 0 when shift = -1 */
+} tm_result;             /* 48 bytes */
+
+/* Host-side plan parameters (no GPU needed). */
+typedef struct {
+  int32_t m1, m2;        /* chosen fold lengths (user order) */
+  int32_t l1, l2;        /* ceil(N / M1), ceil(N / M2) */
+  int32_t fft_log2;      /* P = 2^fft_log2 >= max(M1, M2) + K - 1 */
+  int32_t exact;         /* 1 = exact (integer) path, 0 = real path */
+  int32_t dual;          /* 1 = |M1 - M2| = 1: both folds from one read of x */
+  int32_t fft_in_lds;    /* 1 = the whole FFT fits one workgroup's LDS */
+  int64_t workspace_bytes; /* device workspace one match of this plan uses */
+  int64_t x_bytes;       /* bytes of x read per match */
+} tm_plan_info;
+
+/*
+ * tm_plan_params -- validate desc and compute the plan parameters on the host.
+ * Pure host code: needs no GPU and touches no device.
+ * Errors: TM_ERR_INVALID for K < 1, K > N, bad explicit moduli (see
+ * tm_plan_desc.m1), fold_mult outside {0,1,2}, unknown dtypes or flags.
+ */
+tm_status tm_plan_params(const tm_plan_desc* desc, tm_plan_info* info);
+
+/*
+ * tm_plan_create -- Algorithm 1 steps 2 and 4 for a fixed template.
+ * Chooses (M1, M2) and the FFT length P, copies t (K elements of desc->t_dtype,
+ * host memory when t_is_device = 0, device memory otherwise) to the device,
+ * generates the length-P twiddles in FP64 on the GPU and stores the scaled
+ * template spectrum conj(FFT_P([t 0])) / P the correlation uses.
+ * The plan owns its device memory, is immutable after creation and may be used
+ * from several streams at once.  Work is enqueued on `stream` and the call
+ * waits for it before returning.
+ */
+tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_device,
+                         void* stream, tm_plan* out);
+
+/* tm_plan_destroy -- waits for the device, frees the plan.  NULL is allowed. */
+tm_status tm_plan_destroy(tm_plan plan);
+
+/* tm_plan_get_info -- parameters of an existing plan. */
+tm_status tm_plan_get_info(tm_plan plan, tm_plan_info* info);
+
+/*
+ * tm_match -- one signal, Algorithm 1 steps 3 and 5-9.
+ * x: device pointer to N elements of the plan's x_dtype, 4-byte aligned at
+ *    least (16-byte aligned reads are used when possible).  Read only.
+ * out: one tm_result in host or device memory.  With host memory the call
+ *    waits for the stream; with device memory it only enqueues work and `out`
+ *    is valid once the stream reaches this point.
+ * The caller keeps x (and a device `out`) alive until then.
+ */
+tm_status tm_match(tm_plan plan, const void* x, tm_result* out, void* stream);
+
+/*
+ * tm_match_batch -- `count` independent matches in one launch sequence
+ * (uneven N and K allowed; plans may repeat).  plans[i] with xs[i] gives
+ * out[i].  `out` points to count results in host or device memory (same rule
+ * as tm_match).  The arrays plans and xs are host arrays read during the call.
+ * Each result equals the one tm_match returns for the same plan and signal,
+ * bit for bit.
+ */
+tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const* xs,
+                         tm_result* out, void* stream);
+
+/*
+ * tm_match_intermediates -- tm_match that also writes the intermediate vectors
+ * (for parity checks): y1[0..M1+K-1) and y2[0..M2+K-1) are the literal folds of
+ * Algorithm 1 step 3 (after the fold_store rounding on the real path),
+ * r1[0..M1) and r2[0..M2) the correlations of step 6 (rounded to integers on the
+ * exact path).  All four are device arrays of double; any may be NULL.
+ */
+tm_status tm_match_intermediates(tm_plan plan, const void* x, tm_result* out,
+                                 double* y1, double* y2, double* r1, double* r2,
+                                 void* stream);
+
+/*
+ * Kernel timing for benchmarks.  While enabled, every match call records a pair
+ * of HIP events around its fold kernel launch on the call's stream.
+ * tm_profile_read waits for the recorded events and returns the summed fold
+ * kernel time in milliseconds and the number of fold launches since the last
+ * reset (reset != 0 clears the record).
+ */
+tm_status tm_profile_enable(int on);
+tm_status tm_profile_read(double* fold_ms_total, int64_t* fold_launches, int reset);
+
+/* Message strings. tm_last_error is per calling thread. */
+const char* tm_status_string(tm_status status);
+const char* tm_last_error(void);
+
+/* Library version "major.minor.patch". */
+const char* tm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

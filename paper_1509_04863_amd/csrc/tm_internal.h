@@ -1,0 +1,95 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "tm.h"
+
+namespace tmi {
+
+enum : int32_t { MODE_EXACT = 0, MODE_REAL = 1 };
+
+// Tiles of one row view of x: x read as rows of `m` elements (row i holds
+// x[i*m .. i*m+m)), cut into tiles of `rows` x `cols` elements.
+struct View {
+  int32_t m;      // row length (a fold modulus)
+  int32_t l;      // number of rows, ceil(N / m)
+  int32_t rows;   // tile rows R
+  int32_t cols;   // tile columns W
+  int32_t nrb;    // row blocks, ceil(l / R)
+  int32_t ncb;    // column blocks, ceil(m / W)
+};
+
+// Everything a launch needs about one matching instance.  Built on the host,
+// read by every kernel; 16-byte aligned so a table of them can be copied as is.
+struct alignas(16) Inst {
+  const void* x;          // signal (device)
+  int64_t n;              // N
+  int32_t k;              // K
+  int32_t x_dtype;        // tm_dtype
+  int32_t t_dtype;        // tm_dtype
+  int32_t mode;           // MODE_EXACT / MODE_REAL
+  int32_t fold_store;     // tm_dtype used to store the fold on the real path
+  int32_t dual;           // 1: mb == ma + 1, fold B comes from view A's diagonals
+  int32_t swapped;        // 1: the user's M1 is mb (results are mapped back)
+  int32_t p_log2;         // FFT length P = 2^p_log2
+  View va;                // view with modulus ma (always tiled)
+  View vb;                // view with modulus mb (tiled only when !dual)
+  int32_t tile_base;      // first fold tile of this instance in the launch
+  int32_t ntiles;         // fold tiles of this instance
+  int32_t red_base;       // first reduce chunk of this instance in the launch
+  int32_t nred;           // reduce chunks of this instance
+  int64_t inv_a_mod_b;    // ma^{-1} mod mb
+  // workspace (device)
+  void* col_a;            // [va.nrb][ma] column partials
+  void* diag;             // [va.nrb][va.ncb][va.cols + va.rows - 1] diagonal partials (dual)
+  void* col_b;            // [vb.nrb][mb] column partials (!dual)
+  void* y;                // literal folds: [ma + k - 1] then [mb + k - 1]
+  // plan (device)
+  const void* t;          // template, t_dtype
+  const void* spec;       // P complex values: conj(FFT_P(t)) / P at bit-reversed positions
+  const void* tw;         // P/2 complex values W^e = exp(-2 pi i e / P)
+  double tnorm1;          // sum |t_j|
+  tm_result* out;         // device result slot
+  double* dbg_y1;         // optional intermediates (user order), may be null
+  double* dbg_y2;
+  double* dbg_r1;
+  double* dbg_r2;
+};
+
+// A launch's view of its instances: a device table, or one instance inline in
+// the kernel arguments (single matches skip the table upload).
+struct InstTable {
+  const Inst* table;      // device pointer, or nullptr to use `one`
+  int32_t count;
+  Inst one;
+  __device__ __forceinline__ const Inst& get(int i) const { return table ? table[i] : one; }
+};
+
+constexpr int kFoldThreads = 256;
+constexpr int kReduceThreads = 256;
+constexpr int kReduceChunk = 2048;      // fold entries one reduce workgroup produces
+constexpr int kFinishThreads = 512;
+
+// Element sizes of tm_dtype values.
+inline int dtype_bytes(int dt) { return dt == TM_I8 ? 1 : (dt == TM_F32 ? 4 : 2); }
+
+// Dynamic LDS bytes the kernels need.
+size_t fold_lds_bytes(const View& v, int x_dtype);
+size_t finish_lds_bytes(int p_log2, int mode);
+int fft_lds_max_log2(int mode);         // largest P (log2) whose FFT fits one workgroup
+
+// Kernel launchers (tm_kernels.hip).
+hipError_t configure_kernels();        // raise dynamic LDS limits on the current device
+hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStream_t s);
+hipError_t launch_reduce(const InstTable& tab, int total_chunks, hipStream_t s);
+hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, int mode,
+                         size_t lds, hipStream_t s);
+hipError_t launch_twiddles(void* tw, int p_log2, int as_double, hipStream_t s);
+hipError_t launch_spectrum(const void* t, int t_dtype, int k, int p_log2, const double* tw64,
+                           double* scratch, void* spec, int as_double, hipStream_t s);
+
+}  // namespace tmi

@@ -1,0 +1,637 @@
+// Host runtime and C ABI of the template matcher: plan construction
+// (Algorithm 1 steps 2 and 4), per-stream workspace pools and the launch
+// sequence fold -> reduce -> finish for single and batched matches.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "tm_internal.h"
+
+using namespace tmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+tm_status fail(tm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define TM_HIP(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? TM_ERR_NOMEM : TM_ERR_DEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+int64_t env_int(const char* name, int64_t dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::strtoll(v, nullptr, 10);
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) { const int64_t t = a % b; a = b; b = t; }
+  return a;
+}
+
+// a^{-1} mod m for gcd(a, m) = 1 (extended Euclid); 0 when m == 1
+int64_t mod_inverse(int64_t a, int64_t m) {
+  if (m == 1) return 0;
+  int64_t g = m, x = 0, x1 = 1, a1 = a % m;
+  while (a1) {
+    const int64_t q = g / a1;
+    int64_t t = g - q * a1; g = a1; a1 = t;
+    t = x - q * x1; x = x1; x1 = t;
+  }
+  return ((x % m) + m) % m;
+}
+
+// least m >= 1 with m (m + 1) > n
+int64_t least_m0(int64_t n) {
+  int64_t m = (int64_t)std::sqrt((double)n);
+  if (m < 1) m = 1;
+  while (m > 1 && (m - 1) * m > n) --m;
+  while (m * (m + 1) <= n) ++m;
+  return m;
+}
+
+bool valid_dtype(int32_t dt) { return dt >= TM_I8 && dt <= TM_F16; }
+
+// Tile shape of one row view: rows of m elements, tiles of about
+// TM_TILE_BYTES bytes that are TM_TILE_WBYTES bytes wide.
+View make_view(int64_t n, int64_t m, int eb) {
+  View v{};
+  v.m = (int32_t)m;
+  v.l = (int32_t)ceil_div(n, m);
+  const int64_t tile_bytes = std::max<int64_t>(1024, env_int("TM_TILE_BYTES", 32768));
+  const int64_t wbytes = std::max<int64_t>(16, env_int("TM_TILE_WBYTES", 512));
+  const int64_t w = std::min<int64_t>(m, std::max<int64_t>(1, wbytes / eb));
+  const int64_t r = std::max<int64_t>(1, std::min<int64_t>(v.l, tile_bytes / (w * eb)));
+  v.cols = (int32_t)w;
+  v.rows = (int32_t)r;
+  v.nrb = (int32_t)ceil_div(v.l, r);
+  v.ncb = (int32_t)ceil_div(m, w);
+  return v;
+}
+
+// Plan parameters derived from the descriptor; pure host arithmetic.
+struct Core {
+  int64_t n = 0;
+  int32_t k = 0, m1 = 0, m2 = 0, ma = 0, mb = 0;
+  int32_t swapped = 0, dual = 0, mode = MODE_EXACT, p_log2 = 1;
+  int32_t x_dtype = 0, t_dtype = 0, fold_store = TM_F32;
+  int64_t inv = 0;
+  View va{}, vb{};
+  // workspace offsets (bytes) of one instance
+  size_t off_col_a = 0, off_diag = 0, off_col_b = 0, off_y = 0, off_res = 0, ws_bytes = 0;
+  int32_t ntiles = 0, nred = 0;
+  size_t fold_lds = 0, finish_lds = 0;
+  int fft_in_lds = 1;
+};
+
+tm_status compute_core(const tm_plan_desc* d, Core* c) {
+  if (!d) return fail(TM_ERR_INVALID, "null plan descriptor");
+  if (d->n < 1) return fail(TM_ERR_INVALID, "N must be >= 1");
+  if (d->k < 1 || (int64_t)d->k > d->n) return fail(TM_ERR_INVALID, "need 1 <= K <= N");
+  if (!valid_dtype(d->x_dtype) || !valid_dtype(d->t_dtype)) return fail(TM_ERR_INVALID, "unknown dtype");
+  // TM_I8 (0, the zero-initialised value) selects the default TM_F32
+  const int32_t fs = d->fold_store == TM_I8 ? TM_F32 : d->fold_store;
+  if (fs != TM_F32 && fs != TM_BF16 && fs != TM_F16)
+    return fail(TM_ERR_INVALID, "fold_store must be TM_F32, TM_BF16 or TM_F16");
+  if (d->fold_mult < 0 || d->fold_mult > 2) return fail(TM_ERR_INVALID, "fold_mult must be 0, 1 or 2");
+  if (d->flags & ~(TM_F_EXACT | TM_F_REAL)) return fail(TM_ERR_INVALID, "unknown plan flags");
+  if ((d->flags & TM_F_EXACT) && (d->flags & TM_F_REAL))
+    return fail(TM_ERR_INVALID, "TM_F_EXACT and TM_F_REAL are exclusive");
+  if (d->n > (int64_t(1) << 40)) return fail(TM_ERR_INVALID, "N above 2^40 is not supported");
+
+  c->n = d->n;
+  c->k = d->k;
+  c->x_dtype = d->x_dtype;
+  c->t_dtype = d->t_dtype;
+  c->fold_store = fs;
+  int64_t m1 = d->m1, m2 = d->m2;
+  if (m1 == 0 && m2 == 0) {
+    const int64_t mult = d->fold_mult == 0 ? 1 : d->fold_mult;
+    m1 = std::max<int64_t>(mult * d->k, least_m0(d->n));
+    m2 = m1 + 1;
+  } else {
+    if (m1 < 1 || m2 < 1) return fail(TM_ERR_INVALID, "explicit M1 and M2 must both be >= 1");
+    if (m1 < d->k || m2 < d->k) return fail(TM_ERR_INVALID, "need M1 >= K and M2 >= K");
+    if (gcd64(m1, m2) != 1) return fail(TM_ERR_INVALID, "M1 and M2 must be co-prime");
+    if (m1 * m2 < d->n) return fail(TM_ERR_INVALID, "need M1 * M2 >= N");
+  }
+  if (m1 >= (int64_t(1) << 30) || m2 >= (int64_t(1) << 30))
+    return fail(TM_ERR_INVALID, "fold lengths above 2^30 are not supported");
+  c->m1 = (int32_t)m1;
+  c->m2 = (int32_t)m2;
+  if (m2 == m1 + 1) { c->ma = (int32_t)m1; c->mb = (int32_t)m2; c->dual = 1; }
+  else if (m1 == m2 + 1) { c->ma = (int32_t)m2; c->mb = (int32_t)m1; c->dual = 1; c->swapped = 1; }
+  else { c->ma = (int32_t)m1; c->mb = (int32_t)m2; }
+  c->inv = mod_inverse(c->ma, c->mb);
+
+  const bool both_int = d->x_dtype == TM_I8 && d->t_dtype == TM_I8;
+  c->mode = (d->flags & TM_F_REAL) ? MODE_REAL
+            : ((d->flags & TM_F_EXACT) || both_int) ? MODE_EXACT : MODE_REAL;
+
+  const int64_t need = std::max<int64_t>(c->ma, c->mb) + d->k - 1;
+  int p = 1;
+  while ((int64_t(1) << p) < need) ++p;
+  c->p_log2 = p;
+  c->fft_in_lds = p <= fft_lds_max_log2(c->mode);
+
+  const int eb = dtype_bytes(d->x_dtype);
+  c->va = make_view(d->n, c->ma, eb);
+  if (c->dual) {
+    c->vb = View{};
+    c->vb.m = c->mb;
+    c->vb.l = (int32_t)ceil_div(d->n, c->mb);
+  } else {
+    c->vb = make_view(d->n, c->mb, eb);
+  }
+  c->ntiles = c->va.nrb * c->va.ncb + (c->dual ? 0 : c->vb.nrb * c->vb.ncb);
+  const int64_t ytot = (int64_t)c->ma + c->k - 1 + c->mb + c->k - 1;
+  c->nred = (int32_t)ceil_div(ytot, kReduceChunk);
+
+  size_t off = 0;
+  c->off_col_a = off; off = align256(off + (size_t)c->va.nrb * c->ma * 4);
+  c->off_diag = off;
+  if (c->dual) off = align256(off + (size_t)c->va.nrb * c->va.ncb * (c->va.cols + c->va.rows - 1) * 4);
+  c->off_col_b = off;
+  if (!c->dual) off = align256(off + (size_t)c->vb.nrb * c->mb * 4);
+  c->off_y = off; off = align256(off + (size_t)ytot * 4);
+  c->off_res = off; off = align256(off + sizeof(tm_result));
+  c->ws_bytes = off;
+  c->fold_lds = std::max(fold_lds_bytes(c->va, d->x_dtype), c->dual ? 0 : fold_lds_bytes(c->vb, d->x_dtype));
+  c->finish_lds = finish_lds_bytes(p, c->mode);
+  return TM_OK;
+}
+
+void fill_info(const Core& c, tm_plan_info* info) {
+  info->m1 = c.m1;
+  info->m2 = c.m2;
+  info->l1 = (int32_t)ceil_div(c.n, c.m1);
+  info->l2 = (int32_t)ceil_div(c.n, c.m2);
+  info->fft_log2 = c.p_log2;
+  info->exact = c.mode == MODE_EXACT;
+  info->dual = c.dual;
+  info->fft_in_lds = c.fft_in_lds;
+  info->workspace_bytes = (int64_t)c.ws_bytes;
+  info->x_bytes = c.n * dtype_bytes(c.x_dtype);
+}
+
+// ---------------------------------------------------------------- pools
+
+struct StreamPool {
+  void* dev = nullptr;
+  size_t cap = 0;
+  void* host = nullptr;          // pinned staging for descriptor tables
+  size_t hcap = 0;
+  hipEvent_t staged = nullptr;   // completes when the last staging copy has been read
+  bool staged_pending = false;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, StreamPool> g_pools;
+
+// fold kernel timing (tm_profile_*), guarded by g_mu
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_live;   // recorded, not yet read
+std::vector<hipEvent_t> g_prof_free;
+double g_prof_ms = 0.0;
+int64_t g_prof_n = 0;
+
+hipError_t prof_event(hipEvent_t* e) {
+  if (!g_prof_free.empty()) { *e = g_prof_free.back(); g_prof_free.pop_back(); return hipSuccess; }
+  return hipEventCreate(e);
+}
+
+// launch_fold wrapped with the optional timing events
+hipError_t timed_fold(const InstTable& tab, int tiles, size_t lds, hipStream_t s) {
+  if (!g_prof_on) return launch_fold(tab, tiles, lds, s);
+  hipEvent_t a, b;
+  hipError_t e = prof_event(&a);
+  if (e != hipSuccess) return e;
+  if ((e = prof_event(&b)) != hipSuccess) return e;
+  if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
+  if ((e = launch_fold(tab, tiles, lds, s)) != hipSuccess) return e;
+  if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+  g_prof_live.emplace_back(a, b);
+  return hipSuccess;
+}
+bool g_configured[64] = {};
+
+tm_status ensure_device(StreamPool& p, size_t need, hipStream_t s) {
+  if (p.cap >= need) return TM_OK;
+  if (p.dev) {
+    TM_HIP(hipStreamSynchronize(s));   // in-flight work may still use the old buffer
+    TM_HIP(hipFree(p.dev));
+    p.dev = nullptr;
+    p.cap = 0;
+  }
+  const size_t cap = align256(need + need / 4);
+  TM_HIP(hipMalloc(&p.dev, cap));
+  p.cap = cap;
+  return TM_OK;
+}
+
+tm_status ensure_host(StreamPool& p, size_t need) {
+  if (p.staged_pending) {
+    TM_HIP(hipEventSynchronize(p.staged));
+    p.staged_pending = false;
+  }
+  if (p.hcap >= need) return TM_OK;
+  if (p.host) TM_HIP(hipHostFree(p.host));
+  p.host = nullptr;
+  p.hcap = 0;
+  const size_t cap = align256(need + need / 4);
+  TM_HIP(hipHostMalloc(&p.host, cap, hipHostMallocDefault));
+  p.hcap = cap;
+  if (!p.staged) TM_HIP(hipEventCreateWithFlags(&p.staged, hipEventDisableTiming));
+  return TM_OK;
+}
+
+bool is_device_pointer(const void* ptr) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- plan
+
+struct tm_plan_s {
+  tm_plan_desc desc{};
+  Core core;
+  int device = 0;
+  void* t_dev = nullptr;
+  void* tw64 = nullptr;
+  void* tw32 = nullptr;
+  void* spec = nullptr;
+  double tnorm1 = 0.0;
+};
+
+namespace {
+
+tm_status configure_device(int dev) {
+  if (dev >= 0 && dev < 64 && !g_configured[dev]) {
+    hipError_t e = configure_kernels();
+    if (e != hipSuccess) return fail(TM_ERR_DEVICE, std::string("configure kernels: ") + hipGetErrorString(e));
+    g_configured[dev] = true;
+  }
+  return TM_OK;
+}
+
+void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
+  const Core& c = p->core;
+  std::memset(in, 0, sizeof(*in));
+  in->x = x;
+  in->n = c.n;
+  in->k = c.k;
+  in->x_dtype = c.x_dtype;
+  in->t_dtype = c.t_dtype;
+  in->mode = c.mode;
+  in->fold_store = c.fold_store;
+  in->dual = c.dual;
+  in->swapped = c.swapped;
+  in->p_log2 = c.p_log2;
+  in->va = c.va;
+  in->vb = c.vb;
+  in->ntiles = c.ntiles;
+  in->nred = c.nred;
+  in->inv_a_mod_b = c.inv;
+  in->t = p->t_dev;
+  in->spec = p->spec;
+  in->tw = c.mode == MODE_EXACT ? p->tw64 : p->tw32;
+  in->tnorm1 = p->tnorm1;
+}
+
+void place_workspace(const Core& c, char* base, Inst* in) {
+  in->col_a = base + c.off_col_a;
+  in->diag = c.dual ? base + c.off_diag : nullptr;
+  in->col_b = c.dual ? nullptr : base + c.off_col_b;
+  in->y = base + c.off_y;
+}
+
+tm_status check_plan_for_match(tm_plan p) {
+  if (!p) return fail(TM_ERR_INVALID, "null plan");
+  if (!p->core.fft_in_lds)
+    return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(p->core.p_log2) +
+                                        " exceeds one workgroup's LDS on this build");
+  return TM_OK;
+}
+
+tm_status check_x(const tm_plan_s* p, const void* x) {
+  if (!x) return fail(TM_ERR_INVALID, "null signal pointer");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(x);
+  if (a % (uintptr_t)dtype_bytes(p->core.x_dtype)) return fail(TM_ERR_INVALID, "signal is not aligned to its element size");
+  return TM_OK;
+}
+
+double host_value(const void* t, int dt, int64_t i) {
+  switch (dt) {
+    case TM_I8: return (double)static_cast<const int8_t*>(t)[i];
+    case TM_F32: return (double)static_cast<const float*>(t)[i];
+    case TM_BF16: {
+      uint32_t u = (uint32_t)static_cast<const uint16_t*>(t)[i] << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      return f;
+    }
+    default: {
+      const uint16_t h = static_cast<const uint16_t*>(t)[i];
+      const int sgn = h >> 15, ex = (h >> 10) & 31, man = h & 1023;
+      double v = ex == 0 ? std::ldexp((double)man, -24) : (ex == 31 ? INFINITY : std::ldexp((double)(man | 1024), ex - 25));
+      return sgn ? -v : v;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tm_version(void) { return "0.1.0"; }
+
+const char* tm_status_string(tm_status s) {
+  switch (s) {
+    case TM_OK: return "ok";
+    case TM_ERR_INVALID: return "invalid argument";
+    case TM_ERR_NOMEM: return "out of memory";
+    case TM_ERR_DEVICE: return "device error";
+    case TM_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* tm_last_error(void) { return g_err.c_str(); }
+
+tm_status tm_plan_params(const tm_plan_desc* desc, tm_plan_info* info) {
+  if (!info) return fail(TM_ERR_INVALID, "null info");
+  Core c;
+  const tm_status s = compute_core(desc, &c);
+  if (s != TM_OK) return s;
+  fill_info(c, info);
+  return TM_OK;
+}
+
+tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_device, void* stream,
+                         tm_plan* out) {
+  if (!out) return fail(TM_ERR_INVALID, "null plan output");
+  *out = nullptr;
+  if (!t) return fail(TM_ERR_INVALID, "null template pointer");
+  Core c;
+  tm_status st = compute_core(desc, &c);
+  if (st != TM_OK) return st;
+  if (!c.fft_in_lds)
+    return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(c.p_log2) +
+                                        " exceeds one workgroup's LDS on this build");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  TM_HIP(hipGetDevice(&dev));
+  st = configure_device(dev);
+  if (st != TM_OK) return st;
+
+  const size_t tb = (size_t)c.k * dtype_bytes(c.t_dtype);
+  std::vector<unsigned char> th(tb);
+  if (t_is_device) {
+    TM_HIP(hipMemcpy(th.data(), t, tb, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(th.data(), t, tb);
+  }
+  double norm1 = 0.0;
+  for (int64_t i = 0; i < c.k; ++i) {
+    const double v = host_value(th.data(), c.t_dtype, i);
+    if (!std::isfinite(v)) return fail(TM_ERR_INVALID, "template holds a non-finite value");
+    if (c.mode == MODE_EXACT && v != std::nearbyint(v))
+      return fail(TM_ERR_INVALID, "exact path needs an integer-valued template");
+    norm1 += std::fabs(v);
+  }
+
+  tm_plan_s* p = new tm_plan_s();
+  p->desc = *desc;
+  p->core = c;
+  p->device = dev;
+  p->tnorm1 = norm1;
+  const size_t P = size_t(1) << c.p_log2;
+  void* z = nullptr;
+  auto cleanup = [&]() {
+    if (z) (void)hipFree(z);
+    if (p->t_dev) (void)hipFree(p->t_dev);
+    if (p->tw64) (void)hipFree(p->tw64);
+    if (p->tw32) (void)hipFree(p->tw32);
+    if (p->spec) (void)hipFree(p->spec);
+    delete p;
+  };
+#define TM_HIP_PLAN(expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      cleanup();                                                                       \
+      return fail(e_ == hipErrorOutOfMemory ? TM_ERR_NOMEM : TM_ERR_DEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    }                                                                                  \
+  } while (0)
+  TM_HIP_PLAN(hipMalloc(&p->t_dev, std::max<size_t>(tb, 16)));
+  TM_HIP_PLAN(hipMemcpyAsync(p->t_dev, th.data(), tb, hipMemcpyHostToDevice, s));
+  TM_HIP_PLAN(hipMalloc(&p->tw64, std::max<size_t>(P / 2, 1) * 16));
+  TM_HIP_PLAN(launch_twiddles(p->tw64, c.p_log2, 1, s));
+  if (c.mode == MODE_REAL) {
+    TM_HIP_PLAN(hipMalloc(&p->tw32, std::max<size_t>(P / 2, 1) * 8));
+    TM_HIP_PLAN(launch_twiddles(p->tw32, c.p_log2, 0, s));
+  }
+  TM_HIP_PLAN(hipMalloc(&p->spec, P * (c.mode == MODE_EXACT ? 16 : 8)));
+  TM_HIP_PLAN(hipMalloc(&z, P * 16));
+  TM_HIP_PLAN(launch_spectrum(p->t_dev, c.t_dtype, c.k, c.p_log2, static_cast<const double*>(p->tw64),
+                              static_cast<double*>(z), p->spec, c.mode == MODE_EXACT, s));
+  TM_HIP_PLAN(hipStreamSynchronize(s));
+  TM_HIP_PLAN(hipFree(z));
+  z = nullptr;
+#undef TM_HIP_PLAN
+  *out = p;
+  return TM_OK;
+}
+
+tm_status tm_plan_destroy(tm_plan p) {
+  if (!p) return TM_OK;
+  TM_HIP(hipDeviceSynchronize());
+  if (p->t_dev) TM_HIP(hipFree(p->t_dev));
+  if (p->tw64) TM_HIP(hipFree(p->tw64));
+  if (p->tw32) TM_HIP(hipFree(p->tw32));
+  if (p->spec) TM_HIP(hipFree(p->spec));
+  delete p;
+  return TM_OK;
+}
+
+tm_status tm_plan_get_info(tm_plan p, tm_plan_info* info) {
+  if (!p || !info) return fail(TM_ERR_INVALID, "null argument");
+  fill_info(p->core, info);
+  return TM_OK;
+}
+
+static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1, double* y2,
+                           double* r1, double* r2, void* stream) {
+  tm_status st = check_plan_for_match(p);
+  if (st != TM_OK) return st;
+  st = check_x(p, x);
+  if (st != TM_OK) return st;
+  if (!out) return fail(TM_ERR_INVALID, "null result pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dev_out = is_device_pointer(out);
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamPool& pool = g_pools[{p->device, s}];
+  st = ensure_device(pool, p->core.ws_bytes, s);
+  if (st != TM_OK) return st;
+  InstTable tab{};
+  tab.table = nullptr;
+  tab.count = 1;
+  fill_inst(p, x, &tab.one);
+  char* base = static_cast<char*>(pool.dev);
+  place_workspace(p->core, base, &tab.one);
+  tab.one.tile_base = 0;
+  tab.one.red_base = 0;
+  tab.one.out = dev_out ? out : reinterpret_cast<tm_result*>(base + p->core.off_res);
+  tab.one.dbg_y1 = y1;
+  tab.one.dbg_y2 = y2;
+  tab.one.dbg_r1 = r1;
+  tab.one.dbg_r2 = r2;
+  TM_HIP(timed_fold(tab, p->core.ntiles, p->core.fold_lds, s));
+  TM_HIP(launch_reduce(tab, p->core.nred, s));
+  TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.finish_lds, s));
+  if (!dev_out) {
+    TM_HIP(hipMemcpyAsync(out, tab.one.out, sizeof(tm_result), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+  }
+  return TM_OK;
+}
+
+tm_status tm_match(tm_plan p, const void* x, tm_result* out, void* stream) {
+  return match_one(p, x, out, nullptr, nullptr, nullptr, nullptr, stream);
+}
+
+tm_status tm_match_intermediates(tm_plan p, const void* x, tm_result* out, double* y1, double* y2,
+                                 double* r1, double* r2, void* stream) {
+  return match_one(p, x, out, y1, y2, r1, r2, stream);
+}
+
+tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
+                         void* stream) {
+  if (count < 0) return fail(TM_ERR_INVALID, "negative count");
+  if (count == 0) return TM_OK;
+  if (!plans || !xs || !out) return fail(TM_ERR_INVALID, "null argument");
+  for (int32_t i = 0; i < count; ++i) {
+    tm_status st = check_plan_for_match(plans[i]);
+    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+    st = check_x(plans[i], xs[i]);
+    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dev_out = is_device_pointer(out);
+
+  // layout: [instance workspaces][results if host out][table][lists]
+  std::vector<size_t> ws_off(count);
+  size_t ws = 0;
+  int64_t tiles = 0, chunks = 0;
+  size_t fold_lds = 0, lds_exact = 0, lds_real = 0;
+  int n_exact = 0, n_real = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const Core& c = plans[i]->core;
+    ws_off[i] = ws;
+    ws += c.ws_bytes;
+    tiles += c.ntiles;
+    chunks += c.nred;
+    fold_lds = std::max(fold_lds, c.fold_lds);
+    if (c.mode == MODE_EXACT) { lds_exact = std::max(lds_exact, c.finish_lds); ++n_exact; }
+    else { lds_real = std::max(lds_real, c.finish_lds); ++n_real; }
+  }
+  if (tiles > 0x7fffffff || chunks > 0x7fffffff) return fail(TM_ERR_UNSUPPORTED, "batch too large");
+  const size_t off_res = align256(ws);
+  const size_t off_tab = align256(off_res + (dev_out ? 0 : sizeof(tm_result) * (size_t)count));
+  const size_t tab_bytes = sizeof(Inst) * (size_t)count;
+  const size_t off_lists = off_tab + tab_bytes;   // sizeof(Inst) keeps the list 16-byte aligned
+  const size_t list_bytes = sizeof(int32_t) * (size_t)count;
+  const size_t total = off_lists + list_bytes;
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamPool& pool = g_pools[{plans[0]->device, s}];
+  tm_status st = ensure_device(pool, total, s);
+  if (st != TM_OK) return st;
+  st = ensure_host(pool, tab_bytes + list_bytes);
+  if (st != TM_OK) return st;
+  char* base = static_cast<char*>(pool.dev);
+  Inst* host_tab = static_cast<Inst*>(pool.host);
+  int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host) + tab_bytes);
+  int32_t tile_base = 0, red_base = 0;
+  int ie = 0, ir = n_exact;
+  for (int32_t i = 0; i < count; ++i) {
+    const tm_plan_s* p = plans[i];
+    Inst& in = host_tab[i];
+    fill_inst(p, xs[i], &in);
+    place_workspace(p->core, base + ws_off[i], &in);
+    in.tile_base = tile_base;
+    in.red_base = red_base;
+    tile_base += p->core.ntiles;
+    red_base += p->core.nred;
+    in.out = dev_out ? out + i : reinterpret_cast<tm_result*>(base + off_res) + i;
+    if (p->core.mode == MODE_EXACT) host_list[ie++] = i; else host_list[ir++] = i;
+  }
+  TM_HIP(hipMemcpyAsync(base + off_tab, pool.host, tab_bytes + list_bytes, hipMemcpyHostToDevice, s));
+  TM_HIP(hipEventRecord(pool.staged, s));
+  pool.staged_pending = true;
+
+  InstTable tab{};
+  tab.table = reinterpret_cast<const Inst*>(base + off_tab);
+  tab.count = count;
+  const int32_t* dlist = reinterpret_cast<const int32_t*>(base + off_lists);
+  TM_HIP(timed_fold(tab, (int)tiles, fold_lds, s));
+  TM_HIP(launch_reduce(tab, (int)chunks, s));
+  TM_HIP(launch_finish(tab, dlist, n_exact, MODE_EXACT, lds_exact, s));
+  TM_HIP(launch_finish(tab, dlist + n_exact, n_real, MODE_REAL, lds_real, s));
+  if (!dev_out) {
+    TM_HIP(hipMemcpyAsync(out, base + off_res, sizeof(tm_result) * (size_t)count, hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+  }
+  return TM_OK;
+}
+
+tm_status tm_profile_enable(int on) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_prof_on = on != 0;
+  return TM_OK;
+}
+
+tm_status tm_profile_read(double* fold_ms_total, int64_t* fold_launches, int reset) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& pr : g_prof_live) {
+    TM_HIP(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    TM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    g_prof_ms += ms;
+    ++g_prof_n;
+    g_prof_free.push_back(pr.first);
+    g_prof_free.push_back(pr.second);
+  }
+  g_prof_live.clear();
+  if (fold_ms_total) *fold_ms_total = g_prof_ms;
+  if (fold_launches) *fold_launches = g_prof_n;
+  if (reset) { g_prof_ms = 0.0; g_prof_n = 0; }
+  return TM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+"""Python binding of the C ABI in include/tm.h (ctypes).
+
+Argument marshalling only: every step of the matcher runs in libtm.so's HIP
+kernels.  torch supplies device memory and the current HIP stream; it does no
+arithmetic here.  The library must be built (``python -m
+paper_1509_04863_amd.build``); without it every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtm.so")
+
+TM_OK, TM_ERR_INVALID, TM_ERR_NOMEM, TM_ERR_DEVICE, TM_ERR_UNSUPPORTED = range(5)
+TM_I8, TM_F32, TM_BF16, TM_F16 = range(4)
+TM_F_EXACT, TM_F_REAL = 0x1, 0x2
+TM_R_NOMATCH, TM_R_RESCORED, TM_R_NEAR_TIE, TM_R_EXACT = 0x1, 0x2, 0x4, 0x8
+
+EXPORTS = ["tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_info", "tm_match",
+           "tm_match_batch", "tm_match_intermediates", "tm_status_string", "tm_last_error",
+           "tm_version", "tm_profile_enable", "tm_profile_read"]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("m1", ctypes.c_int32),
+                ("m2", ctypes.c_int32), ("fold_mult", ctypes.c_int32), ("x_dtype", ctypes.c_int32),
+                ("t_dtype", ctypes.c_int32), ("fold_store", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("m1", ctypes.c_int32), ("m2", ctypes.c_int32), ("l1", ctypes.c_int32),
+                ("l2", ctypes.c_int32), ("fft_log2", ctypes.c_int32), ("exact", ctypes.c_int32),
+                ("dual", ctypes.c_int32), ("fft_in_lds", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64), ("x_bytes", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_int64), ("m1_tilde", ctypes.c_int32),
+                ("m2_tilde", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("peak1", ctypes.c_double),
+                ("peak2", ctypes.c_double), ("score", ctypes.c_double)]
+
+
+assert ctypes.sizeof(Result) == 48 and ctypes.sizeof(PlanDesc) == 40
+
+RESULT_DTYPE = np.dtype([("shift", "<i8"), ("m1_tilde", "<i4"), ("m2_tilde", "<i4"),
+                         ("n_candidates", "<i4"), ("flags", "<u4"), ("peak1", "<f8"),
+                         ("peak2", "<f8"), ("score", "<f8")])
+
+
+class TMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("tm status %d: %s" % (status, message))
+        self.status = status
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded libtm.so (raises if it was not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtm.so is not built; run `python -m paper_1509_04863_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+        L.tm_plan_params.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(PlanInfo)]
+        L.tm_plan_create.argtypes = [ctypes.POINTER(PlanDesc), vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.tm_plan_destroy.argtypes = [vp]
+        L.tm_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.tm_match.argtypes = [vp, vp, vp, vp]
+        L.tm_match_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp]
+        L.tm_match_intermediates.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        for fn in ("tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_info",
+                   "tm_match", "tm_match_batch", "tm_match_intermediates"):
+            getattr(L, fn).restype = ctypes.c_int
+        L.tm_status_string.argtypes = [ctypes.c_int]
+        L.tm_status_string.restype = ctypes.c_char_p
+        L.tm_last_error.argtypes = []
+        L.tm_last_error.restype = ctypes.c_char_p
+        L.tm_version.restype = ctypes.c_char_p
+        L.tm_profile_enable.argtypes = [ctypes.c_int]
+        L.tm_profile_enable.restype = ctypes.c_int
+        L.tm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int]
+        L.tm_profile_read.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int):
+    if status != TM_OK:
+        raise TMError(status, lib().tm_last_error().decode())
+
+
+# ------------------------------------------------------------------ dtypes
+
+_NP_TO_TM = {np.dtype(np.int8): TM_I8, np.dtype(np.float32): TM_F32, np.dtype(np.float16): TM_F16}
+
+
+def tm_dtype_of(arr) -> int:
+    """tm_dtype of a numpy array or torch tensor."""
+    try:
+        import torch
+        if isinstance(arr, torch.Tensor):
+            return {torch.int8: TM_I8, torch.float32: TM_F32, torch.bfloat16: TM_BF16,
+                    torch.float16: TM_F16}[arr.dtype]
+    except ImportError:
+        pass
+    return _NP_TO_TM[np.dtype(arr.dtype)]
+
+
+def _desc(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32, flags=0):
+    return PlanDesc(n=int(n), k=int(k), m1=int(m1), m2=int(m2), fold_mult=int(fold_mult),
+                    x_dtype=int(x_dtype), t_dtype=int(t_dtype), fold_store=int(fold_store),
+                    flags=int(flags))
+
+
+def _info_dict(info: PlanInfo) -> dict:
+    return {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+
+
+def plan_params(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32,
+                flags=0) -> dict:
+    """Host-only plan parameters (tm_plan_params)."""
+    info = PlanInfo()
+    _check(lib().tm_plan_params(ctypes.byref(_desc(n, k, m1, m2, fold_mult, x_dtype, t_dtype,
+                                                   fold_store, flags)), ctypes.byref(info)))
+    return _info_dict(info)
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+@dataclasses.dataclass
+class MatchResult:
+    shift: int
+    m1_tilde: int
+    m2_tilde: int
+    n_candidates: int
+    flags: int
+    peak1: float
+    peak2: float
+    score: float
+
+    @property
+    def nomatch(self) -> bool:
+        return bool(self.flags & TM_R_NOMATCH)
+
+    @property
+    def exact(self) -> bool:
+        return bool(self.flags & TM_R_EXACT)
+
+    @property
+    def near_tie(self) -> bool:
+        return bool(self.flags & TM_R_NEAR_TIE)
+
+
+def _row(r):
+    if isinstance(r, np.void):
+        return (int(r["shift"]), int(r["m1_tilde"]), int(r["m2_tilde"]), int(r["n_candidates"]),
+                int(r["flags"]), float(r["peak1"]), float(r["peak2"]), float(r["score"]))
+    return (int(r.shift), int(r.m1_tilde), int(r.m2_tilde), int(r.n_candidates), int(r.flags),
+            float(r.peak1), float(r.peak2), float(r.score))
+
+
+class Plan:
+    """A template with its device state (tm_plan)."""
+
+    def __init__(self, t, n: int, m1: int = 0, m2: int = 0, fold_mult: int = 1,
+                 x_dtype: Optional[int] = None, fold_store: int = TM_F32, flags: int = 0,
+                 stream=None):
+        if hasattr(t, "detach"):
+            import torch
+            tt = t.detach().cpu().contiguous()
+            t_host = tt.view(torch.int16).numpy() if tt.dtype == torch.bfloat16 else tt.numpy()
+        else:
+            t_host = np.ascontiguousarray(t)
+        t_dtype = tm_dtype_of(t)
+        if x_dtype is None:
+            x_dtype = t_dtype
+        self.desc = _desc(n, t_host.shape[0], m1, m2, fold_mult, x_dtype, t_dtype, fold_store, flags)
+        self._t_host = np.ascontiguousarray(t_host)
+        handle = ctypes.c_void_p()
+        _check(lib().tm_plan_create(ctypes.byref(self.desc), self._t_host.ctypes.data, 0,
+                                    _stream_handle(stream) if _torch_cuda() else None,
+                                    ctypes.byref(handle)))
+        self.handle = handle
+        info = PlanInfo()
+        _check(lib().tm_plan_get_info(self.handle, ctypes.byref(info)))
+        self.info = _info_dict(info)
+
+    @property
+    def n(self) -> int:
+        return int(self.desc.n)
+
+    @property
+    def k(self) -> int:
+        return int(self.desc.k)
+
+    @property
+    def m1(self) -> int:
+        return int(self.info["m1"])
+
+    @property
+    def m2(self) -> int:
+        return int(self.info["m2"])
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _check(lib().tm_plan_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _torch_cuda() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except ImportError:
+        return False
+
+
+def _check_signal(plan: Plan, x):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("x must be a CUDA (HIP) torch tensor")
+    if x.numel() != plan.n or not x.is_contiguous():
+        raise ValueError("x must be a contiguous tensor of N elements")
+    if tm_dtype_of(x) != plan.desc.x_dtype:
+        raise TypeError("x dtype does not match the plan")
+
+
+def match(plan: Plan, x, stream=None) -> MatchResult:
+    """One match with a host result (waits for the stream)."""
+    _check_signal(plan, x)
+    res = Result()
+    _check(lib().tm_match(plan.handle, x.data_ptr(), ctypes.addressof(res), _stream_handle(stream)))
+    return MatchResult(*_row(res))
+
+
+def match_into(plan: Plan, x, out, index: int = 0, stream=None):
+    """One match writing a device result: `out` is a CUDA uint8 tensor of
+    48*count bytes; nothing waits."""
+    _check_signal(plan, x)
+    _check(lib().tm_match(plan.handle, x.data_ptr(), out.data_ptr() + 48 * index,
+                          _stream_handle(stream)))
+
+
+def results_from_device(out) -> List[MatchResult]:
+    arr = out.cpu().numpy().view(RESULT_DTYPE)
+    return [MatchResult(*_row(r)) for r in arr]
+
+
+def match_batch(plans: Sequence[Plan], xs: Sequence, stream=None, out=None) -> Optional[List[MatchResult]]:
+    """tm_match_batch.  With out=None the results come back to the host;
+    with a CUDA uint8 tensor of 48*count bytes they stay on the device."""
+    count = len(plans)
+    if count != len(xs):
+        raise ValueError("plans and xs differ in length")
+    for p, x in zip(plans, xs):
+        _check_signal(p, x)
+    parr = (ctypes.c_void_p * count)(*[p.handle.value for p in plans])
+    xarr = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+    if out is not None:
+        _check(lib().tm_match_batch(count, parr, xarr, out.data_ptr(), _stream_handle(stream)))
+        return None
+    host = np.zeros(count, dtype=RESULT_DTYPE)
+    _check(lib().tm_match_batch(count, parr, xarr, host.ctypes.data, _stream_handle(stream)))
+    return [MatchResult(*_row(r)) for r in host]
+
+
+def match_intermediates(plan: Plan, x, stream=None):
+    """Match and return (result, y1, y2, r1, r2) with the intermediates as
+    numpy float64 arrays."""
+    import torch
+    _check_signal(plan, x)
+    m1, m2, k = plan.m1, plan.m2, plan.k
+    dev = x.device
+    y1 = torch.empty(m1 + k - 1, dtype=torch.float64, device=dev)
+    y2 = torch.empty(m2 + k - 1, dtype=torch.float64, device=dev)
+    r1 = torch.empty(m1, dtype=torch.float64, device=dev)
+    r2 = torch.empty(m2, dtype=torch.float64, device=dev)
+    res = Result()
+    _check(lib().tm_match_intermediates(plan.handle, x.data_ptr(), ctypes.addressof(res),
+                                        y1.data_ptr(), y2.data_ptr(), r1.data_ptr(),
+                                        r2.data_ptr(), _stream_handle(stream)))
+    return (MatchResult(*_row(res)), y1.cpu().numpy(), y2.cpu().numpy(), r1.cpu().numpy(),
+            r2.cpu().numpy())
+
+
+def profile_enable(on: bool = True):
+    """Record HIP events around every fold kernel launch (tm_profile_enable)."""
+    _check(lib().tm_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = False):
+    """(summed fold kernel milliseconds, fold launches) since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().tm_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value

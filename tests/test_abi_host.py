@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol that
+include/tm.h declares, and its host-only plan logic (tm_plan_params) follows
+the same reading of Algorithm 1 step 2 as the oracle.  No GPU is touched."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ftm as O
+from paper_1509_04863_amd import tm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = tm.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(tm.EXPORTS) <= set(names)
+
+
+def test_status_strings_and_version():
+    L = tm.lib()
+    assert L.tm_status_string(0) == b"ok"
+    assert L.tm_status_string(1) == b"invalid argument"
+    assert re.match(rb"^\d+\.\d+\.\d+$", L.tm_version())
+
+
+@pytest.mark.parametrize("n,k", [(65536, 1024), (1 << 22, 4096), (1 << 20, 512), (1 << 16, 4096),
+                                  (12345, 7), (1, 1), (100, 100), (1 << 24, 256), (99991, 300)])
+@pytest.mark.parametrize("c", [1, 2])
+def test_auto_moduli_follow_oracle_rule(n, k, c):
+    info = tm.plan_params(n, k, fold_mult=c)
+    m1, m2 = O.choose_moduli(n, k, c)
+    assert (info["m1"], info["m2"]) == (m1, m2)
+    assert info["l1"] == -(-n // m1) and info["l2"] == -(-n // m2)
+    P = 1 << info["fft_log2"]
+    assert P >= m2 + k - 1 and (P // 2 < m2 + k - 1 or P == 2)
+    assert info["dual"] == 1 and info["exact"] == 1
+
+
+def test_explicit_moduli_and_orientation():
+    info = tm.plan_params(1000, 10, 33, 32)           # swapped consecutive pair
+    assert (info["m1"], info["m2"], info["dual"]) == (33, 32, 1)
+    info = tm.plan_params(1000, 10, 31, 37)           # general co-prime pair
+    assert (info["m1"], info["m2"], info["dual"]) == (31, 37, 0)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=100, k=101),                      # K > N
+    dict(n=100, k=0),                        # K < 1
+    dict(n=100, k=10, m1=10, m2=12),         # gcd 2
+    dict(n=200, k=10, m1=10, m2=11),         # M1 M2 < N
+    dict(n=100, k=12, m1=10, m2=11),         # M < K
+    dict(n=100, k=10, m1=5, m2=0),           # only one explicit modulus
+    dict(n=100, k=10, fold_mult=3),
+    dict(n=100, k=10, x_dtype=7),
+    dict(n=100, k=10, fold_store=1 << 5),
+    dict(n=100, k=10, flags=0x100),
+    dict(n=100, k=10, flags=tm.TM_F_EXACT | tm.TM_F_REAL),
+])
+def test_invalid_plans_are_rejected(kw):
+    with pytest.raises(tm.TMError) as e:
+        tm.plan_params(**kw)
+    assert e.value.status == tm.TM_ERR_INVALID
+    assert tm.lib().tm_last_error()
+
+
+def test_modes():
+    assert tm.plan_params(1000, 10)["exact"] == 1
+    assert tm.plan_params(1000, 10, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32)["exact"] == 0
+    assert tm.plan_params(1000, 10, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32,
+                          flags=tm.TM_F_EXACT)["exact"] == 1
+    assert tm.plan_params(1000, 10, flags=tm.TM_F_REAL)["exact"] == 0
+    assert tm.plan_params(1000, 10, x_dtype=tm.TM_I8, t_dtype=tm.TM_F32)["exact"] == 0
+
+
+def test_fft_length_limits():
+    # exact path keeps P <= 2^13 in one workgroup's LDS, the real path P <= 2^14
+    assert tm.plan_params(1 << 22, 4096)["fft_in_lds"] == 1
+    assert tm.plan_params(1 << 24, 8192)["fft_in_lds"] == 0
+    assert tm.plan_params(1 << 24, 8192, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32)["fft_in_lds"] == 1
+
+
+def test_plan_create_without_device_fails_cleanly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    desc = tm._desc(1000, 10)
+    h = ctypes.c_void_p()
+    t = np.ones(10, dtype=np.int8)
+    st = tm.lib().tm_plan_create(ctypes.byref(desc), t.ctypes.data, 0, None, ctypes.byref(h))
+    assert st in (tm.TM_ERR_DEVICE, tm.TM_ERR_NOMEM)
+    assert not h.value

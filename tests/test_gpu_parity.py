@@ -1,0 +1,235 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer data: every intermediate (both folds, both correlations), both
+argmaxes, the candidate count, the shift, the peaks and the score must be
+bit-identical.  Real data: folds and correlations within a normwise relative
+1e-5 of the FP64 oracle, argmaxes equal unless either side reports a near tie.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ftm as O
+from paper_1509_04863_amd import datagen as G
+from paper_1509_04863_amd import tm
+
+from _util import assert_exact_parity, gpu_match, normwise, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _print_case(*a):
+    print("case:", *a, flush=True)
+
+
+# ---------------------------------------------------------------- configs
+
+@pytest.mark.parametrize("c", [1, 2])
+def test_config1_exact(c):
+    inst = G.config1(0, fold_mult=c)
+    _print_case("config1", c, inst.shift)
+    res, ref = assert_exact_parity(inst.x, inst.t, fold_mult=c)
+    assert res.peak1 >= 0
+
+
+def test_config2_exact_fp32_storage():
+    inst = G.config2(0)
+    _print_case("config2", inst.shift)
+    assert_exact_parity(inst.x, inst.t, flags=tm.TM_F_EXACT)
+
+
+# ---------------------------------------------------------------- edges
+
+EDGE = [
+    # (name, n, k, c, m1, m2, shift)
+    ("K=1", 1000, 1, 1, 0, 0, 17),
+    ("K=N", 777, 777, 1, 0, 0, 5),
+    ("L=1 (N<M)", 100, 80, 2, 0, 0, 99),
+    ("M|N", 4096 * 4, 4096, 1, 0, 0, 4096 * 4 - 1),
+    ("rho=1", 1024 * 9 + 1, 1024, 1, 0, 0, 0),
+    ("rho=M-1", 1024 * 9 + 1023, 1024, 1, 0, 0, 300),
+    ("prime N", 99991, 300, 1, 0, 0, 99991 - 150),
+    ("wrap template", 50000, 2000, 1, 0, 0, 50000 - 1000),
+    ("m < M - rho", 1024 * 9 + 100, 1024, 1, 0, 0, 3),
+    ("raised M (K(K+1)<=N)", 1 << 20, 300, 1, 0, 0, 123456),
+    ("non-consecutive", 5000, 20, 1, 61, 97, 4321),
+    ("non-consecutive wide", 200000, 300, 1, 509, 512, 77777),
+    ("swapped", 30000, 100, 1, 175, 174, 29999),
+    ("N=1", 1, 1, 1, 0, 0, 0),
+    ("N=2", 2, 1, 1, 0, 0, 1),
+    ("tiny", 7, 3, 1, 0, 0, 6),
+]
+
+
+@pytest.mark.parametrize("name,n,k,c,m1,m2,shift", EDGE, ids=[e[0] for e in EDGE])
+def test_edge_cases_exact(name, n, k, c, m1, m2, shift):
+    inst = G.planted_pm1(n, k, 7, n + k, flip_frac=0.05, shift=shift)
+    _print_case(name, n, k, c, m1, m2, shift)
+    assert_exact_parity(inst.x, inst.t, m1=m1, m2=m2, fold_mult=c)
+
+
+def test_constant_signal_ties():
+    n, k = 20000, 500
+    x = np.ones(n, dtype=np.int8)
+    t = np.ones(k, dtype=np.int8)
+    res, ref = assert_exact_parity(x, t)
+    assert res.m1_tilde == 0 and res.m2_tilde == 0
+
+
+def test_general_int8_values():
+    rng = np.random.default_rng(3)
+    x = rng.integers(-128, 128, 123457).astype(np.int8)
+    t = rng.integers(-128, 128, 611).astype(np.int8)
+    assert_exact_parity(x, t)
+
+
+def test_random_sweep_exact():
+    """Small random shapes: ragged tiles, wraps, empty and multiple intersections."""
+    rng = np.random.default_rng(11)
+    kinds = {0: 0, 1: 0, 2: 0, 3: 0}
+    for case in range(60):
+        n = int(rng.integers(1, 3000))
+        k = int(rng.integers(1, min(n, 200) + 1))
+        c = int(rng.integers(1, 3))
+        x = rng.integers(-3, 4, n).astype(np.int8)
+        t = rng.integers(-3, 4, k).astype(np.int8)
+        _print_case("sweep", case, n, k, c)
+        res, ref = assert_exact_parity(x, t, fold_mult=c)
+        kinds[ref.n_candidates] += 1
+    assert kinds[0] > 0 and kinds[1] > 0
+
+
+@pytest.mark.parametrize("tile_bytes,wbytes", [(1024, 16), (4096, 64), (65536, 2048), (16384, 100000)])
+def test_tile_shapes_do_not_change_exact_results(tile_bytes, wbytes, monkeypatch):
+    monkeypatch.setenv("TM_TILE_BYTES", str(tile_bytes))
+    monkeypatch.setenv("TM_TILE_WBYTES", str(wbytes))
+    for (n, k, shift) in [(65536, 1024, 4000), (70001, 333, 70000), (3000, 40, 2999)]:
+        inst = G.planted_pm1(n, k, 8, n, flip_frac=0.05, shift=shift)
+        _print_case("tiles", tile_bytes, wbytes, n, k)
+        assert_exact_parity(inst.x, inst.t)
+
+
+# ---------------------------------------------------------------- real path
+
+def _real_check(x, t, x_oracle=None, tol=1e-5, **kw):
+    res, y1, y2, r1, r2, plan = gpu_match(x, t, **kw)
+    xo = x.astype(np.float64) if x_oracle is None else x_oracle
+    ref = O.ftm(xo, t.astype(np.float64), plan.m1, plan.m2)
+    k = t.shape[0]
+    assert normwise(y1, ref.y1[:plan.m1 + k - 1]) <= tol
+    assert normwise(y2, ref.y2[:plan.m2 + k - 1]) <= tol
+    assert normwise(r1, ref.r1) <= tol
+    assert normwise(r2, ref.r2) <= tol
+    near = res.near_tie or O.top2_gap(ref.r1) <= 2 * tol * np.max(np.abs(ref.r1)) \
+        or O.top2_gap(ref.r2) <= 2 * tol * np.max(np.abs(ref.r2))
+    if not near:
+        assert (res.m1_tilde, res.m2_tilde) == (ref.m1_tilde, ref.m2_tilde)
+        assert res.shift == ref.shift and res.n_candidates == ref.n_candidates
+        if ref.shift != O.NOMATCH:
+            assert abs(res.score - float(ref.score)) <= 1e-9 * max(1.0, abs(float(ref.score)))
+    return res, ref, near
+
+
+@pytest.mark.parametrize("n,k,snr", [(65536, 512, None), (1 << 20, 4096, 0.0), (99991, 1000, -3.0),
+                                      (5000, 70, 3.0)])
+def test_real_fp32(n, k, snr):
+    inst = G.planted_gauss(n, k, snr, 60, n)
+    _print_case("real", n, k, snr)
+    res, ref, near = _real_check(inst.x, inst.t)
+    assert not res.exact
+
+
+def test_real_fp32_large_fft():
+    inst = G.planted_gauss(1 << 21, 8000, 0.0, 61, 0)       # P = 16384 in LDS
+    _print_case("real P=16384")
+    _real_check(inst.x, inst.t)
+
+
+def test_real_int8_signal_float_template():
+    inst = G.planted_pm1(200000, 700, 62, 0)
+    t = (inst.t.astype(np.float32) + 0.3 * np.random.default_rng(0).standard_normal(700)).astype(np.float32)
+    _print_case("i8 x, f32 t")
+    _real_check(inst.x, t)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_half_precision_inputs(dt):
+    inst = G.planted_gauss(300000, 900, 0.0, 63, 0)
+    xt = torch.from_numpy(inst.x).to(torch.bfloat16 if dt == "bf16" else torch.float16)
+    x_oracle = xt.float().numpy().astype(np.float64)
+    _print_case("half input", dt)
+    res, y1, y2, r1, r2, plan = gpu_match(inst.x, inst.t, x_dev=xt.cuda())
+    ref = O.ftm(x_oracle, inst.t.astype(np.float64), plan.m1, plan.m2)
+    assert normwise(r1, ref.r1) <= 1e-5 and normwise(r2, ref.r2) <= 1e-5
+
+
+@pytest.mark.parametrize("store,bound", [(tm.TM_BF16, 2.0 ** -8), (tm.TM_F16, 2.0 ** -11)])
+def test_fold_storage_precision(store, bound):
+    """BF16/FP16 storage of the fold: each stored y is the FP32 fold rounded
+    once, so |y - y64| <= 2^-8 |y64| (bf16) or 2^-11 |y64| (fp16) plus the FP32 sum error."""
+    inst = G.config5a(0, n=1 << 22, k=2048)
+    _print_case("fold store", store)
+    res, y1, y2, r1, r2, plan = gpu_match(inst.x, inst.t, fold_store=store)
+    ref = O.ftm(inst.x.astype(np.float64), inst.t.astype(np.float64), plan.m1, plan.m2)
+    k = inst.k
+    for y, yr in ((y1, ref.y1[:plan.m1 + k - 1]), (y2, ref.y2[:plan.m2 + k - 1])):
+        err = np.abs(y - yr)
+        assert np.all(err <= bound * np.abs(yr) + 1e-4 * np.max(np.abs(yr)))
+    e1, e2 = normwise(r1, ref.r1), normwise(r2, ref.r2)
+    print("fold store", store, "normwise r error", e1, e2)
+    assert e1 <= 8 * bound and e2 <= 8 * bound
+
+
+# ---------------------------------------------------------------- batches
+
+def test_batch_matches_single_and_oracle():
+    insts = []
+    rng = np.random.default_rng(5)
+    for i in range(24):
+        n = int(round(2 ** rng.uniform(12, 17)))
+        k = int(round(2 ** rng.uniform(5, 10)))
+        k = min(k, n)
+        insts.append(G.planted_pm1(n, k, 70, i, flip_frac=float(rng.uniform(0.05, 0.15))))
+    reals = [G.planted_gauss(int(round(2 ** rng.uniform(12, 16))), 64, 0.0, 71, i) for i in range(6)]
+    plans = [tm.Plan(s.t, n=s.n) for s in insts] + [tm.Plan(s.t, n=s.n) for s in reals]
+    xs = [to_device(s.x) for s in insts + reals]
+    batch = tm.match_batch(plans, xs)
+    single = [tm.match(p, x) for p, x in zip(plans, xs)]
+    for b, s in zip(batch, single):
+        assert b == s                      # bitwise: every field
+    for b, s, inst in zip(batch[:24], single[:24], insts):
+        ref = O.ftm(inst.x, inst.t, O.choose_moduli(inst.n, inst.k)[0],
+                    O.choose_moduli(inst.n, inst.k)[1])
+        assert (b.shift, b.m1_tilde, b.m2_tilde, b.n_candidates) == \
+            (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
+        assert b.score == float(ref.score if ref.score is not None else 0)
+
+
+def test_device_output_and_repeat_determinism():
+    inst = G.config1(3)
+    plan = tm.Plan(inst.t, n=inst.n)
+    x = to_device(inst.x)
+    out = torch.zeros(48 * 4, dtype=torch.uint8, device="cuda")
+    for i in range(4):
+        tm.match_into(plan, x, out, i)
+    rs = tm.results_from_device(out)
+    host = tm.match(plan, x)
+    assert all(r == host for r in rs)
+
+
+def test_invalid_calls_leave_no_side_effects():
+    inst = G.config1(0)
+    plan = tm.Plan(inst.t, n=inst.n)
+    with pytest.raises(TypeError):
+        tm.match(plan, to_device(inst.x.astype(np.float32)))
+    res = tm.Result()
+    st = tm.lib().tm_match(plan.handle, None, tm.ctypes.addressof(res), None)
+    assert st == tm.TM_ERR_INVALID
+    st = tm.lib().tm_match(None, None, tm.ctypes.addressof(res), None)
+    assert st == tm.TM_ERR_INVALID
