@@ -40,14 +40,18 @@ struct alignas(16) Inst {
   View vb;                // view with modulus mb (tiled only when !dual)
   int32_t tile_base;      // first fold tile of this instance in the launch
   int32_t ntiles;         // fold tiles of this instance
-  int32_t red_base;       // first reduce chunk of this instance in the launch
-  int32_t nred;           // reduce chunks of this instance
+  int32_t red_base;       // first reduce workgroup of this instance in the launch
+  int32_t nred;           // reduce workgroups of this instance (real-valued folds only)
+  int32_t red_tpe;        // reduce threads per fold entry (a power of two <= 256)
+  int32_t acc_int;        // 1: integer fold accumulated with atomics into `yp`
   int64_t inv_a_mod_b;    // ma^{-1} mod mb
   // workspace (device)
   void* col_a;            // [va.nrb][ma] column partials
   void* diag;             // [va.nrb][va.ncb][va.cols + va.rows - 1] diagonal partials (dual)
   void* col_b;            // [vb.nrb][mb] column partials (!dual)
-  void* y;                // literal folds: [ma + k - 1] then [mb + k - 1]
+  void* y;                // literal folds (float path): [ma + k - 1] then [mb + k - 1]
+  int* yp;                // partition folds (integer path): [ma] then [mb]; all zero
+                          // between launches (the finish kernel clears what it read)
   // plan (device)
   const void* t;          // template, t_dtype
   const void* spec;       // P complex values: conj(FFT_P(t)) / P at bit-reversed positions
@@ -70,9 +74,15 @@ struct InstTable {
 };
 
 constexpr int kFoldThreads = 256;
+constexpr int kFoldLoads = 16;          // 16-byte chunks each fold thread stages per tile
+constexpr int kFoldMaxCols = 512;       // tile columns W <= 512 (elements)
+constexpr int kFoldMaxRows = 256;       // tile rows R <= 256
+constexpr size_t kFoldLdsBudget = 60 * 1024;   // skewed tile bytes (two workgroups per CU)
 constexpr int kReduceThreads = 256;
-constexpr int kReduceChunk = 2048;      // fold entries one reduce workgroup produces
 constexpr int kFinishThreads = 512;
+
+// 16-byte chunks that cover one tile row of `cols` elements at any alignment
+inline __host__ __device__ int fold_chunks(int cols, int eb) { return (cols * eb + 15) / 16 + 1; }
 
 // Element sizes of tm_dtype values.
 inline int dtype_bytes(int dt) { return dt == TM_I8 ? 1 : (dt == TM_F32 ? 4 : 2); }

@@ -1,15 +1,19 @@
 // gfx950 kernels of the template matcher.
 //
-//   k_fold     Algorithm 1 step 3 (Eq. (2)): per-tile partial folds.  x is read
-//              as rows of M1 elements; a tile of R rows x W columns yields the
-//              column sums (fold M1) and, when M2 = M1 + 1, the diagonal sums
-//              (element (i, c) has index i*M1 + c = i*M2 + (c - i), so it falls
-//              in bucket (c - i) mod M2): both folds from one read of x.
-//   k_reduce   sums the partials of each bucket in a fixed order and applies the
-//              cyclic wrap of Algorithm 1's indices (Section 2: indices mod N),
-//              giving the literal folds y[0 .. M+K-1).
-//   k_finish   one workgroup per instance: packs y1 + i*y2, FFT, product with
-//              the plan's spectrum conj(FFT(t))/P, inverse FFT (steps 4-6 as a
+//   k_fold     Algorithm 1 step 3 (Eq. (2)).  x is read as rows of M1 elements;
+//              a tile of R rows x W columns is staged in LDS and yields the
+//              column sums (fold over M1) and, when M2 = M1 + 1, the diagonal
+//              sums (element (i, c) has index i*M1 + c = i*M2 + (c - i), so it
+//              belongs to bucket (c - i) mod M2): both folds from one read of x.
+//              Integer folds are added straight into the partition-fold buckets
+//              with int32 atomics (exact and order independent); real-valued
+//              folds are written as per-tile partials.
+//   k_reduce   real-valued folds only: sums each bucket's partials in a fixed
+//              order and applies the cyclic wrap of Algorithm 1's indices
+//              (indices mod N, Section 2), giving the literal folds y[0..M+K-1).
+//   k_finish   one workgroup per instance: literal folds (wrapping the integer
+//              buckets itself), z = y1 + i*y2, FFT, product with the plan's
+//              spectrum conj(FFT(t))/P, inverse FFT (steps 4-6 read as a
 //              cross-correlation), argmax over [0, M) (step 7), candidate
 //              intersection (steps 8-9, Theorem 4) and (Tx) scoring.
 //   k_twiddles FP64 twiddles exp(-2 pi i e / P) (stored FP64 or FP32).
@@ -35,16 +39,18 @@ __device__ __forceinline__ float to_float(f16_t v) { return __half2float(__ushor
 
 template <typename Acc> struct AccOf;
 template <> struct AccOf<int> {
+  static constexpr bool kInt = true;
   __device__ __forceinline__ static int from(int8_t v) { return (int)v; }
+  // integer-valued storage: truncation is exact (one instruction)
   template <typename Tin> __device__ __forceinline__ static int from(Tin v) {
-    return __float2int_rn(to_float(v));
+    return __float2int_rz(to_float(v));
   }
 };
 template <> struct AccOf<float> {
+  static constexpr bool kInt = false;
   template <typename Tin> __device__ __forceinline__ static float from(Tin v) { return to_float(v); }
 };
 
-// value of x[idx] as a double (for scores) for any storage type
 __device__ __forceinline__ double load_as_double(const void* p, int dt, int64_t idx) {
   switch (dt) {
     case TM_I8: return (double)((const int8_t*)p)[idx];
@@ -54,23 +60,88 @@ __device__ __forceinline__ double load_as_double(const void* p, int dt, int64_t 
   }
 }
 
+__device__ __forceinline__ int load_as_int(const void* p, int dt, int64_t idx) {
+  switch (dt) {
+    case TM_I8: return (int)((const int8_t*)p)[idx];
+    case TM_F32: return __float2int_rn(((const float*)p)[idx]);
+    case TM_BF16: return __float2int_rn(to_float(((const bf16_t*)p)[idx]));
+    default: return __float2int_rn(to_float(((const f16_t*)p)[idx]));
+  }
+}
+
+__device__ __forceinline__ float load_as_float(const void* p, int dt, int64_t idx) {
+  switch (dt) {
+    case TM_I8: return (float)((const int8_t*)p)[idx];
+    case TM_F32: return ((const float*)p)[idx];
+    case TM_BF16: return to_float(((const bf16_t*)p)[idx]);
+    default: return to_float(((const f16_t*)p)[idx]);
+  }
+}
+
+__device__ __forceinline__ bool acc_is_int(const Inst& d) { return d.acc_int != 0; }
+
+// v mod n for 0 <= v: a few subtractions cover the common v < 4n, a division the rest
+__device__ __forceinline__ int64_t mod_pos(int64_t v, int64_t n) {
+  if (v >= 4 * n) return v % n;
+  while (v >= n) v -= n;
+  return v;
+}
+
 // --------------------------------------------------------------------------
 // fold tiles
 // --------------------------------------------------------------------------
 
-__host__ __device__ __forceinline__ int fold_slot_bytes(int cols, int eb) {
-  return ((cols * eb + 15) & ~15) + 16;
+// global-memory (address space 1) views: plain loads, never FLAT
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gload16(uintptr_t a) {
+  const u32x4v v = *(__attribute__((address_space(1))) const u32x4v*)a;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ unsigned char gload8(uintptr_t a) {
+  return *(__attribute__((address_space(1))) const unsigned char*)a;
+}
+
+// Tile staging layout: row r of the tile sits in LDS shifted right by R-1-r
+// elements inside a zero-filled row of S = W + R - 1 elements.  Column j of the
+// tile is then the stride-(S-1) sequence starting at j + R - 1, and diagonal e
+// (elements (r, j) with j - r = e - (R - 1)) the stride-S sequence starting at e.
+__host__ __device__ __forceinline__ size_t fold_tile_bytes(int rows, int cols, int eb) {
+  return (((size_t)rows * (cols + rows - 1) * eb) + 15) & ~(size_t)15;
 }
 
 size_t fold_lds_bytes(const View& v, int x_dtype) {
-  const int eb = dtype_bytes(x_dtype);
-  return (size_t)v.rows * fold_slot_bytes(v.cols, eb) + (size_t)v.rows * sizeof(int2);
+  return fold_tile_bytes(v.rows, v.cols, dtype_bytes(x_dtype));
+}
+
+template <typename Acc, typename Tin>
+__device__ __forceinline__ Acc strided_sum(const Tin* p, int stride, int n) {
+  Acc acc = 0;
+  int r = 0;
+  for (; r + 8 <= n; r += 8) {
+    Tin v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = p[(r + i) * stride];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc += AccOf<Acc>::from(v[i]);
+  }
+  for (; r < n; ++r) acc += AccOf<Acc>::from(p[r * stride]);
+  return acc;
+}
+
+template <typename Tin>
+__device__ __forceinline__ Tin chunk_elem(const uint4& c, int e) {
+  const uint32_t w = e * (int)sizeof(Tin) / 4 == 0 ? c.x : e * (int)sizeof(Tin) / 4 == 1 ? c.y
+                   : e * (int)sizeof(Tin) / 4 == 2 ? c.z : c.w;
+  const int sh = (e * (int)sizeof(Tin)) % 4 * 8;
+  if constexpr (sizeof(Tin) == 4) { Tin v; __builtin_memcpy(&v, &w, 4); return v; }
+  else if constexpr (sizeof(Tin) == 2) { const uint16_t h = (uint16_t)(w >> sh); Tin v; __builtin_memcpy(&v, &h, 2); return v; }
+  else { const uint8_t b = (uint8_t)(w >> sh); Tin v; __builtin_memcpy(&v, &b, 1); return v; }
 }
 
 template <typename Tin, typename Acc>
-__device__ void fold_tile(const Inst& d, int lt, unsigned char* lds) {
+__device__ __forceinline__ void fold_tile(const Inst& d, int lt, unsigned char* lds) {
   const int tid = threadIdx.x;
-  const int NT = blockDim.x;
+  constexpr int NT = kFoldThreads;
   const int nta = d.va.nrb * d.va.ncb;
   const bool in_a = lt < nta;
   const View v = in_a ? d.va : d.vb;
@@ -82,71 +153,103 @@ __device__ void fold_tile(const Inst& d, int lt, unsigned char* lds) {
   const int64_t N = d.n;
   const int Reff = min(R, v.l - rb * R);
   const int c0 = cb * W;
+  const int S = W + R - 1;
   constexpr int EB = sizeof(Tin);
-  const int SLOT = fold_slot_bytes(W, EB);
-  const int CQ = SLOT >> 4;
-  int2* rowinfo = reinterpret_cast<int2*>(lds + (size_t)R * SLOT);
+  constexpr int EPC = 16 / EB;                        // elements per 16-byte chunk
+  const int CQ = fold_chunks(W, EB);
   const uintptr_t xa = reinterpret_cast<uintptr_t>(d.x);
   const uintptr_t xend = xa + (uintptr_t)N * EB;
+  Tin* t = reinterpret_cast<Tin*>(lds);
 
-  // per row: byte offset of column c0 inside its 16-byte envelope, valid columns
-  for (int r = tid; r < Reff; r += NT) {
-    const int64_t n0 = (int64_t)(rb * R + r) * M + c0;
-    int64_t nv = min((int64_t)min(M - c0, W), N - n0);
-    if (nv < 0) nv = 0;
-    const uintptr_t a0 = xa + (uintptr_t)n0 * EB;
-    rowinfo[r] = make_int2((int)(a0 & 15), (int)nv);
+  // valid columns: Wc in every row but the last row of x
+  const int Wc = min(M - c0, W);
+  const int64_t n_last = (int64_t)(rb * R + Reff - 1) * M + c0;
+  const int nv_last = (int)max((int64_t)0, min((int64_t)Wc, N - n_last));
+  const int Rfull = nv_last == Wc ? Reff : Reff - 1;
+
+  // 1) issue every 16-byte load of the tile (global address space, no branch
+  //    around the load: lanes without a chunk read a safe in-bounds chunk)
+  const unsigned total = (unsigned)(Reff * CQ);
+  const unsigned magic = 0xFFFFFFFFu / (unsigned)CQ + 1u;   // exact r = idx / CQ for idx < 2^16
+  const uintptr_t safeA = (xa + 15) & ~(uintptr_t)15;
+  const bool has_safe = safeA + 16 <= xend;
+  uint4 vb[kFoldLoads];
+  unsigned need = 0, slow = 0;
+#pragma unroll
+  for (int u = 0; u < kFoldLoads; ++u) {
+    const unsigned idx = tid + u * NT;
+    const unsigned r = __umulhi(idx, magic);
+    const unsigned q = idx - r * (unsigned)CQ;
+    const uintptr_t a0 = xa + (uintptr_t)(((int64_t)(rb * R + (int)r) * M + c0) * EB);
+    const int off = (int)(a0 & 15);
+    const int nv = (int)r < Rfull ? Wc : nv_last;
+    const uintptr_t A = (a0 & ~(uintptr_t)15) + (uintptr_t)q * 16;
+    const bool has = idx < total && (int)(q * 16) < off + nv * EB;
+    const bool fast = has && A >= xa && A + 16 <= xend;
+    if (has_safe) vb[u] = gload16(fast ? A : safeA);
+    need |= (unsigned)has << u;
+    slow |= (unsigned)(has && !fast) << u;
+  }
+
+  // 2) zero the skewed tile, then 3) scatter the valid elements into it
+  {
+    uint4* z = reinterpret_cast<uint4*>(lds);
+    const int nz = (int)(fold_tile_bytes(R, W, EB) >> 4);
+    for (int i = tid; i < nz; i += NT) z[i] = make_uint4(0, 0, 0, 0);
   }
   __syncthreads();
-
-  // stage the tile: aligned 16-byte loads, byte loads at the array's ends
-  for (int idx = tid; idx < Reff * CQ; idx += NT) {
-    const int r = idx / CQ;
-    const int q = idx - r * CQ;
-    const int2 ri = rowinfo[r];
-    if (q * 16 >= ri.x + ri.y * EB) continue;
-    const int64_t n0 = (int64_t)(rb * R + r) * M + c0;
-    const uintptr_t A = ((xa + (uintptr_t)n0 * EB) & ~(uintptr_t)15) + (uintptr_t)q * 16;
-    unsigned char* dst = lds + (size_t)r * SLOT + q * 16;
-    if (A >= xa && A + 16 <= xend) {
-      *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(A);
-    } else {
+#pragma unroll
+  for (int u = 0; u < kFoldLoads; ++u) {
+    if (!((need >> u) & 1)) continue;
+    const unsigned idx = tid + u * NT;
+    const int r = (int)__umulhi(idx, magic);
+    const int q = (int)(idx - (unsigned)r * (unsigned)CQ);
+    const uintptr_t a0 = xa + (uintptr_t)(((int64_t)(rb * R + r) * M + c0) * EB);
+    const int off = (int)(a0 & 15);
+    const int nv = r < Rfull ? Wc : nv_last;
+    uint4 c = vb[u];
+    if ((slow >> u) & 1) {
+      const uintptr_t A = (a0 & ~(uintptr_t)15) + (uintptr_t)q * 16;
+      unsigned char bytes[16];
       for (int b = 0; b < 16; ++b) {
         const uintptr_t ad = A + b;
-        dst[b] = (ad >= xa && ad < xend) ? *reinterpret_cast<const unsigned char*>(ad) : 0;
+        bytes[b] = (ad >= xa && ad < xend) ? gload8(ad) : 0;
       }
+      __builtin_memcpy(&c, bytes, 16);
+    }
+    const int j0 = (q * 16 - off) / EB;                // column of the chunk's first element
+    Tin* row = t + (size_t)r * S + (R - 1 - r);
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+      const int j = j0 + e;
+      if (j >= 0 && j < nv) row[j] = chunk_elem<Tin>(c, e);
     }
   }
   __syncthreads();
 
-  // column sums (fold over modulus M), rows in increasing order
-  Acc* colp = reinterpret_cast<Acc*>(in_a ? d.col_a : d.col_b);
-  for (int j = tid; j < W && c0 + j < M; j += NT) {
-    Acc acc = 0;
-    for (int r = 0; r < Reff; ++r) {
-      const int2 ri = rowinfo[r];
-      if (j < ri.y)
-        acc += AccOf<Acc>::from(*reinterpret_cast<const Tin*>(lds + (size_t)r * SLOT + ri.x + j * EB));
+  // 4) column sums (fold over M) and diagonal sums (fold over M + 1), rows in
+  //    increasing order, no bounds checks (invalid positions hold zeros)
+  for (int j = tid; j < Wc; j += NT) {
+    const Acc acc = strided_sum<Acc>(t + j + R - 1, S - 1, Reff);
+    if constexpr (AccOf<Acc>::kInt) {   // integer: exact, order-independent atomics
+      int* yp = d.yp + (in_a ? 0 : d.va.m);
+      if (acc) __hip_atomic_fetch_add(yp + c0 + j, (int)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      Acc* colp = reinterpret_cast<Acc*>(in_a ? d.col_a : d.col_b);
+      colp[(int64_t)rb * M + c0 + j] = acc;
     }
-    colp[(int64_t)rb * M + c0 + j] = acc;
   }
-
-  // diagonal sums (fold over M + 1): diagonal e holds elements (r, j) with
-  // j - r = e - (R - 1); rows in increasing order
   if (want_diag) {
-    const int E = W + R - 1;
-    Acc* dp = reinterpret_cast<Acc*>(d.diag) + (int64_t)(rb * v.ncb + cb) * E;
-    for (int e = tid; e < E; e += NT) {
-      Acc acc = 0;
-      const int rlo = max(0, R - 1 - e);
-      const int rhi = min(Reff, R - 1 - e + W);
-      for (int r = rlo; r < rhi; ++r) {
-        const int j = e - (R - 1) + r;
-        const int2 ri = rowinfo[r];
-        if (j < ri.y)
-          acc += AccOf<Acc>::from(*reinterpret_cast<const Tin*>(lds + (size_t)r * SLOT + ri.x + j * EB));
+    const int64_t mb = d.vb.m;
+    for (int e = tid; e < S; e += NT) {
+      const Acc acc = strided_sum<Acc>(t + e, S, Reff);
+      if constexpr (AccOf<Acc>::kInt) {
+        int64_t b = ((int64_t)c0 + e - (R - 1) - (int64_t)rb * R) % mb;
+        if (b < 0) b += mb;
+        if (acc) __hip_atomic_fetch_add(d.yp + d.va.m + b, (int)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        reinterpret_cast<Acc*>(d.diag)[(int64_t)(rb * v.ncb + cb) * S + e] = acc;
       }
-      dp[e] = acc;
     }
   }
 }
@@ -155,30 +258,21 @@ __device__ __forceinline__ int find_inst_by_tile(const InstTable& tab, int tile)
   int lo = 0, hi = tab.count - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (tab.get(mid).tile_base <= tile) lo = mid; else hi = mid - 1;
+    if (tab.table[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
-__device__ __forceinline__ int find_inst_by_chunk(const InstTable& tab, int chunk) {
+__device__ __forceinline__ int find_inst_by_red(const InstTable& tab, int wg) {
   int lo = 0, hi = tab.count - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (tab.get(mid).red_base <= chunk) lo = mid; else hi = mid - 1;
+    if (tab.table[mid].red_base <= wg) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
-__device__ __forceinline__ bool acc_is_int(const Inst& d) {
-  return d.x_dtype == TM_I8 || d.mode == MODE_EXACT;
-}
-
-__global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_tiles) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int tile = blockIdx.x;
-  if (tile >= total_tiles) return;
-  const Inst& d = tab.get(find_inst_by_tile(tab, tile));
-  const int lt = tile - d.tile_base;
+__device__ __forceinline__ void fold_dispatch(const Inst& d, int lt, unsigned char* lds) {
   if (acc_is_int(d)) {
     switch (d.x_dtype) {
       case TM_I8: fold_tile<int8_t, int>(d, lt, lds); break;
@@ -195,91 +289,89 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_
   }
 }
 
+// The table and the inline descriptor take separate paths so that each keeps
+// its own address space (no private copy of the kernel argument).
+__global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_tiles) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tile = blockIdx.x;
+  if (tile >= total_tiles) return;
+  if (tab.table) {
+    const Inst& d = tab.table[find_inst_by_tile(tab, tile)];
+    fold_dispatch(d, tile - d.tile_base, lds);
+  } else {
+    fold_dispatch(tab.one, tile, lds);
+  }
+}
+
 // --------------------------------------------------------------------------
-// reduce partials to the literal folds
+// real-valued folds: fixed-order reduction of the partials
 // --------------------------------------------------------------------------
 
-// partition sum of bucket s: sum of x[n] over n < N with n = s (mod M)
-template <typename Acc>
-__device__ Acc bucket_sum(const Inst& d, int fold, int s) {
-  Acc acc = 0;
-  if (fold == 0) {
-    const Acc* p = reinterpret_cast<const Acc*>(d.col_a);
-    for (int rb = 0; rb < d.va.nrb; ++rb) acc += p[(int64_t)rb * d.va.m + s];
-  } else if (!d.dual) {
-    const Acc* p = reinterpret_cast<const Acc*>(d.col_b);
-    for (int rb = 0; rb < d.vb.nrb; ++rb) acc += p[(int64_t)rb * d.vb.m + s];
-  } else {
-    // diagonal e of tile (rb, cb) covers bucket (e + cb*W - rb*R - (R-1)) mod mb
-    const Acc* p = reinterpret_cast<const Acc*>(d.diag);
-    const int R = d.va.rows, W = d.va.cols, E = W + R - 1, ncb = d.va.ncb;
-    const int64_t mb = d.vb.m;
-    const int64_t qmax = (int64_t)ncb * W + R - 1;
-    for (int rb = 0; rb < d.va.nrb; ++rb) {
-      const int64_t v0 = ((int64_t)s + (int64_t)rb * R + R - 1) % mb;
-      for (int64_t q = v0; q < qmax; q += mb) {
-        const int cb_hi = (int)min(q / W, (int64_t)ncb - 1);
-        const int64_t lo_num = q - (E - 1);
-        const int cb_lo = lo_num <= 0 ? 0 : (int)((lo_num + W - 1) / W);
-        for (int cb = cb_lo; cb <= cb_hi; ++cb)
-          acc += p[(int64_t)(rb * ncb + cb) * E + (q - (int64_t)cb * W)];
-      }
-    }
+// contribution of row block rb to bucket s of fold f (partition fold)
+__device__ __forceinline__ float bucket_part(const Inst& d, int f, int s, int rb) {
+  if (f == 0) return reinterpret_cast<const float*>(d.col_a)[(int64_t)rb * d.va.m + s];
+  if (!d.dual) return reinterpret_cast<const float*>(d.col_b)[(int64_t)rb * d.vb.m + s];
+  // diagonal e of tile (rb, cb) covers bucket (e + cb*W - rb*R - (R-1)) mod mb
+  const float* p = reinterpret_cast<const float*>(d.diag);
+  const int R = d.va.rows, W = d.va.cols, E = W + R - 1, ncb = d.va.ncb;
+  const int64_t mb = d.vb.m;
+  const int64_t qmax = (int64_t)ncb * W + R - 1;
+  float acc = 0.f;
+  const int64_t v0 = ((int64_t)s + (int64_t)rb * R + R - 1) % mb;
+  for (int64_t q = v0; q < qmax; q += mb) {
+    const int cb_hi = (int)min(q / W, (int64_t)ncb - 1);
+    const int64_t lo_num = q - (E - 1);
+    const int cb_lo = lo_num <= 0 ? 0 : (int)((lo_num + W - 1) / W);
+    for (int cb = cb_lo; cb <= cb_hi; ++cb) acc += p[(int64_t)(rb * ncb + cb) * E + (q - (int64_t)cb * W)];
   }
   return acc;
 }
 
-template <typename Tin, typename Acc>
-__device__ __forceinline__ Acc xval(const Inst& d, int64_t idx) {
-  return AccOf<Acc>::from(reinterpret_cast<const Tin*>(d.x)[idx]);
-}
-
-// literal fold entry u of fold f (Algorithm 1 step 3): y[u] for u < M + K - 1
-template <typename Tin, typename Acc>
-__device__ Acc literal_fold(const Inst& d, int f, int u) {
-  const int64_t M = f ? d.vb.m : d.va.m;
-  const int64_t L = f ? d.vb.l : d.va.l;
-  const int64_t N = d.n;
-  const int s = u < M ? u : (int)(u - M);
-  Acc acc = bucket_sum<Acc>(d, f, s);
-  // the last of the L terms wraps past N-1 (cyclic index of Section 2)
-  if ((int64_t)s + (L - 1) * M >= N) acc += xval<Tin, Acc>(d, ((int64_t)s + (L - 1) * M) % N);
-  // y[M + s] = y[s] - x[s] + x[(s + L M) mod N]
-  if (u >= M) acc += xval<Tin, Acc>(d, ((int64_t)s + L * M) % N) - xval<Tin, Acc>(d, s);
-  return acc;
-}
-
-template <typename Tin, typename Acc>
-__device__ void reduce_chunk(const Inst& d, int lc) {
+// Threads of a workgroup are split into groups of red_tpe lanes, one group per
+// fold entry; lane t sums row blocks t, t + tpe, ... and lane 0 adds the lanes
+// in order, then the cyclic wrap terms.
+__device__ __forceinline__ void reduce_wg(const Inst& d, int lc, float* part) {
+  const int tpe = d.red_tpe;
+  const int epw = kReduceThreads / tpe;
+  const int tid = threadIdx.x;
+  const int e = tid / tpe, t = tid - e * tpe;
   const int totA = d.va.m + d.k - 1;
   const int tot = totA + d.vb.m + d.k - 1;
-  const int u0 = lc * kReduceChunk;
-  const int u1 = min(u0 + kReduceChunk, tot);
-  Acc* y = reinterpret_cast<Acc*>(d.y);
-  for (int u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
-    const int f = u >= totA;
-    y[u] = literal_fold<Tin, Acc>(d, f, f ? u - totA : u);
+  const int u = lc * epw + e;
+  const int f = u >= totA;
+  const int uu = f ? u - totA : u;
+  const int64_t M = f ? d.vb.m : d.va.m;
+  const int s = uu < M ? uu : (int)(uu - M);
+  const int nrb = f ? (d.dual ? d.va.nrb : d.vb.nrb) : d.va.nrb;
+  float acc = 0.f;
+  if (u < tot)
+    for (int rb = t; rb < nrb; rb += tpe) acc += bucket_part(d, f, s, rb);
+  part[tid] = acc;
+  __syncthreads();
+  if (t == 0 && u < tot) {
+    float sum = 0.f;
+    for (int i = 0; i < tpe; ++i) sum += part[e * tpe + i];
+    const int64_t L = f ? d.vb.l : d.va.l;
+    const int64_t N = d.n;
+    if ((int64_t)s + (L - 1) * M >= N) sum += load_as_float(d.x, d.x_dtype, mod_pos((int64_t)s + (L - 1) * M, N));
+    if (uu >= M)
+      sum += load_as_float(d.x, d.x_dtype, mod_pos((int64_t)s + L * M, N)) - load_as_float(d.x, d.x_dtype, s);
+    reinterpret_cast<float*>(d.y)[u] = sum;
   }
 }
 
-__global__ void __launch_bounds__(kReduceThreads) k_reduce(InstTable tab, int total_chunks) {
-  const int chunk = blockIdx.x;
-  if (chunk >= total_chunks) return;
-  const Inst& d = tab.get(find_inst_by_chunk(tab, chunk));
-  const int lc = chunk - d.red_base;
-  if (acc_is_int(d)) {
-    switch (d.x_dtype) {
-      case TM_I8: reduce_chunk<int8_t, int>(d, lc); break;
-      case TM_F32: reduce_chunk<float, int>(d, lc); break;
-      case TM_BF16: reduce_chunk<bf16_t, int>(d, lc); break;
-      default: reduce_chunk<f16_t, int>(d, lc); break;
-    }
+// Threads of a workgroup are split into groups of red_tpe lanes, one group per
+// fold entry; lane t sums row blocks t, t + tpe, ... and lane 0 adds the lanes
+// in order, then the cyclic wrap terms.
+__global__ void __launch_bounds__(kReduceThreads) k_reduce(InstTable tab, int total_wgs) {
+  __shared__ float part[kReduceThreads];
+  const int wg = blockIdx.x;
+  if (wg >= total_wgs) return;
+  if (tab.table) {
+    const Inst& d = tab.table[find_inst_by_red(tab, wg)];
+    reduce_wg(d, wg - d.red_base, part);
   } else {
-    switch (d.x_dtype) {
-      case TM_F32: reduce_chunk<float, float>(d, lc); break;
-      case TM_BF16: reduce_chunk<bf16_t, float>(d, lc); break;
-      default: reduce_chunk<f16_t, float>(d, lc); break;
-    }
+    reduce_wg(tab.one, wg, part);
   }
 }
 
@@ -298,9 +390,89 @@ template <typename T> __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
+// cos(pi j / 16), j = 0..8
+__device__ __forceinline__ constexpr double cos_pi16(int j) {
+  return j == 0 ? 1.0
+       : j == 1 ? 0.98078528040323044913
+       : j == 2 ? 0.92387953251128675613
+       : j == 3 ? 0.83146961230254523708
+       : j == 4 ? 0.70710678118654752440
+       : j == 5 ? 0.55557023301960222474
+       : j == 6 ? 0.38268343236508977173
+       : j == 7 ? 0.19509032201612826785
+       : 0.0;
+}
+// omega_32^J = exp(-2 pi i J / 32) for J in [0, 16)
+__device__ __forceinline__ constexpr double root_re(int J) { return J <= 8 ? cos_pi16(J) : -cos_pi16(16 - J); }
+__device__ __forceinline__ constexpr double root_im(int J) { return -(J <= 8 ? cos_pi16(8 - J) : cos_pi16(J - 8)); }
+
+// x * omega_32^J (J fixed at compile time after unrolling)
+template <typename T>
+__device__ __forceinline__ cplx<T> mul_root(cplx<T> x, int J) {
+  const T c = (T)0.70710678118654752440;
+  if (J == 0) return x;
+  if (J == 8) return {x.y, -x.x};
+  if (J == 4) return {(x.x + x.y) * c, (x.y - x.x) * c};
+  if (J == 12) return {(x.y - x.x) * c, -(x.x + x.y) * c};
+  const T wr = (T)root_re(J), wi = (T)root_im(J);
+  return {x.x * wr - x.y * wi, x.x * wi + x.y * wr};
+}
+// x * conj(omega_32^J)
+template <typename T>
+__device__ __forceinline__ cplx<T> mul_root_conj(cplx<T> x, int J) {
+  const T c = (T)0.70710678118654752440;
+  if (J == 0) return x;
+  if (J == 8) return {-x.y, x.x};
+  if (J == 4) return {(x.x - x.y) * c, (x.x + x.y) * c};
+  if (J == 12) return {-(x.x + x.y) * c, (x.x - x.y) * c};
+  const T wr = (T)root_re(J), wi = (T)root_im(J);
+  return {x.x * wr + x.y * wi, x.y * wr - x.x * wi};
+}
+
+// Radix-2 decimation-in-frequency stages over 2^KB points with constant
+// twiddles: natural order in, DFT at bit-reversed positions out.
+template <int KB, typename T>
+__device__ __forceinline__ void dft_dif(cplx<T>* v) {
+  constexpr int RR = 1 << KB;
+#pragma unroll
+  for (int st = 0; st < KB; ++st) {
+    const int hm = RR >> (st + 1);
+#pragma unroll
+    for (int m = 0; m < RR; ++m) {
+      if (m & hm) continue;
+      const cplx<T> a = v[m], b = v[m + hm];
+      v[m] = a + b;
+      v[m + hm] = mul_root(a - b, (m & (hm - 1)) * (16 / hm));
+    }
+  }
+}
+
+// Exact inverse of dft_dif up to the factor 2^KB.
+template <int KB, typename T>
+__device__ __forceinline__ void dft_dit(cplx<T>* v) {
+  constexpr int RR = 1 << KB;
+#pragma unroll
+  for (int st = KB - 1; st >= 0; --st) {
+    const int hm = RR >> (st + 1);
+#pragma unroll
+    for (int m = 0; m < RR; ++m) {
+      if (m & hm) continue;
+      const cplx<T> a = v[m];
+      const cplx<T> b = mul_root_conj(v[m + hm], (m & (hm - 1)) * (16 / hm));
+      v[m] = a + b;
+      v[m + hm] = a - b;
+    }
+  }
+}
+
+__device__ __forceinline__ constexpr int bitrev(int m, int kb) {
+  int r = 0;
+  for (int i = 0; i < kb; ++i) r |= ((m >> i) & 1) << (kb - 1 - i);
+  return r;
+}
+
 // one pad element per 16 keeps strided butterfly accesses off a single bank
 __device__ __forceinline__ int padi(int j) { return j + (j >> 4); }
-
 __host__ __device__ __forceinline__ int padded_len(int P) { return P + (P >> 4) + 1; }
 
 int fft_lds_max_log2(int mode) { return mode == MODE_EXACT ? 13 : 14; }
@@ -310,12 +482,38 @@ size_t finish_lds_bytes(int p_log2, int mode) {
   return (size_t)padded_len(1 << p_log2) * el + (size_t)kFinishThreads * 16;
 }
 
-// A pass applies radix-2 stages s0 .. s0+KB-1 to groups of 2^KB elements
-// spaced 2^(p - s0 - KB) apart.  DIR 0: forward decimation-in-frequency
-// stages (natural order in, bit-reversed out).  DIR 1: inverse
-// decimation-in-time stages in descending order (each undoes the forward
-// stage up to a factor 2).  DIR 2: forward stages, product with the spectrum
-// (stored at the bit-reversed positions), inverse stages.
+// Output twiddles of a pass: w = W^(off 2^s0); position m gets w^br(m).  The
+// pass loads w^(2^j) from the table and forms w^q = w^(q & 3) * (w^4)^(q >> 2).
+template <int KB, typename T>
+struct PassTwiddles {
+  cplx<T> lo[4];     // w^0 .. w^3
+  cplx<T> hi[8];     // (w^4)^0 .. (w^4)^7
+  __device__ __forceinline__ void init(const cplx<T>* __restrict__ tw, int off, int s0) {
+    lo[0] = {(T)1, (T)0};
+    hi[0] = {(T)1, (T)0};
+    if (KB >= 1) lo[1] = tw[off << s0];
+    if (KB >= 2) { lo[2] = tw[(off << 1) << s0]; lo[3] = cmul(lo[2], lo[1]); }
+    if (KB >= 3) hi[1] = tw[(off << 2) << s0];
+    if (KB >= 4) { hi[2] = tw[(off << 3) << s0]; hi[3] = cmul(hi[2], hi[1]); }
+    if (KB >= 5) {
+      hi[4] = tw[(off << 4) << s0];
+      hi[5] = cmul(hi[4], hi[1]);
+      hi[6] = cmul(hi[4], hi[2]);
+      hi[7] = cmul(hi[6], hi[1]);
+    }
+  }
+  __device__ __forceinline__ cplx<T> pow(int q) const {
+    const int a = q & 3, b = q >> 2;
+    if (b == 0) return lo[a];
+    if (a == 0) return hi[b];
+    return cmul(lo[a], hi[b]);
+  }
+};
+
+// DIR 0: forward pass (constant DFT, then output twiddles).  DIR 1: inverse
+// pass (conjugate twiddles, then the inverse constant DFT).  DIR 2: the last
+// forward pass, the product with the spectrum and the first inverse pass; its
+// groups are contiguous (offset 0), so it has no output twiddles.
 template <int KB, int DIR, typename T>
 __device__ void fft_pass(cplx<T>* buf, int p, int s0, const cplx<T>* __restrict__ tw,
                          const cplx<T>* __restrict__ spec) {
@@ -331,42 +529,27 @@ __device__ void fft_pass(cplx<T>* buf, int p, int s0, const cplx<T>* __restrict_
     cplx<T> v[RR];
 #pragma unroll
     for (int m = 0; m < RR; ++m) v[m] = buf[padi(base + (m << lh))];
-    if (DIR != 1) {
+    if (DIR == 0) {
+      dft_dif<KB>(v);
+      if (off) {
+        PassTwiddles<KB, T> w;
+        w.init(tw, off, s0);
 #pragma unroll
-      for (int st = 0; st < KB; ++st) {
-        const int s = s0 + st;
-        const int hm = RR >> (st + 1);
-        const int hmask = (P >> (s + 1)) - 1;
-#pragma unroll
-        for (int m = 0; m < RR; ++m) {
-          if (m & hm) continue;
-          const int e = ((off + (m << lh)) & hmask) << s;
-          const cplx<T> a = v[m], b = v[m + hm];
-          v[m] = a + b;
-          v[m + hm] = cmul(a - b, tw[e]);
-        }
+        for (int m = 1; m < RR; ++m) v[m] = cmul(v[m], w.pow(bitrev(m, KB)));
       }
-    }
-    if (DIR == 2) {
+    } else if (DIR == 1) {
+      if (off) {
+        PassTwiddles<KB, T> w;
+        w.init(tw, off, s0);
+#pragma unroll
+        for (int m = 1; m < RR; ++m) v[m] = cmulc(v[m], w.pow(bitrev(m, KB)));
+      }
+      dft_dit<KB>(v);
+    } else {
+      dft_dif<KB>(v);
 #pragma unroll
       for (int m = 0; m < RR; ++m) v[m] = cmul(v[m], spec[base + (m << lh)]);
-    }
-    if (DIR != 0) {
-#pragma unroll
-      for (int st = KB - 1; st >= 0; --st) {
-        const int s = s0 + st;
-        const int hm = RR >> (st + 1);
-        const int hmask = (P >> (s + 1)) - 1;
-#pragma unroll
-        for (int m = 0; m < RR; ++m) {
-          if (m & hm) continue;
-          const int e = ((off + (m << lh)) & hmask) << s;
-          const cplx<T> a = v[m];
-          const cplx<T> b = cmulc(v[m + hm], tw[e]);
-          v[m] = a + b;
-          v[m + hm] = a - b;
-        }
-      }
+      dft_dit<KB>(v);
     }
 #pragma unroll
     for (int m = 0; m < RR; ++m) buf[padi(base + (m << lh))] = v[m];
@@ -380,22 +563,20 @@ __device__ __forceinline__ void fft_pass_kb(int kb, cplx<T>* buf, int p, int s0,
     case 1: fft_pass<1, DIR>(buf, p, s0, tw, spec); break;
     case 2: fft_pass<2, DIR>(buf, p, s0, tw, spec); break;
     case 3: fft_pass<3, DIR>(buf, p, s0, tw, spec); break;
-    default: fft_pass<4, DIR>(buf, p, s0, tw, spec); break;
+    case 4: fft_pass<4, DIR>(buf, p, s0, tw, spec); break;
+    default: fft_pass<5, DIR>(buf, p, s0, tw, spec); break;
   }
 }
 
-// c[n] = sum_j t_j z[(n + j) mod P]: forward transform, product with the
-// spectrum, inverse transform, all in LDS.
-// Pass i of the plan for length 2^p: radix-2^kb stages starting at s0.
-// p <= 4: one pass; otherwise an optional p mod 4 pass first, then radix 16.
-__device__ __forceinline__ int fft_npasses(int p) { return p <= 4 ? 1 : ((p & 3) ? 1 : 0) + (p >> 2); }
+// Pass i of the plan for length 2^p: at most 5 stages per pass, as few passes
+// as possible, sizes balanced and the larger ones last (the fused middle pass).
+__device__ __forceinline__ int fft_npasses(int p) { return (p + 4) / 5; }
 __device__ __forceinline__ void fft_pass_of(int i, int p, int& s0, int& kb) {
-  if (p <= 4) { s0 = 0; kb = p; return; }
-  const int rem = p & 3;
-  if (rem == 0) { s0 = 4 * i; kb = 4; return; }
-  if (i == 0) { s0 = 0; kb = rem; return; }
-  s0 = rem + 4 * (i - 1);
-  kb = 4;
+  const int np = fft_npasses(p);
+  const int small = p / np, nbig = p - small * np;   // the last nbig passes get small + 1
+  const int nsmall = np - nbig;
+  if (i < nsmall) { s0 = i * small; kb = small; }
+  else { s0 = nsmall * small + (i - nsmall) * (small + 1); kb = small + 1; }
 }
 
 // c[n] = sum_j t_j z[(n + j) mod P]: forward transform, product with the
@@ -457,7 +638,7 @@ __device__ S block_sum(S mine, S* scratch) {
 }
 
 // --------------------------------------------------------------------------
-// finish: FFT correlation, argmax, candidate intersection, scoring
+// finish: literal folds, FFT correlation, argmax, intersection, scoring
 // --------------------------------------------------------------------------
 
 template <typename T>
@@ -472,12 +653,12 @@ __device__ __forceinline__ T store_round(float v, int fold_store) {
 }
 
 // Score (Tx)_c = sum_j t_j x[(c + j) mod N]: int64 on the exact path, FP64 otherwise.
-__device__ double score_at(const Inst& d, int64_t c, void* scratch) {
+__device__ __forceinline__ double score_at(const Inst& d, int64_t c, void* scratch) {
   const int64_t N = d.n;
   if (d.mode == MODE_EXACT) {
     long long acc = 0;
     for (int j = threadIdx.x; j < d.k; j += blockDim.x) {
-      const int64_t xi = (c + j) % N;
+      const int64_t xi = c + j < N ? c + j : c + j - N;   // c < N, j < K <= N
       acc += (long long)llrint(load_as_double(d.t, d.t_dtype, j)) *
              (long long)llrint(load_as_double(d.x, d.x_dtype, xi));
     }
@@ -485,14 +666,14 @@ __device__ double score_at(const Inst& d, int64_t c, void* scratch) {
   }
   double acc = 0.0;
   for (int j = threadIdx.x; j < d.k; j += blockDim.x) {
-    const int64_t xi = (c + j) % N;
+    const int64_t xi = c + j < N ? c + j : c + j - N;
     acc += load_as_double(d.t, d.t_dtype, j) * load_as_double(d.x, d.x_dtype, xi);
   }
   return block_sum<double>(acc, (double*)scratch);
 }
 
-template <typename T, typename Acc>
-__device__ void finish_instance(const Inst& d, unsigned char* lds) {
+template <typename T>
+__device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* lds) {
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
   const int p = d.p_log2;
@@ -501,29 +682,70 @@ __device__ void finish_instance(const Inst& d, unsigned char* lds) {
   void* scratch = lds + (size_t)padded_len(P) * sizeof(cplx<T>);
   const int ma = d.va.m, mb = d.vb.m, K = d.k;
   const int na = ma + K - 1, nb = mb + K - 1;
-  const Acc* y = reinterpret_cast<const Acc*>(d.y);
   const bool exact = d.mode == MODE_EXACT;
+  const bool ints = acc_is_int(d);
   double* dya = d.swapped ? d.dbg_y2 : d.dbg_y1;
   double* dyb = d.swapped ? d.dbg_y1 : d.dbg_y2;
   double* dra = d.swapped ? d.dbg_r2 : d.dbg_r1;
   double* drb = d.swapped ? d.dbg_r1 : d.dbg_r2;
+  double znorm2 = 0.0;
 
-  // pack z = yA + i yB, zero padded to P
-  double ss = 0.0;
-  for (int n = tid; n < P; n += NT) {
-    T re = 0, im = 0;
-    if (n < na) {
-      re = exact ? (T)y[n] : store_round<T>((float)y[n], d.fold_store);
-      if (dya) dya[n] = (double)re;
+  // literal folds (Algorithm 1 step 3) packed as z = yA + i yB, zero padded to P
+  if (ints) {
+    // 1) partition buckets, 2) wrapped last terms, 3) the K-1 entries past M:
+    //    y[M + s] = y[s] - x[s] + x[(s + L M) mod N].  Integer values, exact in
+    //    T (FP64; FP32 below 2^24 in magnitude).
+    const int64_t N = d.n;
+    for (int n = tid; n < P; n += NT)
+      buf[padi(n)] = cplx<T>{n < ma ? (T)d.yp[n] : (T)0, n < mb ? (T)d.yp[ma + n] : (T)0};
+    __syncthreads();
+    for (int f = 0; f < 2; ++f) {
+      const int64_t M = f ? mb : ma, L = f ? d.vb.l : d.va.l;
+      const int64_t s0 = max((int64_t)0, N - (L - 1) * M);   // first bucket whose last term wraps
+      for (int64_t s = s0 + tid; s < M; s += NT) {
+        T* e = f ? &buf[padi((int)s)].y : &buf[padi((int)s)].x;
+        *e += (T)load_as_int(d.x, d.x_dtype, mod_pos(s + (L - 1) * M, N));
+      }
     }
-    if (n < nb) {
-      im = exact ? (T)y[na + n] : store_round<T>((float)y[na + n], d.fold_store);
-      if (dyb) dyb[n] = (double)im;
+    __syncthreads();
+    for (int f = 0; f < 2; ++f) {
+      const int64_t M = f ? mb : ma, L = f ? d.vb.l : d.va.l;
+      for (int s = tid; s < K - 1; s += NT) {
+        const T lo = f ? buf[padi(s)].y : buf[padi(s)].x;
+        const T v = lo - (T)load_as_int(d.x, d.x_dtype, s) +
+                    (T)load_as_int(d.x, d.x_dtype, mod_pos((int64_t)s + L * M, N));
+        if (f) buf[padi((int)M + s)].y = v; else buf[padi((int)M + s)].x = v;
+      }
     }
-    ss += (double)re * (double)re + (double)im * (double)im;
-    buf[padi(n)] = cplx<T>{re, im};
+    __syncthreads();
+    double ss = 0.0;
+    for (int n = tid; n < P; n += NT) {
+      cplx<T> v = buf[padi(n)];
+      if (!exact) {
+        v.x = store_round<T>((float)v.x, d.fold_store);
+        v.y = store_round<T>((float)v.y, d.fold_store);
+        buf[padi(n)] = v;
+      }
+      if (dya && n < na) dya[n] = (double)v.x;
+      if (dyb && n < nb) dyb[n] = (double)v.y;
+      ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+    znorm2 = block_sum<double>(ss, (double*)scratch);   // includes barriers
+    for (int s = tid; s < ma + mb; s += NT) d.yp[s] = 0;   // buckets back to zero
+  } else {
+    const float* yf = reinterpret_cast<const float*>(d.y);
+    double ss = 0.0;
+#pragma unroll 4
+    for (int n = tid; n < P; n += NT) {
+      const T re = n < na ? store_round<T>(yf[n], d.fold_store) : (T)0;
+      const T im = n < nb ? store_round<T>(yf[na + n], d.fold_store) : (T)0;
+      if (dya && n < na) dya[n] = (double)re;
+      if (dyb && n < nb) dyb[n] = (double)im;
+      ss += (double)re * (double)re + (double)im * (double)im;
+      buf[padi(n)] = cplx<T>{re, im};
+    }
+    znorm2 = block_sum<double>(ss, (double*)scratch);
   }
-  const double znorm2 = block_sum<double>(ss, (double*)scratch);   // includes a barrier
 
   fft_correlate<T>(buf, p, reinterpret_cast<const cplx<T>*>(d.tw), reinterpret_cast<const cplx<T>*>(d.spec));
 
@@ -578,7 +800,7 @@ __device__ void finish_instance(const Inst& d, unsigned char* lds) {
     const int64_t N = d.n;
     const int64_t A = ma, B = mb, La = d.va.l, Lb = d.vb.l;
     const int64_t a = amax.i, b = bmax.i;
-    long long c0 = -1, c1 = -1, c2 = -1;   // ascending after insertion, -1 = unused
+    long long c0 = -1, c1 = -1, c2 = -1;   // ascending, -1 = unused
     auto insert = [&](long long v) {
       if (v == c0 || v == c1 || v == c2) return;
       if (c0 < 0 || v < c0) { c2 = c1; c1 = c0; c0 = v; }
@@ -633,9 +855,8 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish(InstTable tab, const 
   extern __shared__ __align__(16) unsigned char lds[];
   const int b = blockIdx.x;
   if (b >= count) return;
-  const Inst& d = tab.get(list ? list[b] : b);
-  if (acc_is_int(d)) finish_instance<T, int>(d, lds);
-  else finish_instance<T, float>(d, lds);
+  if (tab.table) finish_instance<T>(tab.table[list ? list[b] : b], lds);
+  else finish_instance<T>(tab.one, lds);
 }
 
 // --------------------------------------------------------------------------
@@ -709,9 +930,9 @@ hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const InstTable& tab, int total_chunks, hipStream_t s) {
-  if (total_chunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(total_chunks), dim3(kReduceThreads), 0, s, tab, total_chunks);
+hipError_t launch_reduce(const InstTable& tab, int total_wgs, hipStream_t s) {
+  if (total_wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(total_wgs), dim3(kReduceThreads), 0, s, tab, total_wgs);
   return hipGetLastError();
 }
 

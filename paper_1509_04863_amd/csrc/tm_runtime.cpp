@@ -70,16 +70,21 @@ int64_t least_m0(int64_t n) {
 
 bool valid_dtype(int32_t dt) { return dt >= TM_I8 && dt <= TM_F16; }
 
-// Tile shape of one row view: rows of m elements, tiles of about
-// TM_TILE_BYTES bytes that are TM_TILE_WBYTES bytes wide.
+// Tile shape of one row view: TM_TILE_WBYTES-wide rows (1 KiB for 4-byte
+// elements, 512 elements otherwise), as many rows as the skewed LDS tile
+// budget, the staging loads and TM_TILE_BYTES allow.
 View make_view(int64_t n, int64_t m, int eb) {
   View v{};
   v.m = (int32_t)m;
   v.l = (int32_t)ceil_div(n, m);
-  const int64_t tile_bytes = std::max<int64_t>(1024, env_int("TM_TILE_BYTES", 32768));
-  const int64_t wbytes = std::max<int64_t>(16, env_int("TM_TILE_WBYTES", 512));
-  const int64_t w = std::min<int64_t>(m, std::max<int64_t>(1, wbytes / eb));
-  const int64_t r = std::max<int64_t>(1, std::min<int64_t>(v.l, tile_bytes / (w * eb)));
+  const int64_t wdef = eb == 4 ? 256 : 512;
+  const int64_t tile_bytes = std::max<int64_t>(256, env_int("TM_TILE_BYTES", 1 << 20));
+  const int64_t wbytes = std::max<int64_t>(eb, env_int("TM_TILE_WBYTES", wdef * eb));
+  const int64_t w = std::min<int64_t>({m, std::max<int64_t>(1, wbytes / eb), (int64_t)kFoldMaxCols});
+  const int64_t rmax_stage = (int64_t)kFoldThreads * kFoldLoads / fold_chunks((int)w, eb);
+  int64_t r = std::max<int64_t>(1, std::min<int64_t>({(int64_t)v.l, tile_bytes / (w * eb), rmax_stage,
+                                                       (int64_t)kFoldMaxRows}));
+  while (r > 1 && (size_t)r * (w + r - 1) * eb > kFoldLdsBudget) --r;
   v.cols = (int32_t)w;
   v.rows = (int32_t)r;
   v.nrb = (int32_t)ceil_div(v.l, r);
@@ -97,7 +102,8 @@ struct Core {
   View va{}, vb{};
   // workspace offsets (bytes) of one instance
   size_t off_col_a = 0, off_diag = 0, off_col_b = 0, off_y = 0, off_res = 0, ws_bytes = 0;
-  int32_t ntiles = 0, nred = 0;
+  int32_t ntiles = 0, nred = 0, red_tpe = 1, acc_int = 0;
+  size_t acc_bytes = 0;     // integer bucket zone (int32 [ma + mb]); lives in the zeroed pool
   size_t fold_lds = 0, finish_lds = 0;
   int fft_in_lds = 1;
 };
@@ -162,16 +168,26 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
     c->vb = make_view(d->n, c->mb, eb);
   }
   c->ntiles = c->va.nrb * c->va.ncb + (c->dual ? 0 : c->vb.nrb * c->vb.ncb);
+  c->acc_int = d->x_dtype == TM_I8 || c->mode == MODE_EXACT;
   const int64_t ytot = (int64_t)c->ma + c->k - 1 + c->mb + c->k - 1;
-  c->nred = (int32_t)ceil_div(ytot, kReduceChunk);
-
   size_t off = 0;
-  c->off_col_a = off; off = align256(off + (size_t)c->va.nrb * c->ma * 4);
-  c->off_diag = off;
-  if (c->dual) off = align256(off + (size_t)c->va.nrb * c->va.ncb * (c->va.cols + c->va.rows - 1) * 4);
-  c->off_col_b = off;
-  if (!c->dual) off = align256(off + (size_t)c->vb.nrb * c->mb * 4);
-  c->off_y = off; off = align256(off + (size_t)ytot * 4);
+  if (c->acc_int) {
+    // integer folds go straight to the bucket zone: no partials, no reduce
+    c->acc_bytes = align256((size_t)(c->ma + c->mb) * 4);
+    c->nred = 0;
+  } else {
+    const int nrb = std::max(c->va.nrb, c->dual ? 0 : c->vb.nrb);
+    int tpe = 1;
+    while (tpe < nrb && tpe < kReduceThreads) tpe *= 2;
+    c->red_tpe = tpe;
+    c->nred = (int32_t)ceil_div(ytot, kReduceThreads / tpe);
+    c->off_col_a = off; off = align256(off + (size_t)c->va.nrb * c->ma * 4);
+    c->off_diag = off;
+    if (c->dual) off = align256(off + (size_t)c->va.nrb * c->va.ncb * (c->va.cols + c->va.rows - 1) * 4);
+    c->off_col_b = off;
+    if (!c->dual) off = align256(off + (size_t)c->vb.nrb * c->mb * 4);
+    c->off_y = off; off = align256(off + (size_t)ytot * 4);
+  }
   c->off_res = off; off = align256(off + sizeof(tm_result));
   c->ws_bytes = off;
   c->fold_lds = std::max(fold_lds_bytes(c->va, d->x_dtype), c->dual ? 0 : fold_lds_bytes(c->vb, d->x_dtype));
@@ -188,7 +204,7 @@ void fill_info(const Core& c, tm_plan_info* info) {
   info->exact = c.mode == MODE_EXACT;
   info->dual = c.dual;
   info->fft_in_lds = c.fft_in_lds;
-  info->workspace_bytes = (int64_t)c.ws_bytes;
+  info->workspace_bytes = (int64_t)(c.ws_bytes + c.acc_bytes);
   info->x_bytes = c.n * dtype_bytes(c.x_dtype);
 }
 
@@ -197,6 +213,9 @@ void fill_info(const Core& c, tm_plan_info* info) {
 struct StreamPool {
   void* dev = nullptr;
   size_t cap = 0;
+  void* acc = nullptr;           // integer bucket zone: all zero between launches
+  size_t acc_cap = 0;
+  bool acc_dirty = false;        // a launch sequence broke off after its fold
   void* host = nullptr;          // pinned staging for descriptor tables
   size_t hcap = 0;
   hipEvent_t staged = nullptr;   // completes when the last staging copy has been read
@@ -244,6 +263,26 @@ tm_status ensure_device(StreamPool& p, size_t need, hipStream_t s) {
   const size_t cap = align256(need + need / 4);
   TM_HIP(hipMalloc(&p.dev, cap));
   p.cap = cap;
+  return TM_OK;
+}
+
+tm_status ensure_acc(StreamPool& p, size_t need, hipStream_t s) {
+  if (p.acc_cap < need) {
+    if (p.acc) {
+      TM_HIP(hipStreamSynchronize(s));
+      TM_HIP(hipFree(p.acc));
+      p.acc = nullptr;
+      p.acc_cap = 0;
+    }
+    const size_t cap = align256(std::max<size_t>(need + need / 4, 4096));
+    TM_HIP(hipMalloc(&p.acc, cap));
+    p.acc_cap = cap;
+    p.acc_dirty = true;
+  }
+  if (p.acc_dirty) {
+    TM_HIP(hipMemsetAsync(p.acc, 0, p.acc_cap, s));
+    p.acc_dirty = false;
+  }
   return TM_OK;
 }
 
@@ -315,6 +354,8 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->vb = c.vb;
   in->ntiles = c.ntiles;
   in->nred = c.nred;
+  in->red_tpe = c.red_tpe;
+  in->acc_int = c.acc_int;
   in->inv_a_mod_b = c.inv;
   in->t = p->t_dev;
   in->spec = p->spec;
@@ -322,7 +363,11 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->tnorm1 = p->tnorm1;
 }
 
-void place_workspace(const Core& c, char* base, Inst* in) {
+void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
+  if (c.acc_int) {
+    in->yp = reinterpret_cast<int*>(acc);
+    return;
+  }
   in->col_a = base + c.off_col_a;
   in->diag = c.dual ? base + c.off_diag : nullptr;
   in->col_b = c.dual ? nullptr : base + c.off_col_b;
@@ -498,12 +543,14 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   StreamPool& pool = g_pools[{p->device, s}];
   st = ensure_device(pool, p->core.ws_bytes, s);
   if (st != TM_OK) return st;
+  st = ensure_acc(pool, p->core.acc_bytes, s);
+  if (st != TM_OK) return st;
   InstTable tab{};
   tab.table = nullptr;
   tab.count = 1;
   fill_inst(p, x, &tab.one);
   char* base = static_cast<char*>(pool.dev);
-  place_workspace(p->core, base, &tab.one);
+  place_workspace(p->core, base, static_cast<char*>(pool.acc), &tab.one);
   tab.one.tile_base = 0;
   tab.one.red_base = 0;
   tab.one.out = dev_out ? out : reinterpret_cast<tm_result*>(base + p->core.off_res);
@@ -512,8 +559,10 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   tab.one.dbg_r1 = r1;
   tab.one.dbg_r2 = r2;
   TM_HIP(timed_fold(tab, p->core.ntiles, p->core.fold_lds, s));
+  pool.acc_dirty = true;                 // until the finish kernel is enqueued
   TM_HIP(launch_reduce(tab, p->core.nred, s));
   TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.finish_lds, s));
+  pool.acc_dirty = false;
   if (!dev_out) {
     TM_HIP(hipMemcpyAsync(out, tab.one.out, sizeof(tm_result), hipMemcpyDeviceToHost, s));
     TM_HIP(hipStreamSynchronize(s));
@@ -545,8 +594,8 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   const bool dev_out = is_device_pointer(out);
 
   // layout: [instance workspaces][results if host out][table][lists]
-  std::vector<size_t> ws_off(count);
-  size_t ws = 0;
+  std::vector<size_t> ws_off(count), acc_off(count);
+  size_t ws = 0, accb = 0;
   int64_t tiles = 0, chunks = 0;
   size_t fold_lds = 0, lds_exact = 0, lds_real = 0;
   int n_exact = 0, n_real = 0;
@@ -554,6 +603,8 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     const Core& c = plans[i]->core;
     ws_off[i] = ws;
     ws += c.ws_bytes;
+    acc_off[i] = accb;
+    accb += c.acc_bytes;
     tiles += c.ntiles;
     chunks += c.nred;
     fold_lds = std::max(fold_lds, c.fold_lds);
@@ -572,6 +623,8 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   StreamPool& pool = g_pools[{plans[0]->device, s}];
   tm_status st = ensure_device(pool, total, s);
   if (st != TM_OK) return st;
+  st = ensure_acc(pool, accb, s);
+  if (st != TM_OK) return st;
   st = ensure_host(pool, tab_bytes + list_bytes);
   if (st != TM_OK) return st;
   char* base = static_cast<char*>(pool.dev);
@@ -583,7 +636,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     const tm_plan_s* p = plans[i];
     Inst& in = host_tab[i];
     fill_inst(p, xs[i], &in);
-    place_workspace(p->core, base + ws_off[i], &in);
+    place_workspace(p->core, base + ws_off[i], static_cast<char*>(pool.acc) + acc_off[i], &in);
     in.tile_base = tile_base;
     in.red_base = red_base;
     tile_base += p->core.ntiles;
@@ -600,9 +653,11 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   tab.count = count;
   const int32_t* dlist = reinterpret_cast<const int32_t*>(base + off_lists);
   TM_HIP(timed_fold(tab, (int)tiles, fold_lds, s));
+  pool.acc_dirty = true;                 // until every finish kernel is enqueued
   TM_HIP(launch_reduce(tab, (int)chunks, s));
   TM_HIP(launch_finish(tab, dlist, n_exact, MODE_EXACT, lds_exact, s));
   TM_HIP(launch_finish(tab, dlist + n_exact, n_real, MODE_REAL, lds_real, s));
+  pool.acc_dirty = false;
   if (!dev_out) {
     TM_HIP(hipMemcpyAsync(out, base + off_res, sizeof(tm_result) * (size_t)count, hipMemcpyDeviceToHost, s));
     TM_HIP(hipStreamSynchronize(s));
