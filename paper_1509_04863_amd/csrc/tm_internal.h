@@ -41,7 +41,7 @@ struct alignas(16) Inst {
   int32_t tile_base;      // first fold tile of this instance in the launch
   int32_t ntiles;         // fold tiles of this instance
   int32_t red_base;       // first reduce workgroup of this instance in the launch
-  int32_t nred;           // reduce workgroups of this instance (real-valued folds only)
+  int32_t nred;           // reduce (real folds) or prep (integer folds) workgroups
   int32_t red_tpe;        // reduce threads per fold entry (a power of two <= 256)
   int32_t acc_int;        // 1: integer fold accumulated with atomics into `yp`
   int64_t inv_a_mod_b;    // ma^{-1} mod mb

@@ -51,34 +51,61 @@ template <> struct AccOf<float> {
   template <typename Tin> __device__ __forceinline__ static float from(Tin v) { return to_float(v); }
 };
 
+// Global memory through explicit address-space-1 pointers: plain global
+// instructions instead of FLAT ones (which would also tie LDS waits to
+// outstanding memory traffic).
+#define GAS __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GAS T* G(T* p) { return (GAS T*)p; }
+template <typename T> __device__ __forceinline__ GAS const T* G(const T* p) { return (GAS const T*)p; }
+
 __device__ __forceinline__ double load_as_double(const void* p, int dt, int64_t idx) {
   switch (dt) {
-    case TM_I8: return (double)((const int8_t*)p)[idx];
-    case TM_F32: return (double)((const float*)p)[idx];
-    case TM_BF16: return (double)to_float(((const bf16_t*)p)[idx]);
-    default: return (double)to_float(((const f16_t*)p)[idx]);
+    case TM_I8: return (double)G((const int8_t*)p)[idx];
+    case TM_F32: return (double)G((const float*)p)[idx];
+    case TM_BF16: return (double)to_float(bf16_t{G((const uint16_t*)p)[idx]});
+    default: return (double)to_float(f16_t{G((const uint16_t*)p)[idx]});
   }
 }
 
 __device__ __forceinline__ int load_as_int(const void* p, int dt, int64_t idx) {
   switch (dt) {
-    case TM_I8: return (int)((const int8_t*)p)[idx];
-    case TM_F32: return __float2int_rn(((const float*)p)[idx]);
-    case TM_BF16: return __float2int_rn(to_float(((const bf16_t*)p)[idx]));
-    default: return __float2int_rn(to_float(((const f16_t*)p)[idx]));
+    case TM_I8: return (int)G((const int8_t*)p)[idx];
+    case TM_F32: return __float2int_rn(G((const float*)p)[idx]);
+    case TM_BF16: return __float2int_rn(to_float(bf16_t{G((const uint16_t*)p)[idx]}));
+    default: return __float2int_rn(to_float(f16_t{G((const uint16_t*)p)[idx]}));
   }
 }
 
 __device__ __forceinline__ float load_as_float(const void* p, int dt, int64_t idx) {
   switch (dt) {
-    case TM_I8: return (float)((const int8_t*)p)[idx];
-    case TM_F32: return ((const float*)p)[idx];
-    case TM_BF16: return to_float(((const bf16_t*)p)[idx]);
-    default: return to_float(((const f16_t*)p)[idx]);
+    case TM_I8: return (float)G((const int8_t*)p)[idx];
+    case TM_F32: return G((const float*)p)[idx];
+    case TM_BF16: return to_float(bf16_t{G((const uint16_t*)p)[idx]});
+    default: return to_float(f16_t{G((const uint16_t*)p)[idx]});
   }
 }
 
 __device__ __forceinline__ bool acc_is_int(const Inst& d) { return d.acc_int != 0; }
+
+// typed loads of one element as int / double (storage type known at compile time)
+template <typename Tin> __device__ __forceinline__ int ld_int(const void* p, int64_t i);
+template <> __device__ __forceinline__ int ld_int<int8_t>(const void* p, int64_t i) { return G((const int8_t*)p)[i]; }
+template <> __device__ __forceinline__ int ld_int<float>(const void* p, int64_t i) { return __float2int_rn(G((const float*)p)[i]); }
+template <> __device__ __forceinline__ int ld_int<bf16_t>(const void* p, int64_t i) {
+  return __float2int_rn(to_float(bf16_t{G((const uint16_t*)p)[i]}));
+}
+template <> __device__ __forceinline__ int ld_int<f16_t>(const void* p, int64_t i) {
+  return __float2int_rn(to_float(f16_t{G((const uint16_t*)p)[i]}));
+}
+template <typename Tin> __device__ __forceinline__ double ld_dbl(const void* p, int64_t i);
+template <> __device__ __forceinline__ double ld_dbl<int8_t>(const void* p, int64_t i) { return G((const int8_t*)p)[i]; }
+template <> __device__ __forceinline__ double ld_dbl<float>(const void* p, int64_t i) { return G((const float*)p)[i]; }
+template <> __device__ __forceinline__ double ld_dbl<bf16_t>(const void* p, int64_t i) {
+  return to_float(bf16_t{G((const uint16_t*)p)[i]});
+}
+template <> __device__ __forceinline__ double ld_dbl<f16_t>(const void* p, int64_t i) {
+  return to_float(f16_t{G((const uint16_t*)p)[i]});
+}
 
 // v mod n for 0 <= v: a few subtractions cover the common v < 4n, a division the rest
 __device__ __forceinline__ int64_t mod_pos(int64_t v, int64_t n) {
@@ -233,10 +260,10 @@ __device__ __forceinline__ void fold_tile(const Inst& d, int lt, unsigned char* 
     const Acc acc = strided_sum<Acc>(t + j + R - 1, S - 1, Reff);
     if constexpr (AccOf<Acc>::kInt) {   // integer: exact, order-independent atomics
       int* yp = d.yp + (in_a ? 0 : d.va.m);
-      if (acc) __hip_atomic_fetch_add(yp + c0 + j, (int)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (acc) __hip_atomic_fetch_add(G(yp + c0 + j), (int)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       Acc* colp = reinterpret_cast<Acc*>(in_a ? d.col_a : d.col_b);
-      colp[(int64_t)rb * M + c0 + j] = acc;
+      G(colp)[(int64_t)rb * M + c0 + j] = acc;
     }
   }
   if (want_diag) {
@@ -246,9 +273,9 @@ __device__ __forceinline__ void fold_tile(const Inst& d, int lt, unsigned char* 
       if constexpr (AccOf<Acc>::kInt) {
         int64_t b = ((int64_t)c0 + e - (R - 1) - (int64_t)rb * R) % mb;
         if (b < 0) b += mb;
-        if (acc) __hip_atomic_fetch_add(d.yp + d.va.m + b, (int)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (acc) __hip_atomic_fetch_add(G(d.yp + d.va.m + b), (int)acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
-        reinterpret_cast<Acc*>(d.diag)[(int64_t)(rb * v.ncb + cb) * S + e] = acc;
+        G(reinterpret_cast<Acc*>(d.diag))[(int64_t)(rb * v.ncb + cb) * S + e] = acc;
       }
     }
   }
@@ -309,8 +336,8 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_
 
 // contribution of row block rb to bucket s of fold f (partition fold)
 __device__ __forceinline__ float bucket_part(const Inst& d, int f, int s, int rb) {
-  if (f == 0) return reinterpret_cast<const float*>(d.col_a)[(int64_t)rb * d.va.m + s];
-  if (!d.dual) return reinterpret_cast<const float*>(d.col_b)[(int64_t)rb * d.vb.m + s];
+  if (f == 0) return G(reinterpret_cast<const float*>(d.col_a))[(int64_t)rb * d.va.m + s];
+  if (!d.dual) return G(reinterpret_cast<const float*>(d.col_b))[(int64_t)rb * d.vb.m + s];
   // diagonal e of tile (rb, cb) covers bucket (e + cb*W - rb*R - (R-1)) mod mb
   const float* p = reinterpret_cast<const float*>(d.diag);
   const int R = d.va.rows, W = d.va.cols, E = W + R - 1, ncb = d.va.ncb;
@@ -322,7 +349,7 @@ __device__ __forceinline__ float bucket_part(const Inst& d, int f, int s, int rb
     const int cb_hi = (int)min(q / W, (int64_t)ncb - 1);
     const int64_t lo_num = q - (E - 1);
     const int cb_lo = lo_num <= 0 ? 0 : (int)((lo_num + W - 1) / W);
-    for (int cb = cb_lo; cb <= cb_hi; ++cb) acc += p[(int64_t)(rb * ncb + cb) * E + (q - (int64_t)cb * W)];
+    for (int cb = cb_lo; cb <= cb_hi; ++cb) acc += G(p)[(int64_t)(rb * ncb + cb) * E + (q - (int64_t)cb * W)];
   }
   return acc;
 }
@@ -330,6 +357,43 @@ __device__ __forceinline__ float bucket_part(const Inst& d, int f, int s, int rb
 // Threads of a workgroup are split into groups of red_tpe lanes, one group per
 // fold entry; lane t sums row blocks t, t + tpe, ... and lane 0 adds the lanes
 // in order, then the cyclic wrap terms.
+// --------------------------------------------------------------------------
+// integer folds: literal folds from the partition buckets
+// --------------------------------------------------------------------------
+
+// y[u] for fold f: y[s] = yp[s] + wrapped last term (Section 2: indices mod N),
+// y[M + s] = y[s] - x[s] + x[(s + L M) mod N].  One thread per entry.
+template <typename Tin>
+__device__ __forceinline__ void prep_wg(const Inst& d, int lc) {
+  const int totA = d.va.m + d.k - 1;
+  const int tot = totA + d.vb.m + d.k - 1;
+  const int u = lc * kReduceThreads + threadIdx.x;
+  if (u >= tot) return;
+  const int f = u >= totA;
+  const int uu = f ? u - totA : u;
+  const int64_t M = f ? d.vb.m : d.va.m;
+  const int64_t L = f ? d.vb.l : d.va.l;
+  const int64_t N = d.n;
+  const int s = uu < M ? uu : (int)(uu - M);
+  const bool wrap = (int64_t)s + (L - 1) * M >= N;
+  const bool ext = uu >= M;
+  // every load issued before any use (addresses of unused terms point at x[0])
+  const int b = G(d.yp)[(f ? d.va.m : 0) + s];
+  const int w = ld_int<Tin>(d.x, wrap ? mod_pos((int64_t)s + (L - 1) * M, N) : 0);
+  const int e1 = ld_int<Tin>(d.x, ext ? mod_pos((int64_t)s + L * M, N) : 0);
+  const int e0 = ld_int<Tin>(d.x, ext ? s : 0);
+  G(reinterpret_cast<int*>(d.y))[u] = b + (wrap ? w : 0) + (ext ? e1 - e0 : 0);
+}
+
+__device__ __forceinline__ void prep_dispatch(const Inst& d, int lc) {
+  switch (d.x_dtype) {
+    case TM_I8: prep_wg<int8_t>(d, lc); break;
+    case TM_F32: prep_wg<float>(d, lc); break;
+    case TM_BF16: prep_wg<bf16_t>(d, lc); break;
+    default: prep_wg<f16_t>(d, lc); break;
+  }
+}
+
 __device__ __forceinline__ void reduce_wg(const Inst& d, int lc, float* part) {
   const int tpe = d.red_tpe;
   const int epw = kReduceThreads / tpe;
@@ -356,22 +420,26 @@ __device__ __forceinline__ void reduce_wg(const Inst& d, int lc, float* part) {
     if ((int64_t)s + (L - 1) * M >= N) sum += load_as_float(d.x, d.x_dtype, mod_pos((int64_t)s + (L - 1) * M, N));
     if (uu >= M)
       sum += load_as_float(d.x, d.x_dtype, mod_pos((int64_t)s + L * M, N)) - load_as_float(d.x, d.x_dtype, s);
-    reinterpret_cast<float*>(d.y)[u] = sum;
+    G(reinterpret_cast<float*>(d.y))[u] = sum;
   }
 }
 
-// Threads of a workgroup are split into groups of red_tpe lanes, one group per
-// fold entry; lane t sums row blocks t, t + tpe, ... and lane 0 adds the lanes
-// in order, then the cyclic wrap terms.
+// Literal folds for every instance of a launch: integer folds from their
+// buckets (one thread per entry); real folds from their partials, with the
+// threads of a workgroup split into groups of red_tpe lanes, one group per fold
+// entry (lane t sums row blocks t, t + tpe, ...; lane 0 adds the lanes in
+// order, then the cyclic wrap terms).
 __global__ void __launch_bounds__(kReduceThreads) k_reduce(InstTable tab, int total_wgs) {
   __shared__ float part[kReduceThreads];
   const int wg = blockIdx.x;
   if (wg >= total_wgs) return;
   if (tab.table) {
     const Inst& d = tab.table[find_inst_by_red(tab, wg)];
-    reduce_wg(d, wg - d.red_base, part);
+    if (d.acc_int) prep_dispatch(d, wg - d.red_base);
+    else reduce_wg(d, wg - d.red_base, part);
   } else {
-    reduce_wg(tab.one, wg, part);
+    if (tab.one.acc_int) prep_dispatch(tab.one, wg);
+    else reduce_wg(tab.one, wg, part);
   }
 }
 
@@ -482,6 +550,12 @@ size_t finish_lds_bytes(int p_log2, int mode) {
   return (size_t)padded_len(1 << p_log2) * el + (size_t)kFinishThreads * 16;
 }
 
+template <typename T>
+__device__ __forceinline__ cplx<T> ldc(const cplx<T>* p, int i) {
+  const GAS T* q = G(reinterpret_cast<const T*>(p));
+  return cplx<T>{q[2 * i], q[2 * i + 1]};
+}
+
 // Output twiddles of a pass: w = W^(off 2^s0); position m gets w^br(m).  The
 // pass loads w^(2^j) from the table and forms w^q = w^(q & 3) * (w^4)^(q >> 2).
 template <int KB, typename T>
@@ -491,12 +565,12 @@ struct PassTwiddles {
   __device__ __forceinline__ void init(const cplx<T>* __restrict__ tw, int off, int s0) {
     lo[0] = {(T)1, (T)0};
     hi[0] = {(T)1, (T)0};
-    if (KB >= 1) lo[1] = tw[off << s0];
-    if (KB >= 2) { lo[2] = tw[(off << 1) << s0]; lo[3] = cmul(lo[2], lo[1]); }
-    if (KB >= 3) hi[1] = tw[(off << 2) << s0];
-    if (KB >= 4) { hi[2] = tw[(off << 3) << s0]; hi[3] = cmul(hi[2], hi[1]); }
+    if (KB >= 1) lo[1] = ldc(tw, off << s0);
+    if (KB >= 2) { lo[2] = ldc(tw, (off << 1) << s0); lo[3] = cmul(lo[2], lo[1]); }
+    if (KB >= 3) hi[1] = ldc(tw, (off << 2) << s0);
+    if (KB >= 4) { hi[2] = ldc(tw, (off << 3) << s0); hi[3] = cmul(hi[2], hi[1]); }
     if (KB >= 5) {
-      hi[4] = tw[(off << 4) << s0];
+      hi[4] = ldc(tw, (off << 4) << s0);
       hi[5] = cmul(hi[4], hi[1]);
       hi[6] = cmul(hi[4], hi[2]);
       hi[7] = cmul(hi[6], hi[1]);
@@ -548,13 +622,18 @@ __device__ void fft_pass(cplx<T>* buf, int p, int s0, const cplx<T>* __restrict_
     } else {
       dft_dif<KB>(v);
 #pragma unroll
-      for (int m = 0; m < RR; ++m) v[m] = cmul(v[m], spec[base + (m << lh)]);
+      for (int m = 0; m < RR; ++m) v[m] = cmul(v[m], ldc(spec, base + (m << lh)));
       dft_dit<KB>(v);
     }
 #pragma unroll
     for (int m = 0; m < RR; ++m) buf[padi(base + (m << lh))] = v[m];
   }
 }
+
+// Twiddled passes stop at radix 16 (a twiddled radix-32 pass with its twiddle
+// table would not fit the register file); the twiddle-free middle pass may be
+// radix 32.
+template <typename T> struct FftLimits { static constexpr int kTw = 4; static constexpr int kMid = 5; };
 
 template <int DIR, typename T>
 __device__ __forceinline__ void fft_pass_kb(int kb, cplx<T>* buf, int p, int s0, const cplx<T>* tw,
@@ -564,17 +643,27 @@ __device__ __forceinline__ void fft_pass_kb(int kb, cplx<T>* buf, int p, int s0,
     case 2: fft_pass<2, DIR>(buf, p, s0, tw, spec); break;
     case 3: fft_pass<3, DIR>(buf, p, s0, tw, spec); break;
     case 4: fft_pass<4, DIR>(buf, p, s0, tw, spec); break;
-    default: fft_pass<5, DIR>(buf, p, s0, tw, spec); break;
+    default:
+      if constexpr (DIR == 2 || FftLimits<T>::kTw >= 5) fft_pass<5, DIR>(buf, p, s0, tw, spec);
+      break;
   }
 }
 
-// Pass i of the plan for length 2^p: at most 5 stages per pass, as few passes
-// as possible, sizes balanced and the larger ones last (the fused middle pass).
-__device__ __forceinline__ int fft_npasses(int p) { return (p + 4) / 5; }
+// Pass plan for length 2^p: the middle pass takes min(p, 5) stages, the
+// twiddled passes before it split the rest as evenly as possible.
+template <typename T>
+__device__ __forceinline__ int fft_npasses(int p) {
+  const int rest = p - min(p, FftLimits<T>::kMid);
+  return 1 + (rest + FftLimits<T>::kTw - 1) / FftLimits<T>::kTw;
+}
+template <typename T>
 __device__ __forceinline__ void fft_pass_of(int i, int p, int& s0, int& kb) {
-  const int np = fft_npasses(p);
-  const int small = p / np, nbig = p - small * np;   // the last nbig passes get small + 1
-  const int nsmall = np - nbig;
+  const int mid = min(p, FftLimits<T>::kMid);
+  const int rest = p - mid;
+  const int ntw = fft_npasses<T>(p) - 1;
+  if (i == ntw) { s0 = rest; kb = mid; return; }
+  const int small = rest / ntw, nbig = rest - small * ntw;   // the last nbig get small + 1
+  const int nsmall = ntw - nbig;
   if (i < nsmall) { s0 = i * small; kb = small; }
   else { s0 = nsmall * small + (i - nsmall) * (small + 1); kb = small + 1; }
 }
@@ -583,18 +672,18 @@ __device__ __forceinline__ void fft_pass_of(int i, int p, int& s0, int& kb) {
 // spectrum, inverse transform, all in LDS.
 template <typename T>
 __device__ void fft_correlate(cplx<T>* buf, int p, const cplx<T>* tw, const cplx<T>* spec) {
-  const int np = fft_npasses(p);
+  const int np = fft_npasses<T>(p);
   int s0, kb;
   for (int i = 0; i + 1 < np; ++i) {
-    fft_pass_of(i, p, s0, kb);
+    fft_pass_of<T>(i, p, s0, kb);
     fft_pass_kb<0>(kb, buf, p, s0, tw, spec);
     __syncthreads();
   }
-  fft_pass_of(np - 1, p, s0, kb);
+  fft_pass_of<T>(np - 1, p, s0, kb);
   fft_pass_kb<2>(kb, buf, p, s0, tw, spec);
   __syncthreads();
   for (int i = np - 2; i >= 0; --i) {
-    fft_pass_of(i, p, s0, kb);
+    fft_pass_of<T>(i, p, s0, kb);
     fft_pass_kb<1>(kb, buf, p, s0, tw, spec);
     __syncthreads();
   }
@@ -610,29 +699,34 @@ __device__ __forceinline__ bool vi_better(const VI& a, const VI& b) {
   return a.v > b.v || (a.v == b.v && a.i < b.i);
 }
 
+// wave reduction with xor shuffles, then one value per wave through LDS
 __device__ VI block_argmax(VI mine, VI* scratch) {
-  const int tid = threadIdx.x;
-  scratch[tid] = mine;
-  __syncthreads();
-  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-    if (tid < s && vi_better(scratch[tid + s], scratch[tid])) scratch[tid] = scratch[tid + s];
-    __syncthreads();
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const VI o{__shfl_xor(mine.v, m), __shfl_xor(mine.i, m)};
+    if (vi_better(o, mine)) mine = o;
   }
-  const VI r = scratch[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) scratch[wave] = mine;
+  __syncthreads();
+  VI r = scratch[0];
+  for (int w = 1; w < nw; ++w)
+    if (vi_better(scratch[w], r)) r = scratch[w];
   __syncthreads();
   return r;
 }
 
+// fixed pairing (xor butterflies inside a wave, waves in index order): the
+// same inputs always give the same sum
 template <typename S>
 __device__ S block_sum(S mine, S* scratch) {
-  const int tid = threadIdx.x;
-  scratch[tid] = mine;
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) mine = mine + __shfl_xor(mine, m);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) scratch[wave] = mine;
   __syncthreads();
-  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-    if (tid < s) scratch[tid] = scratch[tid] + scratch[tid + s];
-    __syncthreads();
-  }
-  const S r = scratch[0];
+  S r = scratch[0];
+  for (int w = 1; w < nw; ++w) r = r + scratch[w];
   __syncthreads();
   return r;
 }
@@ -653,26 +747,38 @@ __device__ __forceinline__ T store_round(float v, int fold_store) {
 }
 
 // Score (Tx)_c = sum_j t_j x[(c + j) mod N]: int64 on the exact path, FP64 otherwise.
+template <typename Tin, typename Tt>
 __device__ __forceinline__ double score_at(const Inst& d, int64_t c, void* scratch) {
   const int64_t N = d.n;
   if (d.mode == MODE_EXACT) {
     long long acc = 0;
+#pragma unroll 4
     for (int j = threadIdx.x; j < d.k; j += blockDim.x) {
       const int64_t xi = c + j < N ? c + j : c + j - N;   // c < N, j < K <= N
-      acc += (long long)llrint(load_as_double(d.t, d.t_dtype, j)) *
-             (long long)llrint(load_as_double(d.x, d.x_dtype, xi));
+      acc += (long long)ld_int<Tt>(d.t, j) * (long long)ld_int<Tin>(d.x, xi);
     }
     return (double)block_sum<long long>(acc, (long long*)scratch);
   }
   double acc = 0.0;
+#pragma unroll 4
   for (int j = threadIdx.x; j < d.k; j += blockDim.x) {
     const int64_t xi = c + j < N ? c + j : c + j - N;
-    acc += load_as_double(d.t, d.t_dtype, j) * load_as_double(d.x, d.x_dtype, xi);
+    acc += ld_dbl<Tt>(d.t, j) * ld_dbl<Tin>(d.x, xi);
   }
   return block_sum<double>(acc, (double*)scratch);
 }
 
-template <typename T>
+template <typename Tin>
+__device__ __forceinline__ double score_any_t(const Inst& d, int64_t c, void* scratch) {
+  switch (d.t_dtype) {
+    case TM_I8: return score_at<Tin, int8_t>(d, c, scratch);
+    case TM_F32: return score_at<Tin, float>(d, c, scratch);
+    case TM_BF16: return score_at<Tin, bf16_t>(d, c, scratch);
+    default: return score_at<Tin, f16_t>(d, c, scratch);
+  }
+}
+
+template <typename T, typename Tin>
 __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* lds) {
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
@@ -690,76 +796,63 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
   double* drb = d.swapped ? d.dbg_r1 : d.dbg_r2;
   double znorm2 = 0.0;
 
-  // literal folds (Algorithm 1 step 3) packed as z = yA + i yB, zero padded to P
-  if (ints) {
-    // 1) partition buckets, 2) wrapped last terms, 3) the K-1 entries past M:
-    //    y[M + s] = y[s] - x[s] + x[(s + L M) mod N].  Integer values, exact in
-    //    T (FP64; FP32 below 2^24 in magnitude).
-    const int64_t N = d.n;
-    for (int n = tid; n < P; n += NT)
-      buf[padi(n)] = cplx<T>{n < ma ? (T)d.yp[n] : (T)0, n < mb ? (T)d.yp[ma + n] : (T)0};
-    __syncthreads();
-    for (int f = 0; f < 2; ++f) {
-      const int64_t M = f ? mb : ma, L = f ? d.vb.l : d.va.l;
-      const int64_t s0 = max((int64_t)0, N - (L - 1) * M);   // first bucket whose last term wraps
-      for (int64_t s = s0 + tid; s < M; s += NT) {
-        T* e = f ? &buf[padi((int)s)].y : &buf[padi((int)s)].x;
-        *e += (T)load_as_int(d.x, d.x_dtype, mod_pos(s + (L - 1) * M, N));
-      }
+  // literal folds (Algorithm 1 step 3) packed as z = yA + i yB, zero padded
+  // to P.  Thread tid owns entries n = tid + v*NT (coalesced) and issues all
+  // their loads before the first use.
+  {
+    constexpr int VMAX = (1 << 14) / kFinishThreads;
+    const int V = (P + NT - 1) / NT;
+    const GAS int* yi = G(reinterpret_cast<const int*>(d.y));
+    const GAS float* yf = G(reinterpret_cast<const float*>(d.y));
+    float ra[VMAX], rb[VMAX];
+#pragma unroll
+    for (int v = 0; v < VMAX; ++v) {
+      const int n = tid + v * NT;
+      const bool in = v < V && n < P;
+      const int ia = in && n < na ? n : 0, ib = in && n < nb ? na + n : 0;
+      if (ints) { ra[v] = __int_as_float(yi[ia]); rb[v] = __int_as_float(yi[ib]); }
+      else { ra[v] = yf[ia]; rb[v] = yf[ib]; }
     }
-    __syncthreads();
-    for (int f = 0; f < 2; ++f) {
-      const int64_t M = f ? mb : ma, L = f ? d.vb.l : d.va.l;
-      for (int s = tid; s < K - 1; s += NT) {
-        const T lo = f ? buf[padi(s)].y : buf[padi(s)].x;
-        const T v = lo - (T)load_as_int(d.x, d.x_dtype, s) +
-                    (T)load_as_int(d.x, d.x_dtype, mod_pos((int64_t)s + L * M, N));
-        if (f) buf[padi((int)M + s)].y = v; else buf[padi((int)M + s)].x = v;
-      }
-    }
-    __syncthreads();
     double ss = 0.0;
-    for (int n = tid; n < P; n += NT) {
-      cplx<T> v = buf[padi(n)];
-      if (!exact) {
-        v.x = store_round<T>((float)v.x, d.fold_store);
-        v.y = store_round<T>((float)v.y, d.fold_store);
-        buf[padi(n)] = v;
+#pragma unroll
+    for (int v = 0; v < VMAX; ++v) {
+      const int n = tid + v * NT;
+      if (v < V && n < P) {
+        T re = 0, im = 0;
+        if (n < na) {
+          const float a = ints ? (float)__float_as_int(ra[v]) : ra[v];
+          re = exact ? (T)__float_as_int(ra[v]) : store_round<T>(a, d.fold_store);
+          if (dya) G(dya)[n] = (double)re;
+        }
+        if (n < nb) {
+          const float b = ints ? (float)__float_as_int(rb[v]) : rb[v];
+          im = exact ? (T)__float_as_int(rb[v]) : store_round<T>(b, d.fold_store);
+          if (dyb) G(dyb)[n] = (double)im;
+        }
+        ss += (double)re * (double)re + (double)im * (double)im;
+        buf[padi(n)] = cplx<T>{re, im};
       }
-      if (dya && n < na) dya[n] = (double)v.x;
-      if (dyb && n < nb) dyb[n] = (double)v.y;
-      ss += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
     }
     znorm2 = block_sum<double>(ss, (double*)scratch);   // includes barriers
-    for (int s = tid; s < ma + mb; s += NT) d.yp[s] = 0;   // buckets back to zero
-  } else {
-    const float* yf = reinterpret_cast<const float*>(d.y);
-    double ss = 0.0;
-#pragma unroll 4
-    for (int n = tid; n < P; n += NT) {
-      const T re = n < na ? store_round<T>(yf[n], d.fold_store) : (T)0;
-      const T im = n < nb ? store_round<T>(yf[na + n], d.fold_store) : (T)0;
-      if (dya && n < na) dya[n] = (double)re;
-      if (dyb && n < nb) dyb[n] = (double)im;
-      ss += (double)re * (double)re + (double)im * (double)im;
-      buf[padi(n)] = cplx<T>{re, im};
-    }
-    znorm2 = block_sum<double>(ss, (double*)scratch);
+    if (ints)   // the buckets were consumed by k_reduce: back to zero for the next launch
+      for (int s = tid; s < ma + mb; s += NT) G(d.yp)[s] = 0;
   }
 
   fft_correlate<T>(buf, p, reinterpret_cast<const cplx<T>*>(d.tw), reinterpret_cast<const cplx<T>*>(d.spec));
 
   // step 7: argmax over [0, M) of each fold, lowest index on ties
   VI ba{-INFINITY, 0x7fffffff}, bb{-INFINITY, 0x7fffffff};
+#pragma unroll 8
   for (int n = tid; n < ma; n += NT) {
     const double v = exact ? rint((double)buf[padi(n)].x) : (double)buf[padi(n)].x;
-    if (dra) dra[n] = v;
+    if (dra) G(dra)[n] = v;
     const VI c{v, n};
     if (vi_better(c, ba)) ba = c;
   }
+#pragma unroll 8
   for (int n = tid; n < mb; n += NT) {
     const double v = exact ? rint((double)buf[padi(n)].y) : (double)buf[padi(n)].y;
-    if (drb) drb[n] = v;
+    if (drb) G(drb)[n] = v;
     const VI c{v, n};
     if (vi_better(c, bb)) bb = c;
   }
@@ -831,22 +924,31 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
   int64_t best = -1;
   double best_score = 0.0;
   for (int i = 0; i < nc; ++i) {
-    const double sc = score_at(d, cand[i], scratch);
+    const double sc = score_any_t<Tin>(d, cand[i], scratch);
     if (i == 0 || sc > best_score) { best = cand[i]; best_score = sc; }
   }
   if (nc == 0) flags |= TM_R_NOMATCH;
   if (nc > 1) flags |= TM_R_RESCORED;
   if (tid == 0) {
-    tm_result r;
-    r.shift = best;
-    r.m1_tilde = d.swapped ? bmax.i : amax.i;
-    r.m2_tilde = d.swapped ? amax.i : bmax.i;
-    r.n_candidates = nc;
-    r.flags = flags;
-    r.peak1 = d.swapped ? bmax.v : amax.v;
-    r.peak2 = d.swapped ? amax.v : bmax.v;
-    r.score = nc ? best_score : 0.0;
-    *d.out = r;
+    GAS tm_result* r = G(d.out);
+    r->shift = best;
+    r->m1_tilde = d.swapped ? bmax.i : amax.i;
+    r->m2_tilde = d.swapped ? amax.i : bmax.i;
+    r->n_candidates = nc;
+    r->flags = flags;
+    r->peak1 = d.swapped ? bmax.v : amax.v;
+    r->peak2 = d.swapped ? amax.v : bmax.v;
+    r->score = nc ? best_score : 0.0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void finish_dispatch(const Inst& d, unsigned char* lds) {
+  switch (d.x_dtype) {
+    case TM_I8: finish_instance<T, int8_t>(d, lds); break;
+    case TM_F32: finish_instance<T, float>(d, lds); break;
+    case TM_BF16: finish_instance<T, bf16_t>(d, lds); break;
+    default: finish_instance<T, f16_t>(d, lds); break;
   }
 }
 
@@ -855,8 +957,8 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish(InstTable tab, const 
   extern __shared__ __align__(16) unsigned char lds[];
   const int b = blockIdx.x;
   if (b >= count) return;
-  if (tab.table) finish_instance<T>(tab.table[list ? list[b] : b], lds);
-  else finish_instance<T>(tab.one, lds);
+  if (tab.table) finish_dispatch<T>(tab.table[list ? list[b] : b], lds);
+  else finish_dispatch<T>(tab.one, lds);
 }
 
 // --------------------------------------------------------------------------

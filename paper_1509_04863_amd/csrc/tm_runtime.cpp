@@ -172,9 +172,10 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   const int64_t ytot = (int64_t)c->ma + c->k - 1 + c->mb + c->k - 1;
   size_t off = 0;
   if (c->acc_int) {
-    // integer folds go straight to the bucket zone: no partials, no reduce
+    // integer folds go straight to the bucket zone; k_reduce writes the literal folds
     c->acc_bytes = align256((size_t)(c->ma + c->mb) * 4);
-    c->nred = 0;
+    c->nred = (int32_t)ceil_div(ytot, kReduceThreads);
+    c->off_y = off; off = align256(off + (size_t)ytot * 4);
   } else {
     const int nrb = std::max(c->va.nrb, c->dual ? 0 : c->vb.nrb);
     int tpe = 1;
@@ -366,6 +367,7 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
 void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
   if (c.acc_int) {
     in->yp = reinterpret_cast<int*>(acc);
+    in->y = base + c.off_y;
     return;
   }
   in->col_a = base + c.off_col_a;
