@@ -217,10 +217,13 @@ struct StreamPool {
   void* acc = nullptr;           // integer bucket zone: all zero between launches
   size_t acc_cap = 0;
   bool acc_dirty = false;        // a launch sequence broke off after its fold
-  void* host = nullptr;          // pinned staging for descriptor tables
-  size_t hcap = 0;
-  hipEvent_t staged = nullptr;   // completes when the last staging copy has been read
-  bool staged_pending = false;
+  // two pinned staging buffers for descriptor tables, used in turn: the host
+  // fills one while the copy out of the other may still be in flight
+  void* host[2] = {nullptr, nullptr};
+  size_t hcap[2] = {0, 0};
+  hipEvent_t staged[2] = {nullptr, nullptr};   // completes when that buffer's copy is done
+  bool staged_pending[2] = {false, false};
+  int next = 0;
 };
 
 std::mutex g_mu;
@@ -287,19 +290,24 @@ tm_status ensure_acc(StreamPool& p, size_t need, hipStream_t s) {
   return TM_OK;
 }
 
-tm_status ensure_host(StreamPool& p, size_t need) {
-  if (p.staged_pending) {
-    TM_HIP(hipEventSynchronize(p.staged));
-    p.staged_pending = false;
+// Pick the next staging buffer, wait until its previous copy has been read,
+// grow it if needed.  Returns its index in *slot.
+tm_status ensure_host(StreamPool& p, size_t need, int* slot) {
+  const int i = p.next;
+  p.next ^= 1;
+  *slot = i;
+  if (p.staged_pending[i]) {
+    TM_HIP(hipEventSynchronize(p.staged[i]));
+    p.staged_pending[i] = false;
   }
-  if (p.hcap >= need) return TM_OK;
-  if (p.host) TM_HIP(hipHostFree(p.host));
-  p.host = nullptr;
-  p.hcap = 0;
+  if (!p.staged[i]) TM_HIP(hipEventCreateWithFlags(&p.staged[i], hipEventDisableTiming));
+  if (p.hcap[i] >= need) return TM_OK;
+  if (p.host[i]) TM_HIP(hipHostFree(p.host[i]));
+  p.host[i] = nullptr;
+  p.hcap[i] = 0;
   const size_t cap = align256(need + need / 4);
-  TM_HIP(hipHostMalloc(&p.host, cap, hipHostMallocDefault));
-  p.hcap = cap;
-  if (!p.staged) TM_HIP(hipEventCreateWithFlags(&p.staged, hipEventDisableTiming));
+  TM_HIP(hipHostMalloc(&p.host[i], cap, hipHostMallocDefault));
+  p.hcap[i] = cap;
   return TM_OK;
 }
 
@@ -599,8 +607,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   std::vector<size_t> ws_off(count), acc_off(count);
   size_t ws = 0, accb = 0;
   int64_t tiles = 0, chunks = 0;
-  size_t fold_lds = 0, lds_exact = 0, lds_real = 0;
-  int n_exact = 0, n_real = 0;
+  size_t fold_lds = 0;
   for (int32_t i = 0; i < count; ++i) {
     const Core& c = plans[i]->core;
     ws_off[i] = ws;
@@ -610,10 +617,16 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     tiles += c.ntiles;
     chunks += c.nred;
     fold_lds = std::max(fold_lds, c.fold_lds);
-    if (c.mode == MODE_EXACT) { lds_exact = std::max(lds_exact, c.finish_lds); ++n_exact; }
-    else { lds_real = std::max(lds_real, c.finish_lds); ++n_real; }
   }
   if (tiles > 0x7fffffff || chunks > 0x7fffffff) return fail(TM_ERR_UNSUPPORTED, "batch too large");
+  // finish launches are grouped by (mode, FFT length) so each gets its own LDS size
+  std::vector<int32_t> order(count);
+  for (int32_t i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    const Core& ca = plans[a]->core;
+    const Core& cb = plans[b]->core;
+    return ca.mode != cb.mode ? ca.mode < cb.mode : ca.p_log2 < cb.p_log2;
+  });
   const size_t off_res = align256(ws);
   const size_t off_tab = align256(off_res + (dev_out ? 0 : sizeof(tm_result) * (size_t)count));
   const size_t tab_bytes = sizeof(Inst) * (size_t)count;
@@ -627,13 +640,13 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   if (st != TM_OK) return st;
   st = ensure_acc(pool, accb, s);
   if (st != TM_OK) return st;
-  st = ensure_host(pool, tab_bytes + list_bytes);
+  int slot = 0;
+  st = ensure_host(pool, tab_bytes + list_bytes, &slot);
   if (st != TM_OK) return st;
   char* base = static_cast<char*>(pool.dev);
-  Inst* host_tab = static_cast<Inst*>(pool.host);
-  int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host) + tab_bytes);
+  Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
+  int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + tab_bytes);
   int32_t tile_base = 0, red_base = 0;
-  int ie = 0, ir = n_exact;
   for (int32_t i = 0; i < count; ++i) {
     const tm_plan_s* p = plans[i];
     Inst& in = host_tab[i];
@@ -644,11 +657,11 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     tile_base += p->core.ntiles;
     red_base += p->core.nred;
     in.out = dev_out ? out + i : reinterpret_cast<tm_result*>(base + off_res) + i;
-    if (p->core.mode == MODE_EXACT) host_list[ie++] = i; else host_list[ir++] = i;
+    host_list[i] = order[i];
   }
-  TM_HIP(hipMemcpyAsync(base + off_tab, pool.host, tab_bytes + list_bytes, hipMemcpyHostToDevice, s));
-  TM_HIP(hipEventRecord(pool.staged, s));
-  pool.staged_pending = true;
+  TM_HIP(hipMemcpyAsync(base + off_tab, pool.host[slot], tab_bytes + list_bytes, hipMemcpyHostToDevice, s));
+  TM_HIP(hipEventRecord(pool.staged[slot], s));
+  pool.staged_pending[slot] = true;
 
   InstTable tab{};
   tab.table = reinterpret_cast<const Inst*>(base + off_tab);
@@ -657,8 +670,13 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   TM_HIP(timed_fold(tab, (int)tiles, fold_lds, s));
   pool.acc_dirty = true;                 // until every finish kernel is enqueued
   TM_HIP(launch_reduce(tab, (int)chunks, s));
-  TM_HIP(launch_finish(tab, dlist, n_exact, MODE_EXACT, lds_exact, s));
-  TM_HIP(launch_finish(tab, dlist + n_exact, n_real, MODE_REAL, lds_real, s));
+  for (int32_t g0 = 0; g0 < count;) {
+    const Core& c0 = plans[order[g0]]->core;
+    int32_t g1 = g0 + 1;
+    while (g1 < count && plans[order[g1]]->core.mode == c0.mode && plans[order[g1]]->core.p_log2 == c0.p_log2) ++g1;
+    TM_HIP(launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.finish_lds, s));
+    g0 = g1;
+  }
   pool.acc_dirty = false;
   if (!dev_out) {
     TM_HIP(hipMemcpyAsync(out, base + off_res, sizeof(tm_result) * (size_t)count, hipMemcpyDeviceToHost, s));

@@ -288,6 +288,26 @@ def match_batch(plans: Sequence[Plan], xs: Sequence, stream=None, out=None) -> O
     return [MatchResult(*_row(r)) for r in host]
 
 
+class Batch:
+    """A fixed list of (plan, signal) pairs whose pointer arrays are built once;
+    run() enqueues tm_match_batch with results in a device buffer."""
+
+    def __init__(self, plans: Sequence[Plan], xs: Sequence):
+        if len(plans) != len(xs):
+            raise ValueError("plans and xs differ in length")
+        for p, x in zip(plans, xs):
+            _check_signal(p, x)
+        self.plans, self.xs = list(plans), list(xs)
+        self.count = len(plans)
+        self._p = (ctypes.c_void_p * self.count)(*[p.handle.value for p in plans])
+        self._x = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in xs])
+
+    def run(self, out, stream=None):
+        """out: CUDA uint8 tensor of 48*count bytes (device results, no wait)."""
+        _check(lib().tm_match_batch(self.count, self._p, self._x, out.data_ptr(),
+                                    _stream_handle(stream)))
+
+
 def match_intermediates(plan: Plan, x, stream=None):
     """Match and return (result, y1, y2, r1, r2) with the intermediates as
     numpy float64 arrays."""
