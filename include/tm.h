@@ -106,6 +106,8 @@ typedef struct {
   int32_t exact;         /* 1 = exact (integer) path, 0 = real path */
   int32_t dual;          /* 1 = |M1 - M2| = 1: both folds from one read of x */
   int32_t fft_in_lds;    /* 1 = the whole FFT fits one workgroup's LDS */
+  int32_t fold_tiles;    /* workgroups of the tiled fold (0 when streamed) */
+  int32_t fold_segments; /* workgroups of the streaming int8 fold (0 when tiled) */
   int64_t workspace_bytes; /* device workspace one match of this plan uses */
   int64_t x_bytes;       /* bytes of x read per match */
 } tm_plan_info;
@@ -139,8 +141,9 @@ tm_status tm_plan_get_info(tm_plan plan, tm_plan_info* info);
 
 /*
  * tm_match -- one signal, Algorithm 1 steps 3 and 5-9.
- * x: device pointer to N elements of the plan's x_dtype, 4-byte aligned at
- *    least (16-byte aligned reads are used when possible).  Read only.
+ * x: device pointer to N elements of the plan's x_dtype, aligned to the
+ *    element size (any byte offset for int8).  Read only; the fold kernels
+ *    read the whole 16-byte aligned chunks that overlap x.
  * out: one tm_result in host or device memory.  With host memory the call
  *    waits for the stream; with device memory it only enqueues work and `out`
  *    is valid once the stream reaches this point.

@@ -44,6 +44,10 @@ struct alignas(16) Inst {
   int32_t nred;           // reduce (real folds) or prep (integer folds) workgroups
   int32_t red_tpe;        // reduce threads per fold entry (a power of two <= 256)
   int32_t acc_int;        // 1: integer fold accumulated with atomics into `yp`
+  int32_t sfold;          // 1: int8 signal folded by k_fold_s8 (biased bucket sums)
+  int32_t seg_base;       // first k_fold_s8 segment of this instance in the launch
+  int32_t nseg;           // k_fold_s8 segments of this instance
+  int32_t seg_chunks;     // 16-byte chunks per segment
   int64_t inv_a_mod_b;    // ma^{-1} mod mb
   // workspace (device)
   void* col_a;            // [va.nrb][ma] column partials
@@ -78,6 +82,22 @@ constexpr int kFoldLoads = 16;          // 16-byte chunks each fold thread stage
 constexpr int kFoldMaxCols = 512;       // tile columns W <= 512 (elements)
 constexpr int kFoldMaxRows = 256;       // tile rows R <= 256
 constexpr size_t kFoldLdsBudget = 60 * 1024;   // skewed tile bytes (two workgroups per CU)
+// streaming int8 fold (k_fold_s8)
+constexpr int kSegThreads = 256;
+constexpr int kSegHalf = 128;                       // threads per modulus
+constexpr int kSegPiece = 16384;                    // bytes per LDS ring piece
+constexpr int kSegPieceChunks = kSegPiece / 16;
+constexpr int kSegLoads = kSegPieceChunks / kSegThreads;
+constexpr int kSegSlots = 9;                        // words per lane per row
+constexpr int kSegMaxM = 4 * kSegHalf * kSegSlots;  // 4608
+constexpr int kSegMinM = 16;
+constexpr int kSegLook = 4640;                      // mirrored bytes: a row of kSegMaxM + 16
+constexpr int kSegLds = 2 * kSegPiece + kSegLook;
+constexpr int kSegZ = 4 * kSegHalf * kSegSlots;     // flush buckets per modulus
+constexpr int kSegMaxRows = 256;                    // rows of the shorter modulus per segment
+static_assert(2 * kSegZ * 4 <= kSegLds, "flush area must fit the ring");
+static_assert(kSegLook >= kSegMaxM + 16 && kSegLook % 16 == 0, "mirror must hold a row");
+
 constexpr int kReduceThreads = 256;
 constexpr int kFinishThreads = 512;
 
@@ -95,6 +115,7 @@ int fft_lds_max_log2(int mode);         // largest P (log2) whose FFT fits one w
 // Kernel launchers (tm_kernels.hip).
 hipError_t configure_kernels();        // raise dynamic LDS limits on the current device
 hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStream_t s);
+hipError_t launch_fold_s8(const InstTable& tab, int total_segs, hipStream_t s);
 hipError_t launch_reduce(const InstTable& tab, int total_chunks, hipStream_t s);
 hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, int mode,
                          size_t lds, hipStream_t s);

@@ -331,6 +331,227 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_
 }
 
 // --------------------------------------------------------------------------
+// streaming int8 fold (int8 signals, both moduli in [kSegMinM, kSegMaxM])
+// --------------------------------------------------------------------------
+//
+// One workgroup folds one segment of x: a run of 16-byte chunks, addressed
+// from x rounded down to 16 bytes (d = x mod 16 bytes sit before x[0]).
+// Chunks pass through a two-piece LDS ring whose first kSegLook bytes are
+// mirrored after it, so a row that starts in one piece is read whole.  Threads
+// 0..127 fold with modulus ma, threads 128..255 with mb.  Lane u owns buckets
+// 4u..4u+3 (plus 512 s for slot s): for each row it reads the two aligned
+// words that hold the row's bytes 4u..4u+3 and one v_perm per parity both
+// realigns them and spreads the even (odd) bytes into 16-bit lanes.  Bytes
+// enter LDS as x + 128 (bit 7 flipped; zero outside x) so the lane sums are
+// unsigned; the bias is removed when the literal folds are formed.  A segment
+// holds at most 256 rows of either modulus, so a 16-bit lane stays below
+// 256 * 255 < 2^16.  A row belongs to the segment holding its first byte.
+
+// bytes [lo, hi) of a 16-byte chunk kept, the rest cleared
+__device__ __forceinline__ uint4 keep_bytes(uint4 v, int lo, int hi) {
+  uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) m |= (4 * q + b >= lo && 4 * q + b < hi) ? (0xFFu << (8 * b)) : 0u;
+    w[q] &= m;
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+struct SegGeom {
+  uintptr_t xc;      // x rounded down to 16 bytes
+  int delta;         // x - xc
+  int64_t nch;       // chunks that hold bytes of x
+  int64_t c_begin;   // first chunk of the segment
+  int64_t c_end;     // one past its last chunk
+  int64_t c_stage;   // one past the last chunk staged (segment plus look-ahead)
+};
+
+__device__ __forceinline__ void seg_load(const SegGeom& g, int piece, uint4 (&v)[kSegLoads]) {
+#pragma unroll
+  for (int u = 0; u < kSegLoads; ++u) {
+    const int64_t c = g.c_begin + (int64_t)piece * kSegPieceChunks + threadIdx.x + u * kSegThreads;
+    const bool ok = c < g.c_stage && c < g.nch;
+    v[u] = gload16(g.xc + (ok ? (uintptr_t)c * 16 : 0));    // chunk 0 always holds x[0]
+  }
+}
+
+__device__ __forceinline__ void seg_store(const SegGeom& g, int64_t n, int piece, const uint4 (&v)[kSegLoads],
+                                          unsigned char* lds) {
+  const int half = piece & 1;
+#pragma unroll
+  for (int u = 0; u < kSegLoads; ++u) {
+    const int cl = threadIdx.x + u * kSegThreads;
+    const int64_t c = g.c_begin + (int64_t)piece * kSegPieceChunks + cl;
+    if (c >= g.c_stage) continue;
+    uint4 w = make_uint4(0, 0, 0, 0);
+    if (c < g.nch) {
+      w = make_uint4(v[u].x ^ 0x80808080u, v[u].y ^ 0x80808080u, v[u].z ^ 0x80808080u, v[u].w ^ 0x80808080u);
+      const int64_t b0 = c * 16;
+      if (b0 < g.delta || b0 + 16 > g.delta + n)
+        w = keep_bytes(w, (int)max((int64_t)0, g.delta - b0), (int)min((int64_t)16, g.delta + n - b0));
+    }
+    *reinterpret_cast<uint4*>(lds + half * kSegPiece + cl * 16) = w;
+    if (half == 0 && cl * 16 < kSegLook) *reinterpret_cast<uint4*>(lds + 2 * kSegPiece + cl * 16) = w;
+  }
+}
+
+// the two aligned words under bytes 4u..4u+3 of a row, for every slot
+template <int NSL>
+__device__ __forceinline__ void seg_read_row(const unsigned char* lds, int abase, int u0,
+                                             uint32_t (&w0)[NSL], uint32_t (&w1)[NSL]) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(lds + abase) + u0;
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    w0[s] = p[kSegHalf * s];
+    w1[s] = p[kSegHalf * s + 1];
+  }
+}
+
+template <int NSL>
+__device__ __forceinline__ void seg_accumulate(const uint32_t (&w0)[NSL], const uint32_t (&w1)[NSL],
+                                               uint32_t sel_even, uint32_t top_even, uint32_t top_odd,
+                                               uint32_t (&lo)[NSL], uint32_t (&hi)[NSL]) {
+  const uint32_t sel_odd = sel_even + 0x00010001u;
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    uint32_t e = __builtin_amdgcn_perm(w1[s], w0[s], sel_even);   // bytes c, c+2 of {w0, w1}
+    uint32_t o = __builtin_amdgcn_perm(w1[s], w0[s], sel_odd);    // bytes c+1, c+3
+    if (s == NSL - 1) { e &= top_even; o &= top_odd; }             // buckets past M
+    lo[s] += e;
+    hi[s] += o;
+  }
+}
+
+template <int NSL>
+__device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, unsigned char* lds) {
+  const int tid = threadIdx.x;
+  const int u0 = tid & (kSegHalf - 1);
+  const int64_t N = d.n;
+  SegGeom g;
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(d.x);
+  g.xc = xa & ~(uintptr_t)15;
+  g.delta = (int)(xa & 15);
+  g.nch = (N + g.delta + 15) >> 4;
+  g.c_begin = (int64_t)seg * d.seg_chunks;
+  g.c_end = min(g.nch, g.c_begin + d.seg_chunks);
+  const int64_t mmax = max(d.va.m, d.vb.m);
+  g.c_stage = g.c_end + (mmax + 16 + 15) / 16;
+  const int nproc = g.c_end > g.c_begin ? (int)((g.c_end - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks) : 0;
+  const int nstage = g.c_end > g.c_begin ? (int)((g.c_stage - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks) : 0;
+
+  // this half's modulus (wave-uniform); row k spans bytes [kM + d, (k+1)M + d) from xc
+  const int64_t M = half ? d.vb.m : d.va.m;
+  const int64_t L = (N + M - 1) / M;
+  const int64_t B0 = g.c_begin * 16, B1 = g.c_end * 16;
+  int64_t k = B0 > g.delta ? (B0 - g.delta + M - 1) / M : 0;
+  int64_t rb = k * M + g.delta;                 // first byte of row k
+  // top slot: bytes of buckets >= M are cleared
+  const int utop = u0 + kSegHalf * (NSL - 1);
+  const int nval = (int)max((int64_t)0, min((int64_t)4, M - 4 * (int64_t)utop));
+  const uint32_t topm = nval >= 4 ? 0xFFFFFFFFu : (1u << (8 * nval)) - 1u;
+  const uint32_t top_even = topm & 0x00FF00FFu, top_odd = (topm >> 8) & 0x00FF00FFu;
+
+  uint32_t lo[NSL], hi[NSL];
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) { lo[s] = 0; hi[s] = 0; }
+
+  uint4 v[kSegLoads];
+  if (nstage > 0) { seg_load(g, 0, v); seg_store(g, N, 0, v, lds); }
+  if (nstage > 1) { seg_load(g, 1, v); seg_store(g, N, 1, v, lds); }
+  if (nstage > 2) seg_load(g, 2, v);
+  __syncthreads();
+
+  for (int j = 0; j < nproc; ++j) {
+    const int64_t Bp = B0 + (int64_t)j * kSegPiece;
+    const int64_t Bend = min(Bp + kSegPiece, B1);
+    const int ring = (j & 1) * kSegPiece;              // LDS offset of byte b: ring + (b - Bp)
+    if (k < L && rb < Bend) {
+      uint32_t a0[NSL], a1[NSL], b0[NSL], b1[NSL];
+      int off = ring + (int)(rb - Bp);
+      seg_read_row<NSL>(lds, off & ~3, u0, a0, a1);
+      while (true) {
+        const uint32_t c = (uint32_t)off & 3u;
+        const uint32_t sel = 0x0C000C00u | c | ((c + 2u) << 16);
+        const int64_t k1 = k + 1, rb1 = rb + M;
+        const bool more = k1 < L && rb1 < Bend;
+        const int off1 = ring + (int)(rb1 - Bp);
+        if (more) seg_read_row<NSL>(lds, off1 & ~3, u0, b0, b1);
+        seg_accumulate<NSL>(a0, a1, sel, top_even, top_odd, lo, hi);
+        k = k1; rb = rb1; off = off1;
+        if (!more) break;
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) { a0[s] = b0[s]; a1[s] = b1[s]; }
+      }
+    }
+    __syncthreads();
+    if (j + 2 < nstage) {
+      seg_store(g, N, j + 2, v, lds);
+      if (j + 3 < nstage) seg_load(g, j + 3, v);
+    }
+    __syncthreads();
+  }
+
+  // flush: word u's lanes are buckets 4u..4u+3; transpose through LDS so the
+  // global atomics are coalesced
+  int* Z = reinterpret_cast<int*>(lds) + half * kSegZ;
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    const int u = u0 + kSegHalf * s;
+    *reinterpret_cast<uint4*>(Z + 4 * u) =
+        make_uint4(lo[s] & 0xFFFFu, hi[s] & 0xFFFFu, lo[s] >> 16, hi[s] >> 16);
+  }
+  __syncthreads();
+  int* yp = d.yp + (half ? d.va.m : 0);
+  for (int b = u0; b < M; b += kSegHalf) {
+    const int val = Z[b];
+    if (val) __hip_atomic_fetch_add(G(yp + b), val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ int find_inst_by_seg(const InstTable& tab, int seg) {
+  int lo = 0, hi = tab.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab.table[mid].seg_base <= seg) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// one instantiation per word count of a row (ceil(M / 512) slots per lane)
+__device__ __forceinline__ void fold_segment_any(const Inst& d, int seg, unsigned char* lds) {
+  const int half = __builtin_amdgcn_readfirstlane(threadIdx.x >> 7);
+  const int m = half ? d.vb.m : d.va.m;
+  switch ((m + 4 * kSegHalf - 1) / (4 * kSegHalf)) {
+    case 1: fold_segment<1>(d, seg, half, lds); break;
+    case 2: fold_segment<2>(d, seg, half, lds); break;
+    case 3: fold_segment<3>(d, seg, half, lds); break;
+    case 4: fold_segment<4>(d, seg, half, lds); break;
+    case 5: fold_segment<5>(d, seg, half, lds); break;
+    case 6: fold_segment<6>(d, seg, half, lds); break;
+    case 7: fold_segment<7>(d, seg, half, lds); break;
+    case 8: fold_segment<8>(d, seg, half, lds); break;
+    default: fold_segment<9>(d, seg, half, lds); break;
+  }
+}
+
+// The two halves of a workgroup may run different instantiations; each runs
+// the same sequence of barriers.
+__global__ void __launch_bounds__(kSegThreads) k_fold_s8(InstTable tab, int total_segs) {
+  __shared__ __align__(16) unsigned char lds[kSegLds];
+  const int seg = blockIdx.x;
+  if (seg >= total_segs) return;
+  if (tab.table) {
+    const Inst& d = tab.table[find_inst_by_seg(tab, seg)];
+    fold_segment_any(d, seg - d.seg_base, lds);
+  } else {
+    fold_segment_any(tab.one, seg, lds);
+  }
+}
+
+// --------------------------------------------------------------------------
 // real-valued folds: fixed-order reduction of the partials
 // --------------------------------------------------------------------------
 
@@ -378,7 +599,8 @@ __device__ __forceinline__ void prep_wg(const Inst& d, int lc) {
   const bool wrap = (int64_t)s + (L - 1) * M >= N;
   const bool ext = uu >= M;
   // every load issued before any use (addresses of unused terms point at x[0])
-  const int b = G(d.yp)[(f ? d.va.m : 0) + s];
+  int b = G(d.yp)[(f ? d.va.m : 0) + s];
+  if (d.sfold && s < N) b -= 128 * (int)((N - 1 - s) / M + 1);    // bucket sums of x + 128
   const int w = ld_int<Tin>(d.x, wrap ? mod_pos((int64_t)s + (L - 1) * M, N) : 0);
   const int e1 = ld_int<Tin>(d.x, ext ? mod_pos((int64_t)s + L * M, N) : 0);
   const int e0 = ld_int<Tin>(d.x, ext ? s : 0);
@@ -1029,6 +1251,12 @@ hipError_t configure_kernels() {
 hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStream_t s) {
   if (total_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fold, dim3(total_tiles), dim3(kFoldThreads), lds, s, tab, total_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_s8(const InstTable& tab, int total_segs, hipStream_t s) {
+  if (total_segs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_s8, dim3(total_segs), dim3(kSegThreads), 0, s, tab, total_segs);
   return hipGetLastError();
 }
 

@@ -103,6 +103,7 @@ struct Core {
   // workspace offsets (bytes) of one instance
   size_t off_col_a = 0, off_diag = 0, off_col_b = 0, off_y = 0, off_res = 0, ws_bytes = 0;
   int32_t ntiles = 0, nred = 0, red_tpe = 1, acc_int = 0;
+  int32_t sfold = 0, nseg = 0, seg_chunks = 0;   // streaming int8 fold
   size_t acc_bytes = 0;     // integer bucket zone (int32 [ma + mb]); lives in the zeroed pool
   size_t fold_lds = 0, finish_lds = 0;
   int fft_in_lds = 1;
@@ -169,6 +170,24 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   }
   c->ntiles = c->va.nrb * c->va.ncb + (c->dual ? 0 : c->vb.nrb * c->vb.ncb);
   c->acc_int = d->x_dtype == TM_I8 || c->mode == MODE_EXACT;
+  // int8 signals with both moduli in [kSegMinM, kSegMaxM]: streaming fold over
+  // segments of x.  A segment holds at most kSegMaxRows rows of the shorter
+  // modulus (16-bit lane sums; a row straddling the end adds one) and, by
+  // default, about N/512 bytes but at least 64 KiB, so a batch of many
+  // instances gets long segments and one large instance still spreads over
+  // many workgroups.
+  const int64_t mmin = std::min(c->ma, c->mb), mmax = std::max(c->ma, c->mb);
+  if (d->x_dtype == TM_I8 && mmin >= kSegMinM && mmax <= kSegMaxM && env_int("TM_FOLD_STREAM", 1) != 0) {
+    const int64_t cap = kSegMaxRows * mmin / 16;
+    int64_t sc = env_int("TM_SEG_BYTES", 0) / 16;
+    if (sc <= 0) sc = std::max<int64_t>(ceil_div(d->n, 512 * 16), 4096);
+    sc = std::max<int64_t>(1, std::min(sc, cap));
+    const int64_t nch = (d->n + 15) / 16 + 1;            // any alignment of x
+    c->sfold = 1;
+    c->seg_chunks = (int32_t)sc;
+    c->nseg = (int32_t)ceil_div(nch, sc);
+    c->ntiles = 0;
+  }
   const int64_t ytot = (int64_t)c->ma + c->k - 1 + c->mb + c->k - 1;
   size_t off = 0;
   if (c->acc_int) {
@@ -205,6 +224,8 @@ void fill_info(const Core& c, tm_plan_info* info) {
   info->exact = c.mode == MODE_EXACT;
   info->dual = c.dual;
   info->fft_in_lds = c.fft_in_lds;
+  info->fold_tiles = c.ntiles;
+  info->fold_segments = c.nseg;
   info->workspace_bytes = (int64_t)(c.ws_bytes + c.acc_bytes);
   info->x_bytes = c.n * dtype_bytes(c.x_dtype);
 }
@@ -241,15 +262,22 @@ hipError_t prof_event(hipEvent_t* e) {
   return hipEventCreate(e);
 }
 
-// launch_fold wrapped with the optional timing events
-hipError_t timed_fold(const InstTable& tab, int tiles, size_t lds, hipStream_t s) {
-  if (!g_prof_on) return launch_fold(tab, tiles, lds, s);
+// the fold kernels of one launch (tiles, then int8 segments), wrapped with the
+// optional timing events
+hipError_t folds(const InstTable& tab, int tiles, size_t lds, int segs, hipStream_t s) {
+  hipError_t e = launch_fold(tab, tiles, lds, s);
+  if (e != hipSuccess) return e;
+  return launch_fold_s8(tab, segs, s);
+}
+
+hipError_t timed_fold(const InstTable& tab, int tiles, size_t lds, int segs, hipStream_t s) {
+  if (!g_prof_on) return folds(tab, tiles, lds, segs, s);
   hipEvent_t a, b;
   hipError_t e = prof_event(&a);
   if (e != hipSuccess) return e;
   if ((e = prof_event(&b)) != hipSuccess) return e;
   if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
-  if ((e = launch_fold(tab, tiles, lds, s)) != hipSuccess) return e;
+  if ((e = folds(tab, tiles, lds, segs, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
   g_prof_live.emplace_back(a, b);
   return hipSuccess;
@@ -365,6 +393,9 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->nred = c.nred;
   in->red_tpe = c.red_tpe;
   in->acc_int = c.acc_int;
+  in->sfold = c.sfold;
+  in->nseg = c.nseg;
+  in->seg_chunks = c.seg_chunks;
   in->inv_a_mod_b = c.inv;
   in->t = p->t_dev;
   in->spec = p->spec;
@@ -562,13 +593,14 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   char* base = static_cast<char*>(pool.dev);
   place_workspace(p->core, base, static_cast<char*>(pool.acc), &tab.one);
   tab.one.tile_base = 0;
+  tab.one.seg_base = 0;
   tab.one.red_base = 0;
   tab.one.out = dev_out ? out : reinterpret_cast<tm_result*>(base + p->core.off_res);
   tab.one.dbg_y1 = y1;
   tab.one.dbg_y2 = y2;
   tab.one.dbg_r1 = r1;
   tab.one.dbg_r2 = r2;
-  TM_HIP(timed_fold(tab, p->core.ntiles, p->core.fold_lds, s));
+  TM_HIP(timed_fold(tab, p->core.ntiles, p->core.fold_lds, p->core.nseg, s));
   pool.acc_dirty = true;                 // until the finish kernel is enqueued
   TM_HIP(launch_reduce(tab, p->core.nred, s));
   TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.finish_lds, s));
@@ -606,7 +638,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   // layout: [instance workspaces][results if host out][table][lists]
   std::vector<size_t> ws_off(count), acc_off(count);
   size_t ws = 0, accb = 0;
-  int64_t tiles = 0, chunks = 0;
+  int64_t tiles = 0, chunks = 0, segs = 0;
   size_t fold_lds = 0;
   for (int32_t i = 0; i < count; ++i) {
     const Core& c = plans[i]->core;
@@ -615,10 +647,12 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     acc_off[i] = accb;
     accb += c.acc_bytes;
     tiles += c.ntiles;
+    segs += c.nseg;
     chunks += c.nred;
     fold_lds = std::max(fold_lds, c.fold_lds);
   }
-  if (tiles > 0x7fffffff || chunks > 0x7fffffff) return fail(TM_ERR_UNSUPPORTED, "batch too large");
+  if (tiles > 0x7fffffff || chunks > 0x7fffffff || segs > 0x7fffffff)
+    return fail(TM_ERR_UNSUPPORTED, "batch too large");
   // finish launches are grouped by (mode, FFT length) so each gets its own LDS size
   std::vector<int32_t> order(count);
   for (int32_t i = 0; i < count; ++i) order[i] = i;
@@ -646,7 +680,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   char* base = static_cast<char*>(pool.dev);
   Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
   int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + tab_bytes);
-  int32_t tile_base = 0, red_base = 0;
+  int32_t tile_base = 0, red_base = 0, seg_base = 0;
   for (int32_t i = 0; i < count; ++i) {
     const tm_plan_s* p = plans[i];
     Inst& in = host_tab[i];
@@ -654,7 +688,9 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     place_workspace(p->core, base + ws_off[i], static_cast<char*>(pool.acc) + acc_off[i], &in);
     in.tile_base = tile_base;
     in.red_base = red_base;
+    in.seg_base = seg_base;
     tile_base += p->core.ntiles;
+    seg_base += p->core.nseg;
     red_base += p->core.nred;
     in.out = dev_out ? out + i : reinterpret_cast<tm_result*>(base + off_res) + i;
     host_list[i] = order[i];
@@ -667,7 +703,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   tab.table = reinterpret_cast<const Inst*>(base + off_tab);
   tab.count = count;
   const int32_t* dlist = reinterpret_cast<const int32_t*>(base + off_lists);
-  TM_HIP(timed_fold(tab, (int)tiles, fold_lds, s));
+  TM_HIP(timed_fold(tab, (int)tiles, fold_lds, (int)segs, s));
   pool.acc_dirty = true;                 // until every finish kernel is enqueued
   TM_HIP(launch_reduce(tab, (int)chunks, s));
   for (int32_t g0 = 0; g0 < count;) {

@@ -22,9 +22,9 @@ def gpu_match(x, t, m1=0, m2=0, fold_mult=1, flags=0, fold_store=tm.TM_F32, x_de
     return res, y1, y2, r1, r2, plan
 
 
-def assert_exact_parity(x, t, m1=0, m2=0, fold_mult=1, flags=0, x_oracle=None, t_oracle=None):
+def assert_exact_parity(x, t, m1=0, m2=0, fold_mult=1, flags=0, x_oracle=None, t_oracle=None, x_dev=None):
     """Bit-exact comparison of every intermediate and output (integer data)."""
-    res, y1, y2, r1, r2, plan = gpu_match(x, t, m1, m2, fold_mult, flags)
+    res, y1, y2, r1, r2, plan = gpu_match(x, t, m1, m2, fold_mult, flags, x_dev=x_dev)
     xo = x if x_oracle is None else x_oracle
     to = t if t_oracle is None else t_oracle
     ref = O.ftm(xo, to, plan.m1, plan.m2)
