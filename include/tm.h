@@ -108,6 +108,8 @@ typedef struct {
   int32_t fft_in_lds;    /* 1 = the whole FFT fits one workgroup's LDS */
   int32_t fold_tiles;    /* workgroups of the tiled fold (0 when streamed) */
   int32_t fold_segments; /* workgroups of the streaming int8 fold (0 when tiled) */
+  int32_t fold_bands;    /* workgroups of the band fold of 4-byte signals */
+  int32_t reserved;
   int64_t workspace_bytes; /* device workspace one match of this plan uses */
   int64_t x_bytes;       /* bytes of x read per match */
 } tm_plan_info;

@@ -41,19 +41,23 @@ struct alignas(16) Inst {
   int32_t tile_base;      // first fold tile of this instance in the launch
   int32_t ntiles;         // fold tiles of this instance
   int32_t red_base;       // first reduce workgroup of this instance in the launch
-  int32_t nred;           // reduce (real folds) or prep (integer folds) workgroups
+  int32_t nred;           // reduce workgroups (real folds; 0 for integer folds)
   int32_t red_tpe;        // reduce threads per fold entry (a power of two <= 256)
   int32_t acc_int;        // 1: integer fold accumulated with atomics into `yp`
   int32_t sfold;          // 1: int8 signal folded by k_fold_s8 (biased bucket sums)
   int32_t seg_base;       // first k_fold_s8 segment of this instance in the launch
   int32_t nseg;           // k_fold_s8 segments of this instance
   int32_t seg_chunks;     // 16-byte chunks per segment
+  int32_t band;           // 1: 4-byte signal folded by k_fold_band (views of 64-column bands)
+  int32_t band_base;      // first k_fold_band workgroup of this instance in the launch
+  int32_t nband;          // k_fold_band workgroups of this instance
+  int32_t pad0;
   int64_t inv_a_mod_b;    // ma^{-1} mod mb
   // workspace (device)
   void* col_a;            // [va.nrb][ma] column partials
   void* diag;             // [va.nrb][va.ncb][va.cols + va.rows - 1] diagonal partials (dual)
   void* col_b;            // [vb.nrb][mb] column partials (!dual)
-  void* y;                // literal folds (float path): [ma + k - 1] then [mb + k - 1]
+  void* y;                // literal folds (real path): [ma + k - 1] then [mb + k - 1]
   int* yp;                // partition folds (integer path): [ma] then [mb]; all zero
                           // between launches (the finish kernel clears what it read)
   // plan (device)
@@ -98,8 +102,15 @@ constexpr int kSegMaxRows = 256;                    // rows of the shorter modul
 static_assert(2 * kSegZ * 4 <= kSegLds, "flush area must fit the ring");
 static_assert(kSegLook >= kSegMaxM + 16 && kSegLook % 16 == 0, "mirror must hold a row");
 
+// band fold of 4-byte signals (k_fold_band)
+constexpr int kBandCols = 64;                       // columns per band: one per lane
+constexpr int kBandWaves = 4;                       // bands (tasks) per workgroup
+constexpr int kBandRowsMax = 256;                   // rows per task
+constexpr int kBandUnroll = 16;                     // rows whose loads are in flight together
+
 constexpr int kReduceThreads = 256;
-constexpr int kFinishThreads = 512;
+constexpr int kFinishThreads = 512;     // largest finish workgroup (P / 16 threads)
+constexpr int kFftMid = 5;              // stages of the FFT's twiddle-free middle pass
 
 // 16-byte chunks that cover one tile row of `cols` elements at any alignment
 inline __host__ __device__ int fold_chunks(int cols, int eb) { return (cols * eb + 15) / 16 + 1; }
@@ -111,13 +122,15 @@ inline int dtype_bytes(int dt) { return dt == TM_I8 ? 1 : (dt == TM_F32 ? 4 : 2)
 size_t fold_lds_bytes(const View& v, int x_dtype);
 size_t finish_lds_bytes(int p_log2, int mode);
 int fft_lds_max_log2(int mode);         // largest P (log2) whose FFT fits one workgroup
+int finish_threads(int p_log2);         // finish workgroup size for FFT length 2^p_log2
 
 // Kernel launchers (tm_kernels.hip).
 hipError_t configure_kernels();        // raise dynamic LDS limits on the current device
 hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStream_t s);
 hipError_t launch_fold_s8(const InstTable& tab, int total_segs, hipStream_t s);
+hipError_t launch_fold_band(const InstTable& tab, int total_wgs, hipStream_t s);
 hipError_t launch_reduce(const InstTable& tab, int total_chunks, hipStream_t s);
-hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, int mode,
+hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, int mode, int p_log2,
                          size_t lds, hipStream_t s);
 hipError_t launch_twiddles(void* tw, int p_log2, int as_double, hipStream_t s);
 hipError_t launch_spectrum(const void* t, int t_dtype, int k, int p_log2, const double* tw64,

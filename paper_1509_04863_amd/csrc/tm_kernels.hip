@@ -552,6 +552,115 @@ __global__ void __launch_bounds__(kSegThreads) k_fold_s8(InstTable tab, int tota
 }
 
 // --------------------------------------------------------------------------
+// band fold (4-byte signals)
+// --------------------------------------------------------------------------
+//
+// One wave folds a band of 64 columns over R rows of view A (of view B too when
+// the moduli are not consecutive).  Lane j reads column c0 + j of every row (a
+// coalesced 256-byte row), adds it to its column sum in a register and to
+// diagonal e = j - r + R - 1 (row r of the band) of a per-wave LDS array with an
+// LDS atomic.  Within a row the lanes hit distinct diagonals and a diagonal
+// receives its rows in order, so float sums are deterministic.  Diagonal e
+// holds the elements of bucket (c0 + e - (R-1) - r0) mod M2 (element (i, c) of
+// view A is x[i M1 + c], which is c - i mod M2 when M2 = M1 + 1): the layout of
+// the tiled fold's partials, which the real path reduces in a fixed order.
+
+template <typename Acc>
+__device__ __forceinline__ void band_task(const Inst& d, int task, Acc* dg) {
+  const int lane = threadIdx.x & 63;
+  const int nta = d.va.nrb * d.va.ncb;
+  const bool in_a = task < nta;
+  const View v = in_a ? d.va : d.vb;
+  if (!in_a) task -= nta;
+  const bool want_diag = in_a && d.dual;
+  const int rb = task / v.ncb, cb = task - rb * v.ncb;
+  const int R = v.rows;
+  const int64_t M = v.m, N = d.n;
+  const int64_t r0 = (int64_t)rb * R;
+  const int Reff = (int)min((int64_t)R, (int64_t)v.l - r0);
+  const int c0 = cb * kBandCols;
+  const int c = c0 + lane;
+  const bool colok = c < M;
+  const int S = R + kBandCols - 1;
+  if (want_diag)
+    for (int e = lane; e < S; e += 64) dg[e] = (Acc)0;
+  Acc ca = (Acc)0;
+  const GAS float* x = G(reinterpret_cast<const float*>(d.x));
+  const int64_t nbase = r0 * M + c;
+  for (int r = 0; r < Reff; r += kBandUnroll) {
+    float xv[kBandUnroll];
+#pragma unroll
+    for (int u = 0; u < kBandUnroll; ++u) {
+      const int64_t n = nbase + (int64_t)(r + u) * M;
+      const bool ok = r + u < Reff && colok && n < N;
+      xv[u] = x[ok ? n : 0];
+      if (!ok) xv[u] = 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kBandUnroll; ++u) {
+      if (r + u < Reff) {
+        const Acc a = AccOf<Acc>::from(xv[u]);
+        ca += a;
+        if (want_diag)
+          __hip_atomic_fetch_add(dg + (lane - (r + u) + R - 1), a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      }
+    }
+  }
+  if constexpr (AccOf<Acc>::kInt) {   // integer: exact, order-independent atomics
+    int* yp = d.yp + (in_a ? 0 : d.va.m);
+    if (colok && ca) __hip_atomic_fetch_add(G(yp + c), (int)ca, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (want_diag) {
+      const int64_t mb = d.vb.m;
+      for (int e = lane; e < S; e += 64) {
+        const int val = (int)dg[e];
+        if (!val) continue;
+        int64_t b = ((int64_t)c0 + e - (R - 1) - r0) % mb;
+        if (b < 0) b += mb;
+        __hip_atomic_fetch_add(G(d.yp + d.va.m + b), val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  } else {
+    Acc* colp = reinterpret_cast<Acc*>(in_a ? d.col_a : d.col_b);
+    if (colok) G(colp)[(int64_t)rb * M + c] = ca;
+    if (want_diag) {
+      Acc* dp = reinterpret_cast<Acc*>(d.diag) + (int64_t)(rb * v.ncb + cb) * S;
+      for (int e = lane; e < S; e += 64) G(dp)[e] = dg[e];
+    }
+  }
+}
+
+__device__ __forceinline__ int find_inst_by_band(const InstTable& tab, int wg) {
+  int lo = 0, hi = tab.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab.table[mid].band_base <= wg) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void band_dispatch(const Inst& d, int wg, unsigned char* lds) {
+  const int wave = threadIdx.x >> 6;
+  const int task = wg * kBandWaves + wave;
+  const int ntasks = d.va.nrb * d.va.ncb + (d.dual ? 0 : d.vb.nrb * d.vb.ncb);
+  if (task >= ntasks) return;
+  const size_t per = (size_t)(kBandRowsMax + kBandCols) * 4;
+  if (d.acc_int) band_task<int>(d, task, reinterpret_cast<int*>(lds + wave * per));
+  else band_task<float>(d, task, reinterpret_cast<float*>(lds + wave * per));
+}
+
+__global__ void __launch_bounds__(64 * kBandWaves) k_fold_band(InstTable tab, int total_wgs) {
+  __shared__ __align__(16) unsigned char lds[kBandWaves * (kBandRowsMax + kBandCols) * 4];
+  const int wg = blockIdx.x;
+  if (wg >= total_wgs) return;
+  if (tab.table) {
+    const Inst& d = tab.table[find_inst_by_band(tab, wg)];
+    band_dispatch(d, wg - d.band_base, lds);
+  } else {
+    band_dispatch(tab.one, wg, lds);
+  }
+}
+
+// --------------------------------------------------------------------------
 // real-valued folds: fixed-order reduction of the partials
 // --------------------------------------------------------------------------
 
@@ -578,44 +687,6 @@ __device__ __forceinline__ float bucket_part(const Inst& d, int f, int s, int rb
 // Threads of a workgroup are split into groups of red_tpe lanes, one group per
 // fold entry; lane t sums row blocks t, t + tpe, ... and lane 0 adds the lanes
 // in order, then the cyclic wrap terms.
-// --------------------------------------------------------------------------
-// integer folds: literal folds from the partition buckets
-// --------------------------------------------------------------------------
-
-// y[u] for fold f: y[s] = yp[s] + wrapped last term (Section 2: indices mod N),
-// y[M + s] = y[s] - x[s] + x[(s + L M) mod N].  One thread per entry.
-template <typename Tin>
-__device__ __forceinline__ void prep_wg(const Inst& d, int lc) {
-  const int totA = d.va.m + d.k - 1;
-  const int tot = totA + d.vb.m + d.k - 1;
-  const int u = lc * kReduceThreads + threadIdx.x;
-  if (u >= tot) return;
-  const int f = u >= totA;
-  const int uu = f ? u - totA : u;
-  const int64_t M = f ? d.vb.m : d.va.m;
-  const int64_t L = f ? d.vb.l : d.va.l;
-  const int64_t N = d.n;
-  const int s = uu < M ? uu : (int)(uu - M);
-  const bool wrap = (int64_t)s + (L - 1) * M >= N;
-  const bool ext = uu >= M;
-  // every load issued before any use (addresses of unused terms point at x[0])
-  int b = G(d.yp)[(f ? d.va.m : 0) + s];
-  if (d.sfold && s < N) b -= 128 * (int)((N - 1 - s) / M + 1);    // bucket sums of x + 128
-  const int w = ld_int<Tin>(d.x, wrap ? mod_pos((int64_t)s + (L - 1) * M, N) : 0);
-  const int e1 = ld_int<Tin>(d.x, ext ? mod_pos((int64_t)s + L * M, N) : 0);
-  const int e0 = ld_int<Tin>(d.x, ext ? s : 0);
-  G(reinterpret_cast<int*>(d.y))[u] = b + (wrap ? w : 0) + (ext ? e1 - e0 : 0);
-}
-
-__device__ __forceinline__ void prep_dispatch(const Inst& d, int lc) {
-  switch (d.x_dtype) {
-    case TM_I8: prep_wg<int8_t>(d, lc); break;
-    case TM_F32: prep_wg<float>(d, lc); break;
-    case TM_BF16: prep_wg<bf16_t>(d, lc); break;
-    default: prep_wg<f16_t>(d, lc); break;
-  }
-}
-
 __device__ __forceinline__ void reduce_wg(const Inst& d, int lc, float* part) {
   const int tpe = d.red_tpe;
   const int epw = kReduceThreads / tpe;
@@ -646,22 +717,20 @@ __device__ __forceinline__ void reduce_wg(const Inst& d, int lc, float* part) {
   }
 }
 
-// Literal folds for every instance of a launch: integer folds from their
-// buckets (one thread per entry); real folds from their partials, with the
-// threads of a workgroup split into groups of red_tpe lanes, one group per fold
-// entry (lane t sums row blocks t, t + tpe, ...; lane 0 adds the lanes in
-// order, then the cyclic wrap terms).
+// Literal real-valued folds for every real instance of a launch (integer
+// folds are formed by the finish kernel from their buckets): the threads of a
+// workgroup are split into groups of red_tpe lanes, one group per fold entry
+// (lane t sums row blocks t, t + tpe, ...; lane 0 adds the lanes in order,
+// then the cyclic wrap terms).
 __global__ void __launch_bounds__(kReduceThreads) k_reduce(InstTable tab, int total_wgs) {
   __shared__ float part[kReduceThreads];
   const int wg = blockIdx.x;
   if (wg >= total_wgs) return;
   if (tab.table) {
     const Inst& d = tab.table[find_inst_by_red(tab, wg)];
-    if (d.acc_int) prep_dispatch(d, wg - d.red_base);
-    else reduce_wg(d, wg - d.red_base, part);
+    reduce_wg(d, wg - d.red_base, part);
   } else {
-    if (tab.one.acc_int) prep_dispatch(tab.one, wg);
-    else reduce_wg(tab.one, wg, part);
+    reduce_wg(tab.one, wg, part);
   }
 }
 
@@ -767,6 +836,21 @@ __host__ __device__ __forceinline__ int padded_len(int P) { return P + (P >> 4) 
 
 int fft_lds_max_log2(int mode) { return mode == MODE_EXACT ? 13 : 14; }
 
+// Threads of a finish workgroup: one radix-16 group of every pass per thread.
+int finish_threads(int p_log2) {
+  const int t = (1 << p_log2) >> 4;
+  return t < 64 ? 64 : (t > kFinishThreads ? kFinishThreads : t);
+}
+
+// The middle pass takes contiguous groups of 2^mid elements, mid = min(p,
+// kFftMid); element m of group g of the spectrum is stored at m * (P >> mid) + g
+// so that the pass's spectrum loads are coalesced across threads.
+__host__ __device__ __forceinline__ int spec_slot(int i, int p) {
+  const int mid = p < kFftMid ? p : kFftMid;
+  const int g = i >> mid, m = i & ((1 << mid) - 1);
+  return (m << (p - mid)) + g;
+}
+
 size_t finish_lds_bytes(int p_log2, int mode) {
   const size_t el = mode == MODE_EXACT ? 16 : 8;
   return (size_t)padded_len(1 << p_log2) * el + (size_t)kFinishThreads * 16;
@@ -842,9 +926,13 @@ __device__ void fft_pass(cplx<T>* buf, int p, int s0, const cplx<T>* __restrict_
       }
       dft_dit<KB>(v);
     } else {
+      // spectrum loads first: their latency overlaps the LDS reads and the DFT
+      cplx<T> sp[RR];
+#pragma unroll
+      for (int m = 0; m < RR; ++m) sp[m] = ldc(spec, (m << (p - KB)) + g);
       dft_dif<KB>(v);
 #pragma unroll
-      for (int m = 0; m < RR; ++m) v[m] = cmul(v[m], ldc(spec, base + (m << lh)));
+      for (int m = 0; m < RR; ++m) v[m] = cmul(v[m], sp[m]);
       dft_dit<KB>(v);
     }
 #pragma unroll
@@ -855,7 +943,7 @@ __device__ void fft_pass(cplx<T>* buf, int p, int s0, const cplx<T>* __restrict_
 // Twiddled passes stop at radix 16 (a twiddled radix-32 pass with its twiddle
 // table would not fit the register file); the twiddle-free middle pass may be
 // radix 32.
-template <typename T> struct FftLimits { static constexpr int kTw = 4; static constexpr int kMid = 5; };
+template <typename T> struct FftLimits { static constexpr int kTw = 4; static constexpr int kMid = kFftMid; };
 
 template <int DIR, typename T>
 __device__ __forceinline__ void fft_pass_kb(int kb, cplx<T>* buf, int p, int s0, const cplx<T>* tw,
@@ -1000,6 +1088,66 @@ __device__ __forceinline__ double score_any_t(const Inst& d, int64_t c, void* sc
   }
 }
 
+// Literal folds from the partition buckets (Algorithm 1 step 3 with Section 2's
+// indices mod N), with rho = N - (L-1) M the length of the last row:
+//   y[s]     = yP[s] + [s >= rho] x[s - rho]                  (s < M)
+//   y[M + s] = y[s] - x[s] + x[(s + L M) mod N]              (s < K - 1)
+// Pass 1 copies the buckets (less 128 per counted element for the streaming
+// int8 fold, whose buckets hold sums of x + 128); pass 2 adds the x terms, one
+// thread per s, so no entry is written twice.
+__device__ __forceinline__ int64_t mod_small(int64_t v, int64_t n, bool general) {
+  if (general) return v % n;                  // only when N < M (single-row folds)
+  return v >= n ? v - n : v;                  // v < 2N whenever N >= M
+}
+
+template <typename Tin, typename T>
+__device__ __forceinline__ void lit_fix(const Inst& d, cplx<T>* buf, int M, int rho, int K, bool im, bool general) {
+  const int64_t N = d.n;
+  const int lo2 = max(rho, K - 1);     // [0, K-1) carries extension terms; [lo2, M) only wraps
+  const int nwork = (K - 1) + max(0, M - lo2);
+  for (int t = threadIdx.x; t < nwork; t += blockDim.x) {
+    const int s = t < K - 1 ? t : lo2 + (t - (K - 1));
+    const bool wrap = s >= rho && s < M;
+    const int xw = wrap ? ld_int<Tin>(d.x, mod_small((int64_t)(s - rho), N, general)) : 0;
+    if (s < K - 1) {
+      const int e1 = ld_int<Tin>(d.x, mod_small((int64_t)s + M - rho, N, general));
+      const int e0 = ld_int<Tin>(d.x, s);
+      const T add = (T)(xw + e1 - e0);
+      cplx<T>& z = buf[padi(M + s)];
+      if (im) z.y += add; else z.x += add;
+    }
+    if (wrap) {
+      cplx<T>& z = buf[padi(s)];
+      if (im) z.y += (T)xw; else z.x += (T)xw;
+    }
+  }
+}
+
+// argmax of both folds (lowest index on ties) and the sum of |z|^2, one pass
+struct FinRed { double va; double vb; double ss; int ia; int ib; };
+
+__device__ __forceinline__ void finred_merge(FinRed& a, const FinRed& o) {
+  if (vi_better(VI{o.va, o.ia}, VI{a.va, a.ia})) { a.va = o.va; a.ia = o.ia; }
+  if (vi_better(VI{o.vb, o.ib}, VI{a.vb, a.ib})) { a.vb = o.vb; a.ib = o.ib; }
+  a.ss += o.ss;
+}
+
+__device__ FinRed block_finred(FinRed mine, FinRed* scratch) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const FinRed o{__shfl_xor(mine.va, m), __shfl_xor(mine.vb, m), __shfl_xor(mine.ss, m),
+                   __shfl_xor(mine.ia, m), __shfl_xor(mine.ib, m)};
+    finred_merge(mine, o);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) scratch[wave] = mine;
+  __syncthreads();
+  FinRed r = scratch[0];
+  for (int w = 1; w < nw; ++w) finred_merge(r, scratch[w]);
+  __syncthreads();
+  return r;
+}
+
 template <typename T, typename Tin>
 __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* lds) {
   const int tid = threadIdx.x;
@@ -1016,71 +1164,104 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
   double* dyb = d.swapped ? d.dbg_y1 : d.dbg_y2;
   double* dra = d.swapped ? d.dbg_r2 : d.dbg_r1;
   double* drb = d.swapped ? d.dbg_r1 : d.dbg_r2;
-  double znorm2 = 0.0;
+  double ss = 0.0;
 
   // literal folds (Algorithm 1 step 3) packed as z = yA + i yB, zero padded
-  // to P.  Thread tid owns entries n = tid + v*NT (coalesced) and issues all
-  // their loads before the first use.
+  // to P; thread tid owns n = tid + v NT, 16 entries' loads in flight at once
   {
-    constexpr int VMAX = (1 << 14) / kFinishThreads;
+    constexpr int CH = 16;
     const int V = (P + NT - 1) / NT;
-    const GAS int* yi = G(reinterpret_cast<const int*>(d.y));
+    const int64_t N = d.n;
+    const int64_t La = d.va.l, Lb = d.vb.l;
+    const int rhoA = (int)(N - (La - 1) * ma), rhoB = (int)(N - (Lb - 1) * mb);
     const GAS float* yf = G(reinterpret_cast<const float*>(d.y));
-    float ra[VMAX], rb[VMAX];
+    const GAS int* yp = G(d.yp);
+    const int biasA = d.sfold ? 128 * (int)(La - 1) : 0, biasB = d.sfold ? 128 * (int)(Lb - 1) : 0;
+    const int bias1 = d.sfold ? 128 : 0;
+    for (int v0 = 0; v0 < V; v0 += CH) {
+      T re[CH], im[CH];
+      if (ints) {
+        int ia[CH], ib[CH];
 #pragma unroll
-    for (int v = 0; v < VMAX; ++v) {
-      const int n = tid + v * NT;
-      const bool in = v < V && n < P;
-      const int ia = in && n < na ? n : 0, ib = in && n < nb ? na + n : 0;
-      if (ints) { ra[v] = __int_as_float(yi[ia]); rb[v] = __int_as_float(yi[ib]); }
-      else { ra[v] = yf[ia]; rb[v] = yf[ib]; }
-    }
-    double ss = 0.0;
+        for (int v = 0; v < CH; ++v) {
+          const int n = tid + (v0 + v) * NT;
+          const int sa = n < ma ? n : n - ma, sb = n < mb ? n : n - mb;
+          ia[v] = yp[n < na ? sa : 0];
+          ib[v] = yp[ma + (n < nb ? sb : 0)];
+        }
 #pragma unroll
-    for (int v = 0; v < VMAX; ++v) {
-      const int n = tid + v * NT;
-      if (v < V && n < P) {
-        T re = 0, im = 0;
-        if (n < na) {
-          const float a = ints ? (float)__float_as_int(ra[v]) : ra[v];
-          re = exact ? (T)__float_as_int(ra[v]) : store_round<T>(a, d.fold_store);
-          if (dya) G(dya)[n] = (double)re;
+        for (int v = 0; v < CH; ++v) {
+          const int n = tid + (v0 + v) * NT;
+          const int sa = n < ma ? n : n - ma, sb = n < mb ? n : n - mb;
+          re[v] = n < na && n < P ? (T)(ia[v] - biasA - (sa < rhoA ? bias1 : 0)) : (T)0;
+          im[v] = n < nb && n < P ? (T)(ib[v] - biasB - (sb < rhoB ? bias1 : 0)) : (T)0;
         }
-        if (n < nb) {
-          const float b = ints ? (float)__float_as_int(rb[v]) : rb[v];
-          im = exact ? (T)__float_as_int(rb[v]) : store_round<T>(b, d.fold_store);
-          if (dyb) G(dyb)[n] = (double)im;
+      } else {
+        float fa[CH], fb[CH];
+#pragma unroll
+        for (int v = 0; v < CH; ++v) {
+          const int n = tid + (v0 + v) * NT;
+          fa[v] = yf[n < na && n < P ? n : 0];
+          fb[v] = yf[n < nb && n < P ? na + n : 0];
         }
-        ss += (double)re * (double)re + (double)im * (double)im;
-        buf[padi(n)] = cplx<T>{re, im};
+#pragma unroll
+        for (int v = 0; v < CH; ++v) {
+          const int n = tid + (v0 + v) * NT;
+          re[v] = n < na ? store_round<T>(fa[v], d.fold_store) : (T)0;
+          im[v] = n < nb ? store_round<T>(fb[v], d.fold_store) : (T)0;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < CH; ++v) {
+        const int n = tid + (v0 + v) * NT;
+        if (v0 + v < V && n < P) buf[padi(n)] = cplx<T>{re[v], im[v]};
       }
     }
-    znorm2 = block_sum<double>(ss, (double*)scratch);   // includes barriers
-    if (ints)   // the buckets were consumed by k_reduce: back to zero for the next launch
+    __syncthreads();
+    if (ints) {
+      // every bucket has been read: back to zero for the next launch
       for (int s = tid; s < ma + mb; s += NT) G(d.yp)[s] = 0;
+      const bool general = N < (int64_t)max(ma, mb);
+      lit_fix<Tin, T>(d, buf, ma, rhoA, K, false, general);
+      __syncthreads();
+      lit_fix<Tin, T>(d, buf, mb, rhoB, K, true, general);
+      __syncthreads();
+    }
+    // storage rounding (real path), |z|^2 and the optional intermediates
+    for (int n = tid; n < P; n += NT) {
+      cplx<T> z = buf[padi(n)];
+      if (ints && !exact) {
+        z.x = store_round<T>((float)z.x, d.fold_store);
+        z.y = store_round<T>((float)z.y, d.fold_store);
+        buf[padi(n)] = z;
+      }
+      if (dya && n < na) G(dya)[n] = (double)z.x;
+      if (dyb && n < nb) G(dyb)[n] = (double)z.y;
+      ss += (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+    }
+    __syncthreads();
   }
 
   fft_correlate<T>(buf, p, reinterpret_cast<const cplx<T>*>(d.tw), reinterpret_cast<const cplx<T>*>(d.spec));
 
   // step 7: argmax over [0, M) of each fold, lowest index on ties
-  VI ba{-INFINITY, 0x7fffffff}, bb{-INFINITY, 0x7fffffff};
-#pragma unroll 8
+  FinRed fr{-INFINITY, -INFINITY, ss, 0x7fffffff, 0x7fffffff};
+#pragma unroll 4
   for (int n = tid; n < ma; n += NT) {
     const double v = exact ? rint((double)buf[padi(n)].x) : (double)buf[padi(n)].x;
     if (dra) G(dra)[n] = v;
-    const VI c{v, n};
-    if (vi_better(c, ba)) ba = c;
+    if (vi_better(VI{v, n}, VI{fr.va, fr.ia})) { fr.va = v; fr.ia = n; }
   }
-#pragma unroll 8
+#pragma unroll 4
   for (int n = tid; n < mb; n += NT) {
     const double v = exact ? rint((double)buf[padi(n)].y) : (double)buf[padi(n)].y;
     if (drb) G(drb)[n] = v;
-    const VI c{v, n};
-    if (vi_better(c, bb)) bb = c;
+    if (vi_better(VI{v, n}, VI{fr.vb, fr.ib})) { fr.vb = v; fr.ib = n; }
   }
+  const FinRed red = block_finred(fr, reinterpret_cast<FinRed*>(scratch));
+  const VI amax{red.va, red.ia}, bmax{red.vb, red.ib};
+  const double znorm2 = red.ss;
   VI* vs = reinterpret_cast<VI*>(scratch);
-  const VI amax = block_argmax(ba, vs);
-  const VI bmax = block_argmax(bb, vs);
 
   uint32_t flags = 0;
   if (!exact) {
@@ -1222,8 +1403,9 @@ __global__ void __launch_bounds__(1024) k_spectrum(const void* t, int t_dtype, i
   const double inv = 1.0 / (double)P;
   for (int n = tid; n < P; n += NT) {
     const double2 v = z[n];
-    if (as_double) reinterpret_cast<double2*>(spec)[n] = make_double2(v.x * inv, -v.y * inv);
-    else reinterpret_cast<float2*>(spec)[n] = make_float2((float)(v.x * inv), (float)(-v.y * inv));
+    const int slot = spec_slot(n, p);
+    if (as_double) reinterpret_cast<double2*>(spec)[slot] = make_double2(v.x * inv, -v.y * inv);
+    else reinterpret_cast<float2*>(spec)[slot] = make_float2((float)(v.x * inv), (float)(-v.y * inv));
   }
 }
 
@@ -1254,6 +1436,12 @@ hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStr
   return hipGetLastError();
 }
 
+hipError_t launch_fold_band(const InstTable& tab, int total_wgs, hipStream_t s) {
+  if (total_wgs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_band, dim3(total_wgs), dim3(64 * kBandWaves), 0, s, tab, total_wgs);
+  return hipGetLastError();
+}
+
 hipError_t launch_fold_s8(const InstTable& tab, int total_segs, hipStream_t s) {
   if (total_segs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fold_s8, dim3(total_segs), dim3(kSegThreads), 0, s, tab, total_segs);
@@ -1266,13 +1454,14 @@ hipError_t launch_reduce(const InstTable& tab, int total_wgs, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, int mode, size_t lds,
-                         hipStream_t s) {
+hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, int mode, int p_log2,
+                         size_t lds, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  const int nt = finish_threads(p_log2);
   if (mode == MODE_EXACT)
-    hipLaunchKernelGGL(k_finish<double>, dim3(count), dim3(kFinishThreads), lds, s, tab, list, count);
+    hipLaunchKernelGGL(k_finish<double>, dim3(count), dim3(nt), lds, s, tab, list, count);
   else
-    hipLaunchKernelGGL(k_finish<float>, dim3(count), dim3(kFinishThreads), lds, s, tab, list, count);
+    hipLaunchKernelGGL(k_finish<float>, dim3(count), dim3(nt), lds, s, tab, list, count);
   return hipGetLastError();
 }
 

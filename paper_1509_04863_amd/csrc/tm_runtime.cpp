@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
@@ -92,6 +93,23 @@ View make_view(int64_t n, int64_t m, int eb) {
   return v;
 }
 
+// Band view of a 4-byte signal: 64-column bands of R rows, R a multiple of
+// kBandUnroll chosen for about 2048 tasks (TM_BAND_ROWS overrides).
+View make_band_view(int64_t n, int64_t m) {
+  View v{};
+  v.m = (int32_t)m;
+  v.l = (int32_t)ceil_div(n, m);
+  v.cols = kBandCols;
+  v.ncb = (int32_t)ceil_div(m, kBandCols);
+  int64_t r = env_int("TM_BAND_ROWS", 0);
+  if (r <= 0) r = ceil_div((int64_t)v.l * v.ncb, 2048);
+  r = ceil_div(std::max<int64_t>(r, 1), kBandUnroll) * kBandUnroll;
+  r = std::min<int64_t>(r, kBandRowsMax);
+  v.rows = (int32_t)r;
+  v.nrb = (int32_t)ceil_div(v.l, r);
+  return v;
+}
+
 // Plan parameters derived from the descriptor; pure host arithmetic.
 struct Core {
   int64_t n = 0;
@@ -104,6 +122,7 @@ struct Core {
   size_t off_col_a = 0, off_diag = 0, off_col_b = 0, off_y = 0, off_res = 0, ws_bytes = 0;
   int32_t ntiles = 0, nred = 0, red_tpe = 1, acc_int = 0;
   int32_t sfold = 0, nseg = 0, seg_chunks = 0;   // streaming int8 fold
+  int32_t band = 0, nband = 0;                    // band fold of 4-byte signals
   size_t acc_bytes = 0;     // integer bucket zone (int32 [ma + mb]); lives in the zeroed pool
   size_t fold_lds = 0, finish_lds = 0;
   int fft_in_lds = 1;
@@ -160,15 +179,26 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   c->fft_in_lds = p <= fft_lds_max_log2(c->mode);
 
   const int eb = dtype_bytes(d->x_dtype);
-  c->va = make_view(d->n, c->ma, eb);
+  // 4-byte signals: band fold (views of 64-column bands, R rows per task);
+  // everything else that the streaming int8 fold below does not take: tiles
+  c->band = d->x_dtype == TM_F32 && env_int("TM_FOLD_BAND", 1) != 0;
+  auto view_of = [&](int64_t m) { return c->band ? make_band_view(d->n, m) : make_view(d->n, m, eb); };
+  c->va = view_of(c->ma);
   if (c->dual) {
     c->vb = View{};
     c->vb.m = c->mb;
     c->vb.l = (int32_t)ceil_div(d->n, c->mb);
   } else {
-    c->vb = make_view(d->n, c->mb, eb);
+    c->vb = view_of(c->mb);
   }
-  c->ntiles = c->va.nrb * c->va.ncb + (c->dual ? 0 : c->vb.nrb * c->vb.ncb);
+  const int64_t nviews = (int64_t)c->va.nrb * c->va.ncb + (c->dual ? 0 : (int64_t)c->vb.nrb * c->vb.ncb);
+  if (nviews > (int64_t(1) << 30)) return fail(TM_ERR_UNSUPPORTED, "signal too large for one launch");
+  if (c->band) {
+    c->nband = (int32_t)ceil_div(nviews, kBandWaves);
+    c->ntiles = 0;
+  } else {
+    c->ntiles = (int32_t)nviews;
+  }
   c->acc_int = d->x_dtype == TM_I8 || c->mode == MODE_EXACT;
   // int8 signals with both moduli in [kSegMinM, kSegMaxM]: streaming fold over
   // segments of x.  A segment holds at most kSegMaxRows rows of the shorter
@@ -177,7 +207,8 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   // instances gets long segments and one large instance still spreads over
   // many workgroups.
   const int64_t mmin = std::min(c->ma, c->mb), mmax = std::max(c->ma, c->mb);
-  if (d->x_dtype == TM_I8 && mmin >= kSegMinM && mmax <= kSegMaxM && env_int("TM_FOLD_STREAM", 1) != 0) {
+  if (d->x_dtype == TM_I8 && mmin >= kSegMinM && mmax <= kSegMaxM && ceil_div(d->n, mmin) < (1 << 23) &&
+      env_int("TM_FOLD_STREAM", 1) != 0) {
     const int64_t cap = kSegMaxRows * mmin / 16;
     int64_t sc = env_int("TM_SEG_BYTES", 0) / 16;
     if (sc <= 0) sc = std::max<int64_t>(ceil_div(d->n, 512 * 16), 4096);
@@ -188,13 +219,15 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
     c->nseg = (int32_t)ceil_div(nch, sc);
     c->ntiles = 0;
   }
+  if (d->x_dtype == TM_I8 && ceil_div(d->n, std::min(c->ma, c->mb)) > (int64_t(1) << 24))
+    return fail(TM_ERR_UNSUPPORTED, "int8 folds of more than 2^24 rows would overflow int32 buckets");
   const int64_t ytot = (int64_t)c->ma + c->k - 1 + c->mb + c->k - 1;
   size_t off = 0;
   if (c->acc_int) {
-    // integer folds go straight to the bucket zone; k_reduce writes the literal folds
+    // integer folds go straight to the bucket zone; the finish kernel forms
+    // the literal folds from it
     c->acc_bytes = align256((size_t)(c->ma + c->mb) * 4);
-    c->nred = (int32_t)ceil_div(ytot, kReduceThreads);
-    c->off_y = off; off = align256(off + (size_t)ytot * 4);
+    c->nred = 0;
   } else {
     const int nrb = std::max(c->va.nrb, c->dual ? 0 : c->vb.nrb);
     int tpe = 1;
@@ -226,6 +259,7 @@ void fill_info(const Core& c, tm_plan_info* info) {
   info->fft_in_lds = c.fft_in_lds;
   info->fold_tiles = c.ntiles;
   info->fold_segments = c.nseg;
+  info->fold_bands = c.nband;
   info->workspace_bytes = (int64_t)(c.ws_bytes + c.acc_bytes);
   info->x_bytes = c.n * dtype_bytes(c.x_dtype);
 }
@@ -262,27 +296,53 @@ hipError_t prof_event(hipEvent_t* e) {
   return hipEventCreate(e);
 }
 
-// the fold kernels of one launch (tiles, then int8 segments), wrapped with the
-// optional timing events
-hipError_t folds(const InstTable& tab, int tiles, size_t lds, int segs, hipStream_t s) {
-  hipError_t e = launch_fold(tab, tiles, lds, s);
+// the fold kernels of one launch (tiles, int8 segments, 4-byte bands), wrapped
+// with the optional timing events
+struct FoldWork { int tiles = 0; size_t lds = 0; int segs = 0; int bands = 0; };
+
+hipError_t folds(const InstTable& tab, const FoldWork& w, hipStream_t s) {
+  hipError_t e = launch_fold(tab, w.tiles, w.lds, s);
   if (e != hipSuccess) return e;
-  return launch_fold_s8(tab, segs, s);
+  if ((e = launch_fold_s8(tab, w.segs, s)) != hipSuccess) return e;
+  return launch_fold_band(tab, w.bands, s);
 }
 
-hipError_t timed_fold(const InstTable& tab, int tiles, size_t lds, int segs, hipStream_t s) {
-  if (!g_prof_on) return folds(tab, tiles, lds, segs, s);
+hipError_t timed_fold(const InstTable& tab, const FoldWork& w, hipStream_t s) {
+  if (!g_prof_on) return folds(tab, w, s);
   hipEvent_t a, b;
   hipError_t e = prof_event(&a);
   if (e != hipSuccess) return e;
   if ((e = prof_event(&b)) != hipSuccess) return e;
   if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
-  if ((e = folds(tab, tiles, lds, segs, s)) != hipSuccess) return e;
+  if ((e = folds(tab, w, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
   g_prof_live.emplace_back(a, b);
   return hipSuccess;
 }
 bool g_configured[64] = {};
+
+// FP64 twiddles exp(-2 pi i e / P), e < P/2, stored FP64 or FP32: one table per
+// (device, P, storage), shared by every plan and kept until the process ends.
+std::mutex g_tw_mu;
+std::map<std::tuple<int, int, int>, void*> g_twiddles;
+
+tm_status shared_twiddles(int dev, int p_log2, int as_double, hipStream_t s, void** out) {
+  std::lock_guard<std::mutex> lock(g_tw_mu);
+  auto it = g_twiddles.find({dev, p_log2, as_double});
+  if (it != g_twiddles.end()) { *out = it->second; return TM_OK; }
+  void* tw = nullptr;
+  const size_t half = std::max<size_t>((size_t(1) << p_log2) / 2, 1);
+  TM_HIP(hipMalloc(&tw, half * (as_double ? 16 : 8)));
+  hipError_t e = launch_twiddles(tw, p_log2, as_double, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(tw);
+    return fail(TM_ERR_DEVICE, std::string("twiddles: ") + hipGetErrorString(e));
+  }
+  g_twiddles[{dev, p_log2, as_double}] = tw;
+  *out = tw;
+  return TM_OK;
+}
 
 tm_status ensure_device(StreamPool& p, size_t need, hipStream_t s) {
   if (p.cap >= need) return TM_OK;
@@ -357,7 +417,7 @@ struct tm_plan_s {
   Core core;
   int device = 0;
   void* t_dev = nullptr;
-  void* tw64 = nullptr;
+  void* tw64 = nullptr;      // shared twiddle tables (not owned)
   void* tw32 = nullptr;
   void* spec = nullptr;
   double tnorm1 = 0.0;
@@ -396,6 +456,8 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->sfold = c.sfold;
   in->nseg = c.nseg;
   in->seg_chunks = c.seg_chunks;
+  in->band = c.band;
+  in->nband = c.nband;
   in->inv_a_mod_b = c.inv;
   in->t = p->t_dev;
   in->spec = p->spec;
@@ -520,8 +582,6 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
   auto cleanup = [&]() {
     if (z) (void)hipFree(z);
     if (p->t_dev) (void)hipFree(p->t_dev);
-    if (p->tw64) (void)hipFree(p->tw64);
-    if (p->tw32) (void)hipFree(p->tw32);
     if (p->spec) (void)hipFree(p->spec);
     delete p;
   };
@@ -536,11 +596,11 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
   } while (0)
   TM_HIP_PLAN(hipMalloc(&p->t_dev, std::max<size_t>(tb, 16)));
   TM_HIP_PLAN(hipMemcpyAsync(p->t_dev, th.data(), tb, hipMemcpyHostToDevice, s));
-  TM_HIP_PLAN(hipMalloc(&p->tw64, std::max<size_t>(P / 2, 1) * 16));
-  TM_HIP_PLAN(launch_twiddles(p->tw64, c.p_log2, 1, s));
-  if (c.mode == MODE_REAL) {
-    TM_HIP_PLAN(hipMalloc(&p->tw32, std::max<size_t>(P / 2, 1) * 8));
-    TM_HIP_PLAN(launch_twiddles(p->tw32, c.p_log2, 0, s));
+  st = shared_twiddles(dev, c.p_log2, 1, s, &p->tw64);
+  if (st == TM_OK && c.mode == MODE_REAL) st = shared_twiddles(dev, c.p_log2, 0, s, &p->tw32);
+  if (st != TM_OK) {
+    cleanup();
+    return st;
   }
   TM_HIP_PLAN(hipMalloc(&p->spec, P * (c.mode == MODE_EXACT ? 16 : 8)));
   TM_HIP_PLAN(hipMalloc(&z, P * 16));
@@ -558,8 +618,6 @@ tm_status tm_plan_destroy(tm_plan p) {
   if (!p) return TM_OK;
   TM_HIP(hipDeviceSynchronize());
   if (p->t_dev) TM_HIP(hipFree(p->t_dev));
-  if (p->tw64) TM_HIP(hipFree(p->tw64));
-  if (p->tw32) TM_HIP(hipFree(p->tw32));
   if (p->spec) TM_HIP(hipFree(p->spec));
   delete p;
   return TM_OK;
@@ -594,16 +652,22 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   place_workspace(p->core, base, static_cast<char*>(pool.acc), &tab.one);
   tab.one.tile_base = 0;
   tab.one.seg_base = 0;
+  tab.one.band_base = 0;
   tab.one.red_base = 0;
   tab.one.out = dev_out ? out : reinterpret_cast<tm_result*>(base + p->core.off_res);
   tab.one.dbg_y1 = y1;
   tab.one.dbg_y2 = y2;
   tab.one.dbg_r1 = r1;
   tab.one.dbg_r2 = r2;
-  TM_HIP(timed_fold(tab, p->core.ntiles, p->core.fold_lds, p->core.nseg, s));
+  FoldWork fw;
+  fw.tiles = p->core.ntiles;
+  fw.lds = p->core.fold_lds;
+  fw.segs = p->core.nseg;
+  fw.bands = p->core.nband;
+  TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;                 // until the finish kernel is enqueued
   TM_HIP(launch_reduce(tab, p->core.nred, s));
-  TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.finish_lds, s));
+  TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2, p->core.finish_lds, s));
   pool.acc_dirty = false;
   if (!dev_out) {
     TM_HIP(hipMemcpyAsync(out, tab.one.out, sizeof(tm_result), hipMemcpyDeviceToHost, s));
@@ -638,7 +702,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   // layout: [instance workspaces][results if host out][table][lists]
   std::vector<size_t> ws_off(count), acc_off(count);
   size_t ws = 0, accb = 0;
-  int64_t tiles = 0, chunks = 0, segs = 0;
+  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0;
   size_t fold_lds = 0;
   for (int32_t i = 0; i < count; ++i) {
     const Core& c = plans[i]->core;
@@ -648,10 +712,11 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     accb += c.acc_bytes;
     tiles += c.ntiles;
     segs += c.nseg;
+    bands += c.nband;
     chunks += c.nred;
     fold_lds = std::max(fold_lds, c.fold_lds);
   }
-  if (tiles > 0x7fffffff || chunks > 0x7fffffff || segs > 0x7fffffff)
+  if (tiles > 0x7fffffff || chunks > 0x7fffffff || segs > 0x7fffffff || bands > 0x7fffffff)
     return fail(TM_ERR_UNSUPPORTED, "batch too large");
   // finish launches are grouped by (mode, FFT length) so each gets its own LDS size
   std::vector<int32_t> order(count);
@@ -680,7 +745,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   char* base = static_cast<char*>(pool.dev);
   Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
   int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + tab_bytes);
-  int32_t tile_base = 0, red_base = 0, seg_base = 0;
+  int32_t tile_base = 0, red_base = 0, seg_base = 0, band_base = 0;
   for (int32_t i = 0; i < count; ++i) {
     const tm_plan_s* p = plans[i];
     Inst& in = host_tab[i];
@@ -689,8 +754,10 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     in.tile_base = tile_base;
     in.red_base = red_base;
     in.seg_base = seg_base;
+    in.band_base = band_base;
     tile_base += p->core.ntiles;
     seg_base += p->core.nseg;
+    band_base += p->core.nband;
     red_base += p->core.nred;
     in.out = dev_out ? out + i : reinterpret_cast<tm_result*>(base + off_res) + i;
     host_list[i] = order[i];
@@ -703,14 +770,19 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   tab.table = reinterpret_cast<const Inst*>(base + off_tab);
   tab.count = count;
   const int32_t* dlist = reinterpret_cast<const int32_t*>(base + off_lists);
-  TM_HIP(timed_fold(tab, (int)tiles, fold_lds, (int)segs, s));
+  FoldWork fw;
+  fw.tiles = (int)tiles;
+  fw.lds = fold_lds;
+  fw.segs = (int)segs;
+  fw.bands = (int)bands;
+  TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;                 // until every finish kernel is enqueued
   TM_HIP(launch_reduce(tab, (int)chunks, s));
   for (int32_t g0 = 0; g0 < count;) {
     const Core& c0 = plans[order[g0]]->core;
     int32_t g1 = g0 + 1;
     while (g1 < count && plans[order[g1]]->core.mode == c0.mode && plans[order[g1]]->core.p_log2 == c0.p_log2) ++g1;
-    TM_HIP(launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.finish_lds, s));
+    TM_HIP(launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.p_log2, c0.finish_lds, s));
     g0 = g1;
   }
   pool.acc_dirty = false;
