@@ -105,11 +105,13 @@ typedef struct {
   int32_t fft_log2;      /* P = 2^fft_log2 >= max(M1, M2) + K - 1 */
   int32_t exact;         /* 1 = exact (integer) path, 0 = real path */
   int32_t dual;          /* 1 = |M1 - M2| = 1: both folds from one read of x */
-  int32_t fft_in_lds;    /* 1 = the whole FFT fits one workgroup's LDS */
+  int32_t fft_in_lds;    /* 1 = the whole FFT fits one workgroup's LDS (P <= 2^13
+                            on the exact path, 2^14 on the real path) */
   int32_t fold_tiles;    /* workgroups of the tiled fold (0 when streamed) */
   int32_t fold_segments; /* workgroups of the streaming int8 fold (0 when tiled) */
   int32_t fold_bands;    /* workgroups of the band fold of 4-byte signals */
-  int32_t reserved;
+  int32_t fft_global;    /* 1 = P above one workgroup's LDS: four-step FFT through
+                            global memory (P up to 2^21) */
   int64_t workspace_bytes; /* device workspace one match of this plan uses */
   int64_t x_bytes;       /* bytes of x read per match */
 } tm_plan_info;

@@ -51,7 +51,14 @@ struct alignas(16) Inst {
   int32_t band;           // 1: 4-byte signal folded by k_fold_band (views of 64-column bands)
   int32_t band_base;      // first k_fold_band workgroup of this instance in the launch
   int32_t nband;          // k_fold_band workgroups of this instance
-  int32_t pad0;
+  int32_t gfft;           // 1: FFT correlation through global memory (P above one workgroup's LDS)
+  int32_t g_q;            // P = P1 x P2 with P1 = 2^g_q (column transforms), P2 = 2^(p_log2 - g_q)
+  int32_t g_logb;         // columns per column workgroup: 2^g_logb
+  void* gz;               // P complex working values (T of the mode)
+  double* gss;            // |z|^2 partials, one per literal-fold workgroup
+  void* gpart;            // argmax partials, one per column workgroup
+  const void* tw_cols;    // twiddles for 2^(g_logb + g_q)
+  const void* tw_rows;    // twiddles for P2
   int64_t inv_a_mod_b;    // ma^{-1} mod mb
   // workspace (device)
   void* col_a;            // [va.nrb][ma] column partials
@@ -108,6 +115,11 @@ constexpr int kBandWaves = 4;                       // bands (tasks) per workgro
 constexpr int kBandRowsMax = 256;                   // rows per task
 constexpr int kBandUnroll = 16;                     // rows whose loads are in flight together
 
+// FFT through global memory (k_gfft_*)
+constexpr int kGfftThreads = 256;                   // literal-fold and final workgroups
+constexpr int kGfftMaxLog2 = 21;                    // P up to 2^21 (rows of <= 4096)
+constexpr int kGfftMaxQ = 9;                        // column transforms of <= 512
+
 constexpr int kReduceThreads = 256;
 constexpr int kFinishThreads = 512;     // largest finish workgroup (P / 16 threads)
 constexpr int kFftMid = 5;              // stages of the FFT's twiddle-free middle pass
@@ -134,6 +146,8 @@ hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, i
                          size_t lds, hipStream_t s);
 hipError_t launch_twiddles(void* tw, int p_log2, int as_double, hipStream_t s);
 hipError_t launch_spectrum(const void* t, int t_dtype, int k, int p_log2, const double* tw64,
-                           double* scratch, void* spec, int as_double, hipStream_t s);
+                           double* scratch, void* spec, int as_double, int row_log2, hipStream_t s);
+size_t gfft_part_bytes();
+hipError_t launch_gfft(const Inst& one, hipStream_t s);   // literal folds .. result, one instance
 
 }  // namespace tmi

@@ -19,6 +19,8 @@
 //   k_twiddles FP64 twiddles exp(-2 pi i e / P) (stored FP64 or FP32).
 //   k_spectrum plan-time FP64 spectrum of the zero-padded template.
 
+#include <algorithm>
+
 #include <hip/hip_fp16.h>
 
 #include "tm_internal.h"
@@ -1100,25 +1102,54 @@ __device__ __forceinline__ int64_t mod_small(int64_t v, int64_t n, bool general)
   return v >= n ? v - n : v;                  // v < 2N whenever N >= M
 }
 
+// Pass 2 for both folds at once (fold A writes the real parts, fold B the
+// imaginary parts, so no element half is written by two threads).
 template <typename Tin, typename T>
-__device__ __forceinline__ void lit_fix(const Inst& d, cplx<T>* buf, int M, int rho, int K, bool im, bool general) {
+__device__ __forceinline__ void lit_fix(const Inst& d, cplx<T>* buf, int ma, int rhoA, int mb, int rhoB, int K,
+                                        bool general) {
+  constexpr int U = 8;                 // work items whose loads are in flight together
   const int64_t N = d.n;
-  const int lo2 = max(rho, K - 1);     // [0, K-1) carries extension terms; [lo2, M) only wraps
-  const int nwork = (K - 1) + max(0, M - lo2);
-  for (int t = threadIdx.x; t < nwork; t += blockDim.x) {
-    const int s = t < K - 1 ? t : lo2 + (t - (K - 1));
-    const bool wrap = s >= rho && s < M;
-    const int xw = wrap ? ld_int<Tin>(d.x, mod_small((int64_t)(s - rho), N, general)) : 0;
-    if (s < K - 1) {
-      const int e1 = ld_int<Tin>(d.x, mod_small((int64_t)s + M - rho, N, general));
-      const int e0 = ld_int<Tin>(d.x, s);
-      const T add = (T)(xw + e1 - e0);
-      cplx<T>& z = buf[padi(M + s)];
-      if (im) z.y += add; else z.x += add;
+  const int loA = max(rhoA, K - 1), loB = max(rhoB, K - 1);   // [0, K-1) extension, [lo, M) wrap only
+  const int nA = (K - 1) + max(0, ma - loA), nB = (K - 1) + max(0, mb - loB);
+  const int NT = blockDim.x;
+  for (int t0 = threadIdx.x; t0 < nA + nB; t0 += U * NT) {
+    int s[U], xw[U], e1[U], e0[U];
+    bool fb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int t = t0 + u * NT;
+      const bool ok = t < nA + nB;
+      fb[u] = t >= nA;
+      if (fb[u]) t -= nA;
+      const int M = fb[u] ? mb : ma, rho = fb[u] ? rhoB : rhoA, lo = fb[u] ? loB : loA;
+      s[u] = t < K - 1 ? t : lo + (t - (K - 1));
+      const bool wrap = ok && s[u] >= rho && s[u] < M;
+      const bool ext = ok && s[u] < K - 1;
+      xw[u] = ld_int<Tin>(d.x, wrap ? mod_small((int64_t)(s[u] - rho), N, general) : 0);
+      e1[u] = ld_int<Tin>(d.x, ext ? mod_small((int64_t)s[u] + M - rho, N, general) : 0);
+      e0[u] = ld_int<Tin>(d.x, ext ? s[u] : 0);
+      if (!wrap) xw[u] = 0;
+      if (!ext) { e1[u] = 0; e0[u] = 0; }
+      if (!ok) s[u] = -1;
     }
-    if (wrap) {
-      cplx<T>& z = buf[padi(s)];
-      if (im) z.y += (T)xw; else z.x += (T)xw;
+    // the targets of different items never coincide: read them all, then write
+    T* ze[U];
+    T* zw[U];
+    T ve[U], vw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int M = fb[u] ? mb : ma;
+      const int half = fb[u] ? 1 : 0;
+      const bool ext = s[u] >= 0 && s[u] < K - 1, wrap = s[u] >= 0 && xw[u] != 0;
+      ze[u] = ext ? reinterpret_cast<T*>(&buf[padi(M + s[u])]) + half : nullptr;
+      zw[u] = wrap ? reinterpret_cast<T*>(&buf[padi(s[u])]) + half : nullptr;
+      ve[u] = ext ? *ze[u] : (T)0;
+      vw[u] = wrap ? *zw[u] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ze[u]) *ze[u] = ve[u] + (T)(xw[u] + e1[u] - e0[u]);
+      if (zw[u]) *zw[u] = vw[u] + (T)xw[u];
     }
   }
 }
@@ -1132,20 +1163,102 @@ __device__ __forceinline__ void finred_merge(FinRed& a, const FinRed& o) {
   a.ss += o.ss;
 }
 
+// One DPP step of the wave reduction: lanes in the enabled rows merge the
+// value DPP brings them; lanes of disabled rows receive the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void finred_dpp(FinRed& r) {
+  auto mv = [](int ident, int v) { return __builtin_amdgcn_update_dpp(ident, v, CTRL, ROWS, 0xF, false); };
+  auto mvd = [&](double ident, double v) {
+    const int lo = mv(__double2loint(ident), __double2loint(v));
+    const int hi = mv(__double2hiint(ident), __double2hiint(v));
+    return __hiloint2double(hi, lo);
+  };
+  FinRed o;
+  o.va = mvd(-INFINITY, r.va);
+  o.vb = mvd(-INFINITY, r.vb);
+  o.ss = mvd(0.0, r.ss);
+  o.ia = mv(0x7fffffff, r.ia);
+  o.ib = mv(0x7fffffff, r.ib);
+  finred_merge(r, o);
+}
+
+// wave reduction by DPP (the full result lands in lane 63), then the waves'
+// results in wave order through LDS
 __device__ FinRed block_finred(FinRed mine, FinRed* scratch) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) {
-    const FinRed o{__shfl_xor(mine.va, m), __shfl_xor(mine.vb, m), __shfl_xor(mine.ss, m),
-                   __shfl_xor(mine.ia, m), __shfl_xor(mine.ib, m)};
-    finred_merge(mine, o);
-  }
+  finred_dpp<0xB1, 0xF>(mine);    // quad_perm [1,0,3,2]
+  finred_dpp<0x4E, 0xF>(mine);    // quad_perm [2,3,0,1]
+  finred_dpp<0x141, 0xF>(mine);   // row_half_mirror
+  finred_dpp<0x140, 0xF>(mine);   // row_mirror: every lane holds its row's result
+  finred_dpp<0x142, 0xA>(mine);   // row_bcast:15 into rows 1 and 3
+  finred_dpp<0x143, 0xC>(mine);   // row_bcast:31 into rows 2 and 3: lane 63 holds the wave
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) scratch[wave] = mine;
+  if (lane == 63) scratch[wave] = mine;
   __syncthreads();
   FinRed r = scratch[0];
   for (int w = 1; w < nw; ++w) finred_merge(r, scratch[w]);
   __syncthreads();
   return r;
+}
+
+// Steps 8-9 (Theorem 4): S_A(a) cap S_B(b) with the candidate sets taken mod
+// N, re-scoring of several candidates by (Tx)_c, and the result record.
+template <typename Tin>
+__device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
+  const int tid = threadIdx.x;
+  const int ma = d.va.m, mb = d.vb.m;
+  __shared__ long long cand[4];
+  __shared__ int ncand;
+  if (tid == 0) {
+    const int64_t N = d.n;
+    const int64_t A = ma, B = mb, La = d.va.l, Lb = d.vb.l;
+    const int64_t a = amax.i, b = bmax.i;
+    long long c0 = -1, c1 = -1, c2 = -1;   // ascending, -1 = unused
+    auto insert = [&](long long v) {
+      if (v == c0 || v == c1 || v == c2) return;
+      if (c0 < 0 || v < c0) { c2 = c1; c1 = c0; c0 = v; }
+      else if (c1 < 0 || v < c1) { c2 = c1; c1 = v; }
+      else c2 = v;
+    };
+    // regular members {a + iA < N} and {b + jB < N}: Chinese remaindering
+    if (a < N && b < N) {
+      const int64_t t = ((((b - a) % B) + B) % B) * d.inv_a_mod_b % B;
+      const int64_t v = a + A * t;
+      if (v < N) insert(v);
+    }
+    // the wrapped members (a + (La-1) A) mod N and (b + (Lb-1) B) mod N
+    const bool wa = a + (La - 1) * A >= N;
+    const bool wb = b + (Lb - 1) * B >= N;
+    const int64_t va = (a + (La - 1) * A) % N;
+    const int64_t vb = (b + (Lb - 1) * B) % N;
+    if (wa && ((b < N && va % B == b) || (wb && va == vb))) insert(va);
+    if (wb && (a < N && vb % A == a)) insert(vb);
+    int w = 0;
+    if (c0 >= 0) cand[w++] = c0;
+    if (c1 >= 0) cand[w++] = c1;
+    if (c2 >= 0) cand[w++] = c2;
+    ncand = w;
+  }
+  __syncthreads();
+  const int nc = ncand;
+  int64_t best = -1;
+  double best_score = 0.0;
+  for (int i = 0; i < nc; ++i) {
+    const double sc = score_any_t<Tin>(d, cand[i], scratch);
+    if (i == 0 || sc > best_score) { best = cand[i]; best_score = sc; }
+  }
+  if (nc == 0) flags |= TM_R_NOMATCH;
+  if (nc > 1) flags |= TM_R_RESCORED;
+  if (tid == 0) {
+    GAS tm_result* r = G(d.out);
+    r->shift = best;
+    r->m1_tilde = d.swapped ? bmax.i : amax.i;
+    r->m2_tilde = d.swapped ? amax.i : bmax.i;
+    r->n_candidates = nc;
+    r->flags = flags;
+    r->peak1 = d.swapped ? bmax.v : amax.v;
+    r->peak2 = d.swapped ? amax.v : bmax.v;
+    r->score = nc ? best_score : 0.0;
+  }
 }
 
 template <typename T, typename Tin>
@@ -1165,6 +1278,31 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
   double* dra = d.swapped ? d.dbg_r2 : d.dbg_r1;
   double* drb = d.swapped ? d.dbg_r1 : d.dbg_r2;
   double ss = 0.0;
+
+  // Touch one word of every 128-byte line of the twiddle and spectrum tables
+  // now, so that the FFT passes find them in L2; the words are consumed (as
+  // an empty asm operand) only after the FFT.
+  uint32_t touch[5] = {0, 0, 0, 0, 0};
+  {
+    const int tw_lines = (int)(((size_t)(P / 2) * sizeof(cplx<T>) + 127) / 128);
+    const int sp_lines = (int)(((size_t)P * sizeof(cplx<T>) + 127) / 128);
+    const GAS uint32_t* tw32 = G(reinterpret_cast<const uint32_t*>(d.tw));
+    const GAS uint32_t* sp32 = G(reinterpret_cast<const uint32_t*>(d.spec));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {     // 3 lines per thread when NT = P / 16
+      const int i = tid + u * NT;
+      const int j = i < tw_lines + sp_lines ? i : 0;
+      touch[u] = j < tw_lines ? tw32[j * 32] : sp32[(j - tw_lines) * 32];
+    }
+    // and the head of x, which the literal folds' wrap and extension terms read
+    if (ints) {
+      const int64_t head = min(d.n * (int64_t)sizeof(Tin), (int64_t)(max(d.va.m, d.vb.m) + d.k) * (int64_t)sizeof(Tin));
+      const GAS unsigned char* xb = G(reinterpret_cast<const unsigned char*>(d.x));
+      const int hl = (int)((head + 127) / 128);
+      const int i = tid < hl ? tid : 0;
+      touch[4] = xb[min((int64_t)i * 128, head - 1)];
+    }
+  }
 
   // literal folds (Algorithm 1 step 3) packed as z = yA + i yB, zero padded
   // to P; thread tid owns n = tid + v NT, 16 entries' loads in flight at once
@@ -1222,9 +1360,7 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
       // every bucket has been read: back to zero for the next launch
       for (int s = tid; s < ma + mb; s += NT) G(d.yp)[s] = 0;
       const bool general = N < (int64_t)max(ma, mb);
-      lit_fix<Tin, T>(d, buf, ma, rhoA, K, false, general);
-      __syncthreads();
-      lit_fix<Tin, T>(d, buf, mb, rhoB, K, true, general);
+      lit_fix<Tin, T>(d, buf, ma, rhoA, mb, rhoB, K, general);
       __syncthreads();
     }
     // storage rounding (real path), |z|^2 and the optional intermediates
@@ -1243,6 +1379,7 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
   }
 
   fft_correlate<T>(buf, p, reinterpret_cast<const cplx<T>*>(d.tw), reinterpret_cast<const cplx<T>*>(d.spec));
+  asm volatile("" : : "v"(touch[0]), "v"(touch[1]), "v"(touch[2]), "v"(touch[3]), "v"(touch[4]));
 
   // step 7: argmax over [0, M) of each fold, lowest index on ties
   FinRed fr{-INFINITY, -INFINITY, ss, 0x7fffffff, 0x7fffffff};
@@ -1289,60 +1426,7 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
     if (bound < 0.5) flags |= TM_R_EXACT;
   }
 
-  // steps 8-9: S_A(a) cap S_B(b) with the candidate sets taken mod N
-  __shared__ long long cand[4];
-  __shared__ int ncand;
-  if (tid == 0) {
-    const int64_t N = d.n;
-    const int64_t A = ma, B = mb, La = d.va.l, Lb = d.vb.l;
-    const int64_t a = amax.i, b = bmax.i;
-    long long c0 = -1, c1 = -1, c2 = -1;   // ascending, -1 = unused
-    auto insert = [&](long long v) {
-      if (v == c0 || v == c1 || v == c2) return;
-      if (c0 < 0 || v < c0) { c2 = c1; c1 = c0; c0 = v; }
-      else if (c1 < 0 || v < c1) { c2 = c1; c1 = v; }
-      else c2 = v;
-    };
-    // regular members {a + iA < N} and {b + jB < N}: Chinese remaindering
-    if (a < N && b < N) {
-      const int64_t t = ((((b - a) % B) + B) % B) * d.inv_a_mod_b % B;
-      const int64_t v = a + A * t;
-      if (v < N) insert(v);
-    }
-    // the wrapped members (a + (La-1) A) mod N and (b + (Lb-1) B) mod N
-    const bool wa = a + (La - 1) * A >= N;
-    const bool wb = b + (Lb - 1) * B >= N;
-    const int64_t va = (a + (La - 1) * A) % N;
-    const int64_t vb = (b + (Lb - 1) * B) % N;
-    if (wa && ((b < N && va % B == b) || (wb && va == vb))) insert(va);
-    if (wb && (a < N && vb % A == a)) insert(vb);
-    int w = 0;
-    if (c0 >= 0) cand[w++] = c0;
-    if (c1 >= 0) cand[w++] = c1;
-    if (c2 >= 0) cand[w++] = c2;
-    ncand = w;
-  }
-  __syncthreads();
-  const int nc = ncand;
-  int64_t best = -1;
-  double best_score = 0.0;
-  for (int i = 0; i < nc; ++i) {
-    const double sc = score_any_t<Tin>(d, cand[i], scratch);
-    if (i == 0 || sc > best_score) { best = cand[i]; best_score = sc; }
-  }
-  if (nc == 0) flags |= TM_R_NOMATCH;
-  if (nc > 1) flags |= TM_R_RESCORED;
-  if (tid == 0) {
-    GAS tm_result* r = G(d.out);
-    r->shift = best;
-    r->m1_tilde = d.swapped ? bmax.i : amax.i;
-    r->m2_tilde = d.swapped ? amax.i : bmax.i;
-    r->n_candidates = nc;
-    r->flags = flags;
-    r->peak1 = d.swapped ? bmax.v : amax.v;
-    r->peak2 = d.swapped ? amax.v : bmax.v;
-    r->score = nc ? best_score : 0.0;
-  }
+  resolve_and_report<Tin>(d, amax, bmax, flags, scratch);
 }
 
 template <typename T>
@@ -1365,6 +1449,308 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish(InstTable tab, const 
 }
 
 // --------------------------------------------------------------------------
+// FFT correlation through global memory (P above one workgroup's LDS)
+// --------------------------------------------------------------------------
+//
+// Four-step transform, P = P1 P2, n = n1 P2 + n2, k = k1 + P1 k2:
+//   cols:  length-P1 DIF transforms of the columns (in blocks of B adjacent
+//          columns, so rows are read as coalesced segments), times W_P^(n2 k1);
+//          position j of a column holds k1 = bitrev(j), written to row j
+//   rows:  each row j: the LDS correlation of fft_correlate (DIF, product with
+//          the spectrum stored per row, DIT), times conj W_P^(n2 k1)
+//   icols: length-P1 DIT transforms of the column blocks back to n1, argmax
+//          partials per block (best, second best, largest magnitude)
+// plus the literal folds into the working buffer before and the final
+// reduction, intersection and scoring after.  The spectrum of row j at
+// position i is S[bitrev(j) + P1 bitrev(i)], which is the plan's bit-reversed
+// spectrum at j P2 + i.
+
+template <typename T>
+__device__ __forceinline__ void stc(cplx<T>* p, int64_t i, cplx<T> v) {
+  GAS T* q = G(reinterpret_cast<T*>(p));
+  q[2 * i] = v.x;
+  q[2 * i + 1] = v.y;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> w_pow(const cplx<T>* tw, int64_t e, int p) {
+  const int64_t P = (int64_t)1 << p;
+  e &= P - 1;
+  const cplx<T> w = ldc(tw, (int)(e & ((P >> 1) - 1)));
+  return e >= (P >> 1) ? cplx<T>{-w.x, -w.y} : w;
+}
+
+// DIF passes over stages [lb, lb + q) of a length-2^(lb + q) transform: B
+// independent length-2^q transforms stored one after another.  The last pass
+// has contiguous groups and no output twiddles.  DIT inverse in reverse order.
+__device__ __forceinline__ int batch_npasses(int q) { return (q + 3) / 4; }
+__device__ __forceinline__ void batch_pass_of(int i, int q, int lb, int& s0, int& kb) {
+  const int np = batch_npasses(q);
+  const int small = q / np, nbig = q - small * np;    // the last nbig passes get one more stage
+  const int nsmall = np - nbig;
+  if (i < nsmall) { s0 = lb + i * small; kb = small; }
+  else { s0 = lb + nsmall * small + (i - nsmall) * (small + 1); kb = small + 1; }
+}
+
+template <typename T>
+__device__ void fft_batch_forward(cplx<T>* buf, int lb, int q, const cplx<T>* tw) {
+  for (int i = 0; i < batch_npasses(q); ++i) {
+    int s0, kb;
+    batch_pass_of(i, q, lb, s0, kb);
+    fft_pass_kb<0>(kb, buf, lb + q, s0, tw, (const cplx<T>*)nullptr);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ void fft_batch_inverse(cplx<T>* buf, int lb, int q, const cplx<T>* tw) {
+  for (int i = batch_npasses(q) - 1; i >= 0; --i) {
+    int s0, kb;
+    batch_pass_of(i, q, lb, s0, kb);
+    fft_pass_kb<1>(kb, buf, lb + q, s0, tw, (const cplx<T>*)nullptr);
+    __syncthreads();
+  }
+}
+
+template <typename T, typename Tin>
+__global__ void __launch_bounds__(kGfftThreads) k_gfft_literal(InstTable tab) {
+  const Inst& d = tab.one;
+  __shared__ double red[kGfftThreads / 64];
+  const int n = blockIdx.x * kGfftThreads + threadIdx.x;
+  const int P = 1 << d.p_log2;
+  const int ma = d.va.m, mb = d.vb.m, K = d.k;
+  const int na = ma + K - 1, nb = mb + K - 1;
+  const bool exact = d.mode == MODE_EXACT;
+  T re = 0, im = 0;
+  if (n < P) {
+    if (d.acc_int) {
+      const int64_t N = d.n;
+      const bool general = N < (int64_t)max(ma, mb);
+      int val[2];
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const int M = f ? mb : ma, nn = f ? nb : na;
+        const int64_t L = f ? d.vb.l : d.va.l;
+        const int rho = (int)(N - (L - 1) * M);
+        const bool ok = n < nn;
+        const int s = n < M ? n : n - M;
+        const bool wrap = ok && s >= rho, ext = ok && n >= M;
+        const int yb = G(d.yp)[(f ? ma : 0) + (ok ? s : 0)];
+        const int xw = ld_int<Tin>(d.x, wrap ? mod_small((int64_t)(s - rho), N, general) : 0);
+        const int x1 = ld_int<Tin>(d.x, ext ? mod_small((int64_t)s + M - rho, N, general) : 0);
+        const int x0 = ld_int<Tin>(d.x, ext ? s : 0);
+        const int bias = d.sfold ? 128 * ((int)L - 1 + (s < rho ? 1 : 0)) : 0;
+        val[f] = ok ? yb - bias + (wrap ? xw : 0) + (ext ? x1 - x0 : 0) : 0;
+      }
+      re = exact ? (T)val[0] : store_round<T>((float)val[0], d.fold_store);
+      im = exact ? (T)val[1] : store_round<T>((float)val[1], d.fold_store);
+    } else {
+      const GAS float* yf = G(reinterpret_cast<const float*>(d.y));
+      re = n < na ? store_round<T>(yf[n], d.fold_store) : (T)0;
+      im = n < nb ? store_round<T>(yf[na + n], d.fold_store) : (T)0;
+    }
+    double* dya = d.swapped ? d.dbg_y2 : d.dbg_y1;
+    double* dyb = d.swapped ? d.dbg_y1 : d.dbg_y2;
+    if (dya && n < na) G(dya)[n] = (double)re;
+    if (dyb && n < nb) G(dyb)[n] = (double)im;
+    stc(reinterpret_cast<cplx<T>*>(d.gz), n, cplx<T>{re, im});
+  }
+  const double ss = block_sum<double>((double)re * (double)re + (double)im * (double)im, red);
+  if (threadIdx.x == 0) G(d.gss)[blockIdx.x] = ss;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFinishThreads) k_gfft_cols(InstTable tab) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const Inst& d = tab.one;
+  const int p = d.p_log2, q = d.g_q, lb = d.g_logb, bb = p - q;
+  const int P1 = 1 << q, P2 = 1 << bb, B = 1 << lb;
+  const int c0 = blockIdx.x * B;
+  const int NT = blockDim.x, tid = threadIdx.x;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(lds);
+  cplx<T>* z = reinterpret_cast<cplx<T>*>(d.gz);
+  if (d.acc_int)   // every literal entry has been formed: buckets back to zero
+    for (int s = blockIdx.x * NT + tid; s < d.va.m + d.vb.m; s += gridDim.x * NT) G(d.yp)[s] = 0;
+  for (int idx = tid; idx < B * P1; idx += NT) {
+    const int b = idx & (B - 1), n1 = idx >> lb;
+    buf[padi(b * P1 + n1)] = ldc(z, n1 * P2 + c0 + b);
+  }
+  __syncthreads();
+  fft_batch_forward<T>(buf, lb, q, reinterpret_cast<const cplx<T>*>(d.tw_cols));
+  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(d.tw);
+  for (int idx = tid; idx < B * P1; idx += NT) {
+    const int b = idx & (B - 1), i = idx >> lb;
+    const cplx<T> v = buf[padi(b * P1 + i)];
+    stc(z, i * P2 + c0 + b, cmul(v, w_pow(tw, (int64_t)(c0 + b) * bitrev(i, q), p)));
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFinishThreads) k_gfft_rows(InstTable tab) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const Inst& d = tab.one;
+  const int p = d.p_log2, q = d.g_q, bb = p - q;
+  const int P2 = 1 << bb;
+  const int j = blockIdx.x;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(lds);
+  cplx<T>* z = reinterpret_cast<cplx<T>*>(d.gz) + (size_t)j * P2;
+  for (int n = threadIdx.x; n < P2; n += blockDim.x) buf[padi(n)] = ldc(z, n);
+  __syncthreads();
+  fft_correlate<T>(buf, bb, reinterpret_cast<const cplx<T>*>(d.tw_rows),
+                   reinterpret_cast<const cplx<T>*>(d.spec) + (size_t)j * P2);
+  const cplx<T>* tw = reinterpret_cast<const cplx<T>*>(d.tw);
+  const int k1 = bitrev(j, q);
+  for (int n = threadIdx.x; n < P2; n += blockDim.x)
+    stc(z, n, cmulc(buf[padi(n)], w_pow(tw, (int64_t)n * k1, p)));
+}
+
+// best, second best (lowest index on ties) and largest magnitude of one fold
+struct Top2 { double v1, v2, mag; int i1, i2; };
+
+__device__ __forceinline__ void top2_add(Top2& t, double v, int i) {
+  t.mag = fmax(t.mag, fabs(v));
+  if (vi_better(VI{v, i}, VI{t.v1, t.i1})) { t.v2 = t.v1; t.i2 = t.i1; t.v1 = v; t.i1 = i; }
+  else if (vi_better(VI{v, i}, VI{t.v2, t.i2})) { t.v2 = v; t.i2 = i; }
+}
+
+__device__ __forceinline__ void top2_merge(Top2& t, const Top2& o) {
+  const double mag = fmax(t.mag, o.mag);
+  top2_add(t, o.v1, o.i1);
+  top2_add(t, o.v2, o.i2);
+  t.mag = mag;
+}
+
+struct GPart { Top2 a, b; };
+
+size_t gfft_part_bytes() { return sizeof(GPart); }
+
+__device__ Top2 block_top2(Top2 mine, Top2* scratch) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const Top2 o{__shfl_xor(mine.v1, m), __shfl_xor(mine.v2, m), __shfl_xor(mine.mag, m),
+                 __shfl_xor(mine.i1, m), __shfl_xor(mine.i2, m)};
+    top2_merge(mine, o);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) scratch[wave] = mine;
+  __syncthreads();
+  Top2 r = scratch[0];
+  for (int w = 1; w < nw; ++w) top2_merge(r, scratch[w]);
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFinishThreads) k_gfft_icols(InstTable tab) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const Inst& d = tab.one;
+  const int p = d.p_log2, q = d.g_q, lb = d.g_logb, bb = p - q;
+  const int P1 = 1 << q, P2 = 1 << bb, B = 1 << lb;
+  const int c0 = blockIdx.x * B;
+  const int NT = blockDim.x, tid = threadIdx.x;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(lds);
+  Top2* scratch = reinterpret_cast<Top2*>(lds + (size_t)padded_len(B * P1) * sizeof(cplx<T>));
+  const cplx<T>* z = reinterpret_cast<const cplx<T>*>(d.gz);
+  for (int idx = tid; idx < B * P1; idx += NT) {
+    const int b = idx & (B - 1), j = idx >> lb;
+    buf[padi(b * P1 + j)] = ldc(z, j * P2 + c0 + b);
+  }
+  __syncthreads();
+  fft_batch_inverse<T>(buf, lb, q, reinterpret_cast<const cplx<T>*>(d.tw_cols));
+  const bool exact = d.mode == MODE_EXACT;
+  const int ma = d.va.m, mb = d.vb.m;
+  double* dra = d.swapped ? d.dbg_r2 : d.dbg_r1;
+  double* drb = d.swapped ? d.dbg_r1 : d.dbg_r2;
+  Top2 ta{-INFINITY, -INFINITY, 0.0, 0x7fffffff, 0x7fffffff}, tb = ta;
+  for (int idx = tid; idx < B * P1; idx += NT) {
+    const int b = idx & (B - 1), n1 = idx >> lb;
+    const int n = n1 * P2 + c0 + b;
+    const cplx<T> v = buf[padi(b * P1 + n1)];
+    if (n < ma) {
+      const double r = exact ? rint((double)v.x) : (double)v.x;
+      if (dra) G(dra)[n] = r;
+      top2_add(ta, r, n);
+    }
+    if (n < mb) {
+      const double r = exact ? rint((double)v.y) : (double)v.y;
+      if (drb) G(drb)[n] = r;
+      top2_add(tb, r, n);
+    }
+  }
+  const Top2 ra = block_top2(ta, scratch);
+  const Top2 rb = block_top2(tb, scratch);
+  if (tid == 0) {
+    GPart* part = reinterpret_cast<GPart*>(d.gpart) + blockIdx.x;
+    part->a = ra;
+    part->b = rb;
+  }
+}
+
+template <typename Tin>
+__global__ void __launch_bounds__(kGfftThreads) k_gfft_final(InstTable tab) {
+  const Inst& d = tab.one;
+  __shared__ __align__(16) unsigned char scratch[kGfftThreads * 16];
+  __shared__ Top2 fa, fb;
+  __shared__ double zn2;
+  const int nparts = (1 << (d.p_log2 - d.g_q)) >> d.g_logb;
+  const int nss = (1 << d.p_log2) / kGfftThreads;
+  if (threadIdx.x == 0) {   // fixed order: deterministic
+    const GPart* parts = reinterpret_cast<const GPart*>(d.gpart);
+    Top2 a = parts[0].a, b = parts[0].b;
+    for (int i = 1; i < nparts; ++i) { top2_merge(a, parts[i].a); top2_merge(b, parts[i].b); }
+    double s2 = 0.0;
+    for (int i = 0; i < nss; ++i) s2 += G(d.gss)[i];
+    fa = a;
+    fb = b;
+    zn2 = s2;
+  }
+  __syncthreads();
+  const Top2 a = fa, b = fb;
+  uint32_t flags = 0;
+  if (d.mode == MODE_EXACT) {
+    // the two twiddle products of the four-step transform count as two more stages
+    const double bound = 20.0 * (d.p_log2 + 2) * 0x1p-53 * d.tnorm1 * sqrt(zn2);
+    if (bound < 0.5) flags |= TM_R_EXACT;
+  } else if (a.v1 - a.v2 <= 1e-5 * a.mag || b.v1 - b.v2 <= 1e-5 * b.mag) {
+    flags |= TM_R_NEAR_TIE;
+  }
+  resolve_and_report<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch);
+}
+
+template <typename T, typename Tin>
+hipError_t launch_gfft_t(const Inst& one, hipStream_t s) {
+  InstTable tab{};
+  tab.table = nullptr;
+  tab.count = 1;
+  tab.one = one;
+  const int p = one.p_log2, q = one.g_q, lb = one.g_logb, bb = p - q;
+  const int P = 1 << p, P2 = 1 << bb, B = 1 << lb;
+  const int cols_threads = std::min(kFinishThreads, std::max(64, (B << q) >> 4));
+  const size_t cols_lds = (size_t)padded_len(B << q) * sizeof(cplx<T>) + (size_t)(kFinishThreads / 64) * sizeof(Top2);
+  const int mode = one.mode;
+  hipLaunchKernelGGL((k_gfft_literal<T, Tin>), dim3(P / kGfftThreads), dim3(kGfftThreads), 0, s, tab);
+  hipLaunchKernelGGL(k_gfft_cols<T>, dim3(P2 / B), dim3(cols_threads), cols_lds, s, tab);
+  hipLaunchKernelGGL(k_gfft_rows<T>, dim3(1 << q), dim3(finish_threads(bb)), finish_lds_bytes(bb, mode), s, tab);
+  hipLaunchKernelGGL(k_gfft_icols<T>, dim3(P2 / B), dim3(cols_threads), cols_lds, s, tab);
+  hipLaunchKernelGGL(k_gfft_final<Tin>, dim3(1), dim3(kGfftThreads), 0, s, tab);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gfft_x(const Inst& one, hipStream_t s) {
+  switch (one.x_dtype) {
+    case TM_I8: return launch_gfft_t<T, int8_t>(one, s);
+    case TM_F32: return launch_gfft_t<T, float>(one, s);
+    case TM_BF16: return launch_gfft_t<T, bf16_t>(one, s);
+    default: return launch_gfft_t<T, f16_t>(one, s);
+  }
+}
+
+hipError_t launch_gfft(const Inst& one, hipStream_t s) {
+  return one.mode == MODE_EXACT ? launch_gfft_x<double>(one, s) : launch_gfft_x<float>(one, s);
+}
+
+// --------------------------------------------------------------------------
 // plan-time kernels
 // --------------------------------------------------------------------------
 
@@ -1383,7 +1769,7 @@ __global__ void k_twiddles(void* tw, int p, int as_double) {
 // (global scratch, one workgroup), then S = conj(Z) / P at the same positions.
 __global__ void __launch_bounds__(1024) k_spectrum(const void* t, int t_dtype, int k, int p,
                                                    const double2* tw64, double2* z, void* spec,
-                                                   int as_double) {
+                                                   int as_double, int row_log2) {
   const int P = 1 << p;
   const int tid = threadIdx.x, NT = blockDim.x;
   for (int n = tid; n < P; n += NT) z[n] = make_double2(n < k ? load_as_double(t, t_dtype, n) : 0.0, 0.0);
@@ -1403,7 +1789,9 @@ __global__ void __launch_bounds__(1024) k_spectrum(const void* t, int t_dtype, i
   const double inv = 1.0 / (double)P;
   for (int n = tid; n < P; n += NT) {
     const double2 v = z[n];
-    const int slot = spec_slot(n, p);
+    // one length-P correlation in LDS, or rows of 2^row_log2 (global-memory FFT)
+    const int slot = row_log2 ? ((n >> row_log2) << row_log2) + spec_slot(n & ((1 << row_log2) - 1), row_log2)
+                              : spec_slot(n, p);
     if (as_double) reinterpret_cast<double2*>(spec)[slot] = make_double2(v.x * inv, -v.y * inv);
     else reinterpret_cast<float2*>(spec)[slot] = make_float2((float)(v.x * inv), (float)(-v.y * inv));
   }
@@ -1422,7 +1810,11 @@ hipError_t configure_kernels() {
   e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
   const void* fns[] = {reinterpret_cast<const void*>(k_fold), reinterpret_cast<const void*>(k_finish<double>),
-                       reinterpret_cast<const void*>(k_finish<float>)};
+                       reinterpret_cast<const void*>(k_finish<float>),
+                       reinterpret_cast<const void*>(k_gfft_cols<double>), reinterpret_cast<const void*>(k_gfft_cols<float>),
+                       reinterpret_cast<const void*>(k_gfft_rows<double>), reinterpret_cast<const void*>(k_gfft_rows<float>),
+                       reinterpret_cast<const void*>(k_gfft_icols<double>),
+                       reinterpret_cast<const void*>(k_gfft_icols<float>)};
   for (const void* f : fns) {
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
       (void)hipGetLastError();
@@ -1473,10 +1865,10 @@ hipError_t launch_twiddles(void* tw, int p_log2, int as_double, hipStream_t s) {
 }
 
 hipError_t launch_spectrum(const void* t, int t_dtype, int k, int p_log2, const double* tw64,
-                           double* scratch, void* spec, int as_double, hipStream_t s) {
+                           double* scratch, void* spec, int as_double, int row_log2, hipStream_t s) {
   hipLaunchKernelGGL(k_spectrum, dim3(1), dim3(1024), 0, s, t, t_dtype, k, p_log2,
                      reinterpret_cast<const double2*>(tw64), reinterpret_cast<double2*>(scratch), spec,
-                     as_double);
+                     as_double, row_log2);
   return hipGetLastError();
 }
 

@@ -123,6 +123,8 @@ struct Core {
   int32_t ntiles = 0, nred = 0, red_tpe = 1, acc_int = 0;
   int32_t sfold = 0, nseg = 0, seg_chunks = 0;   // streaming int8 fold
   int32_t band = 0, nband = 0;                    // band fold of 4-byte signals
+  int32_t gfft = 0, g_q = 0, g_logb = 0;          // FFT through global memory
+  size_t off_gz = 0, off_gss = 0, off_gpart = 0;
   size_t acc_bytes = 0;     // integer bucket zone (int32 [ma + mb]); lives in the zeroed pool
   size_t fold_lds = 0, finish_lds = 0;
   int fft_in_lds = 1;
@@ -177,6 +179,12 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   while ((int64_t(1) << p) < need) ++p;
   c->p_log2 = p;
   c->fft_in_lds = p <= fft_lds_max_log2(c->mode);
+  if (!c->fft_in_lds && p <= kGfftMaxLog2) {
+    // P = P1 x P2: blocks of B columns of P1 with B P1 = 4096 at most, rows of P2
+    c->gfft = 1;
+    c->g_logb = c->mode == MODE_EXACT ? 3 : 4;          // 128-byte row segments
+    c->g_q = std::min(12 - c->g_logb, p - 7);
+  }
 
   const int eb = dtype_bytes(d->x_dtype);
   // 4-byte signals: band fold (views of 64-column bands, R rows per task);
@@ -241,6 +249,13 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
     if (!c->dual) off = align256(off + (size_t)c->vb.nrb * c->mb * 4);
     c->off_y = off; off = align256(off + (size_t)ytot * 4);
   }
+  if (c->gfft) {
+    const size_t P = size_t(1) << p;
+    c->off_gz = off; off = align256(off + P * (c->mode == MODE_EXACT ? 16 : 8));
+    c->off_gss = off; off = align256(off + (P / kGfftThreads) * sizeof(double));
+    c->off_gpart = off;
+    off = align256(off + ((P >> c->g_q) >> c->g_logb) * gfft_part_bytes());
+  }
   c->off_res = off; off = align256(off + sizeof(tm_result));
   c->ws_bytes = off;
   c->fold_lds = std::max(fold_lds_bytes(c->va, d->x_dtype), c->dual ? 0 : fold_lds_bytes(c->vb, d->x_dtype));
@@ -257,6 +272,7 @@ void fill_info(const Core& c, tm_plan_info* info) {
   info->exact = c.mode == MODE_EXACT;
   info->dual = c.dual;
   info->fft_in_lds = c.fft_in_lds;
+  info->fft_global = c.gfft;
   info->fold_tiles = c.ntiles;
   info->fold_segments = c.nseg;
   info->fold_bands = c.nband;
@@ -419,6 +435,8 @@ struct tm_plan_s {
   void* t_dev = nullptr;
   void* tw64 = nullptr;      // shared twiddle tables (not owned)
   void* tw32 = nullptr;
+  void* tw_cols = nullptr;   // global-memory FFT: column blocks and rows
+  void* tw_rows = nullptr;
   void* spec = nullptr;
   double tnorm1 = 0.0;
 };
@@ -462,10 +480,20 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->t = p->t_dev;
   in->spec = p->spec;
   in->tw = c.mode == MODE_EXACT ? p->tw64 : p->tw32;
+  in->gfft = c.gfft;
+  in->g_q = c.g_q;
+  in->g_logb = c.g_logb;
+  in->tw_cols = p->tw_cols;
+  in->tw_rows = p->tw_rows;
   in->tnorm1 = p->tnorm1;
 }
 
 void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
+  if (c.gfft) {
+    in->gz = base + c.off_gz;
+    in->gss = reinterpret_cast<double*>(base + c.off_gss);
+    in->gpart = base + c.off_gpart;
+  }
   if (c.acc_int) {
     in->yp = reinterpret_cast<int*>(acc);
     in->y = base + c.off_y;
@@ -479,7 +507,7 @@ void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
 
 tm_status check_plan_for_match(tm_plan p) {
   if (!p) return fail(TM_ERR_INVALID, "null plan");
-  if (!p->core.fft_in_lds)
+  if (!p->core.fft_in_lds && !p->core.gfft)
     return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(p->core.p_log2) +
                                         " exceeds one workgroup's LDS on this build");
   return TM_OK;
@@ -547,9 +575,9 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
   Core c;
   tm_status st = compute_core(desc, &c);
   if (st != TM_OK) return st;
-  if (!c.fft_in_lds)
-    return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(c.p_log2) +
-                                        " exceeds one workgroup's LDS on this build");
+  if (!c.fft_in_lds && !c.gfft)
+    return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(c.p_log2) + " is above 2^" +
+                                        std::to_string(kGfftMaxLog2));
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   TM_HIP(hipGetDevice(&dev));
@@ -598,6 +626,8 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
   TM_HIP_PLAN(hipMemcpyAsync(p->t_dev, th.data(), tb, hipMemcpyHostToDevice, s));
   st = shared_twiddles(dev, c.p_log2, 1, s, &p->tw64);
   if (st == TM_OK && c.mode == MODE_REAL) st = shared_twiddles(dev, c.p_log2, 0, s, &p->tw32);
+  if (st == TM_OK && c.gfft) st = shared_twiddles(dev, c.g_logb + c.g_q, c.mode == MODE_EXACT, s, &p->tw_cols);
+  if (st == TM_OK && c.gfft) st = shared_twiddles(dev, c.p_log2 - c.g_q, c.mode == MODE_EXACT, s, &p->tw_rows);
   if (st != TM_OK) {
     cleanup();
     return st;
@@ -605,7 +635,8 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
   TM_HIP_PLAN(hipMalloc(&p->spec, P * (c.mode == MODE_EXACT ? 16 : 8)));
   TM_HIP_PLAN(hipMalloc(&z, P * 16));
   TM_HIP_PLAN(launch_spectrum(p->t_dev, c.t_dtype, c.k, c.p_log2, static_cast<const double*>(p->tw64),
-                              static_cast<double*>(z), p->spec, c.mode == MODE_EXACT, s));
+                              static_cast<double*>(z), p->spec, c.mode == MODE_EXACT,
+                              c.gfft ? c.p_log2 - c.g_q : 0, s));
   TM_HIP_PLAN(hipStreamSynchronize(s));
   TM_HIP_PLAN(hipFree(z));
   z = nullptr;
@@ -667,7 +698,8 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;                 // until the finish kernel is enqueued
   TM_HIP(launch_reduce(tab, p->core.nred, s));
-  TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2, p->core.finish_lds, s));
+  if (p->core.gfft) TM_HIP(launch_gfft(tab.one, s));
+  else TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2, p->core.finish_lds, s));
   pool.acc_dirty = false;
   if (!dev_out) {
     TM_HIP(hipMemcpyAsync(out, tab.one.out, sizeof(tm_result), hipMemcpyDeviceToHost, s));
@@ -782,7 +814,11 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     const Core& c0 = plans[order[g0]]->core;
     int32_t g1 = g0 + 1;
     while (g1 < count && plans[order[g1]]->core.mode == c0.mode && plans[order[g1]]->core.p_log2 == c0.p_log2) ++g1;
-    TM_HIP(launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.p_log2, c0.finish_lds, s));
+    if (c0.gfft) {   // one launch sequence per instance
+      for (int32_t g = g0; g < g1; ++g) TM_HIP(launch_gfft(host_tab[order[g]], s));
+    } else {
+      TM_HIP(launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.p_log2, c0.finish_lds, s));
+    }
     g0 = g1;
   }
   pool.acc_dirty = false;

@@ -40,7 +40,7 @@ class PlanInfo(ctypes.Structure):
                 ("l2", ctypes.c_int32), ("fft_log2", ctypes.c_int32), ("exact", ctypes.c_int32),
                 ("dual", ctypes.c_int32), ("fft_in_lds", ctypes.c_int32),
                 ("fold_tiles", ctypes.c_int32), ("fold_segments", ctypes.c_int32),
-                ("fold_bands", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fold_bands", ctypes.c_int32), ("fft_global", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("x_bytes", ctypes.c_int64)]
 
 

@@ -88,10 +88,18 @@ def test_modes():
 
 
 def test_fft_length_limits():
-    # exact path keeps P <= 2^13 in one workgroup's LDS, the real path P <= 2^14
-    assert tm.plan_params(1 << 22, 4096)["fft_in_lds"] == 1
-    assert tm.plan_params(1 << 24, 8192)["fft_in_lds"] == 0
+    # exact path keeps P <= 2^13 in one workgroup's LDS, the real path P <= 2^14;
+    # above that the four-step transform through global memory takes over, up to 2^21
+    info = tm.plan_params(1 << 22, 4096)
+    assert info["fft_in_lds"] == 1 and info["fft_global"] == 0
+    info = tm.plan_params(1 << 24, 8192)
+    assert info["fft_in_lds"] == 0 and info["fft_global"] == 1
     assert tm.plan_params(1 << 24, 8192, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32)["fft_in_lds"] == 1
+    info = tm.plan_params(1 << 24, 1 << 14, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32)
+    assert info["fft_log2"] == 15 and info["fft_global"] == 1
+    assert tm.plan_params(1 << 26, 1 << 16)["fft_global"] == 1          # Section 5 tables: P = 2^17
+    info = tm.plan_params(1 << 30, 1 << 21)                              # P = 2^22: no path
+    assert info["fft_in_lds"] == 0 and info["fft_global"] == 0
 
 
 def test_plan_create_without_device_fails_cleanly():

@@ -1,0 +1,105 @@
+"""FFT lengths above one workgroup's LDS: the four-step transform through
+global memory, against the oracle.
+
+Exact path (P = 2^14, 2^15): every intermediate bit for bit.  Real path
+(P = 2^15 as in the N = 2^24, K = 2^14 precision workload, and P = 2^17 as in
+the Section 5 tables): normwise 1e-5 against the FP64 oracle, whose
+correlation is its direct sum where that finishes quickly and its FP64 FFT
+cross-check otherwise.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import ftm as O
+from paper_1509_04863_amd import datagen as G
+from paper_1509_04863_amd import tm
+
+from _util import assert_exact_parity, gpu_match, normwise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _case(*a):
+    print("case:", *a, flush=True)
+
+
+EXACT = [
+    # (n, k, m1, m2, x dtype)        fold path, P
+    (1 << 20, 6000, 0, 0, np.int8),   # tiled int8, 2^14
+    (1 << 20, 4000, 4607, 4608, np.int8),   # streaming int8, 2^14
+    (3 << 18, 9000, 0, 0, np.int8),   # 2^15
+    (1 << 20, 5000, 0, 0, np.float32),  # band fold of fp32 +-1, 2^14
+    (20000, 8000, 0, 0, np.int8),     # L = 3, wraps, 2^14
+    (9000, 9000, 0, 0, np.int8),      # K = N: M = K = N, L = 1
+]
+
+
+@pytest.mark.parametrize("n,k,m1,m2,dt", EXACT)
+def test_global_fft_exact(n, k, m1, m2, dt):
+    inst = G.planted_pm1(n, k, 95, n + k, flip_frac=0.1, x_dtype=dt)
+    flags = tm.TM_F_EXACT if dt == np.float32 else 0
+    info = tm.plan_params(n, k, m1=m1, m2=m2, x_dtype=tm.tm_dtype_of(inst.x), t_dtype=tm.tm_dtype_of(inst.t),
+                          flags=flags)
+    assert info["fft_global"] == 1 and info["exact"] == 1
+    _case("global exact", n, k, m1, m2, dt.__name__, info["fft_log2"])
+    res, ref = assert_exact_parity(inst.x, inst.t, m1=m1, m2=m2, flags=flags,
+                                   x_oracle=inst.x.astype(np.int64), t_oracle=inst.t.astype(np.int64))
+
+
+def _real_case(inst, correlation, tol=1e-5, **kw):
+    res, y1, y2, r1, r2, plan = gpu_match(inst.x, inst.t, **kw)
+    assert plan.info["fft_global"] == 1
+    ref = O.ftm(inst.x.astype(np.float64), inst.t.astype(np.float64), plan.m1, plan.m2, correlation=correlation)
+    k = inst.k
+    assert normwise(y1, ref.y1[:plan.m1 + k - 1]) <= tol
+    assert normwise(y2, ref.y2[:plan.m2 + k - 1]) <= tol
+    e1, e2 = normwise(r1, ref.r1), normwise(r2, ref.r2)
+    print("normwise r error", e1, e2, flush=True)
+    assert e1 <= tol and e2 <= tol
+    if not res.near_tie and O.top2_gap(ref.r1) > 1e-4 * np.max(np.abs(ref.r1)) \
+            and O.top2_gap(ref.r2) > 1e-4 * np.max(np.abs(ref.r2)):
+        assert (res.m1_tilde, res.m2_tilde) == (ref.m1_tilde, ref.m2_tilde)
+        assert res.shift == ref.shift
+    return res, ref
+
+
+def test_global_fft_real_precision_workload():
+    inst = G.config5a(0, n=1 << 22, k=1 << 14)          # P = 2^15, fp32 FFT through global memory
+    _case("global real 2^15")
+    _real_case(inst, "direct")
+
+
+def test_global_fft_real_section5_length():
+    inst = G.planted_gauss(1 << 20, 1 << 16, 0.0, 96, 0)   # M = 2^16: P = 2^17
+    _case("global real 2^17")
+    _real_case(inst, "fft")
+
+
+@pytest.mark.parametrize("store,bound", [(tm.TM_BF16, 2.0 ** -8), (tm.TM_F16, 2.0 ** -11)])
+def test_global_fft_fold_storage(store, bound):
+    inst = G.config5a(1, n=1 << 22, k=1 << 14)
+    res, y1, y2, r1, r2, plan = gpu_match(inst.x, inst.t, fold_store=store)
+    ref = O.ftm(inst.x.astype(np.float64), inst.t.astype(np.float64), plan.m1, plan.m2, correlation="fft")
+    _case("global fold store", store)
+    assert normwise(r1, ref.r1) <= 8 * bound and normwise(r2, ref.r2) <= 8 * bound
+
+
+def test_batch_with_global_and_lds_instances():
+    shapes = [(1 << 20, 6000), (70000, 700), (3 << 18, 9000), (1 << 18, 2048), (20000, 8000)]
+    insts = [G.planted_pm1(n, k, 97, i, flip_frac=0.07) for i, (n, k) in enumerate(shapes)]
+    plans = [tm.Plan(s.t, n=s.n) for s in insts]
+    assert sum(p.info["fft_global"] for p in plans) == 3
+    xs = [torch.from_numpy(s.x).cuda() for s in insts]
+    _case("global batch")
+    batch = tm.match_batch(plans, xs)
+    single = [tm.match(p, x) for p, x in zip(plans, xs)]
+    assert all(b == s for b, s in zip(batch, single))
+    for b, inst, p in zip(batch, insts, plans):
+        ref = O.ftm(inst.x, inst.t, p.m1, p.m2)
+        assert (b.shift, b.m1_tilde, b.m2_tilde, b.n_candidates) == \
+            (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
