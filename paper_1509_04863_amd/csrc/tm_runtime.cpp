@@ -179,11 +179,13 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   while ((int64_t(1) << p) < need) ++p;
   c->p_log2 = p;
   c->fft_in_lds = p <= fft_lds_max_log2(c->mode);
+  // TM_FFT_GLOBAL=1 also sends in-LDS lengths of 2^10 and more through global memory
+  if (c->fft_in_lds && p >= 10 && env_int("TM_FFT_GLOBAL", 0) != 0) c->fft_in_lds = 0;
   if (!c->fft_in_lds && p <= kGfftMaxLog2) {
     // P = P1 x P2: blocks of B columns of P1 with B P1 = 4096 at most, rows of P2
     c->gfft = 1;
     c->g_logb = c->mode == MODE_EXACT ? 3 : 4;          // 128-byte row segments
-    c->g_q = std::min(12 - c->g_logb, p - 7);
+    c->g_q = std::min(12 - c->g_logb, std::max(p - 7, (p + 1) / 2));
   }
 
   const int eb = dtype_bytes(d->x_dtype);
