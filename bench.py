@@ -29,7 +29,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3"])
+    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "config4"])
+    ap.add_argument("--pool", type=int, default=96, help="device signals in the config4 pool")
+    ap.add_argument("--templates", type=int, default=384, help="distinct config4 requests (plans)")
+    ap.add_argument("--rate", type=float, default=20000.0, help="config4 offered load, requests/s")
+    ap.add_argument("--duration", type=float, default=2.0, help="config4 open-loop seconds")
     ap.add_argument("--batch", type=int, default=4096, help="instances per step for config3")
     ap.add_argument("--rotate-mib", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -107,6 +111,92 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def run_serving(args):
+    """config4: open-loop Poisson arrivals into the request server (p50/p99
+    latency), then closed-loop saturation throughput of the server and of the
+    plain path (one synchronous tm_match per request)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1509_04863_amd import datagen as G
+    from paper_1509_04863_amd import tm
+
+    pool = G.config4_pool(args.pool)
+    xs = [torch.from_numpy(s.x).cuda() for s in pool]
+    reqs = G.config4_requests(pool, args.templates, rate_hz=args.rate)
+    plans = [tm.Plan(r.t, n=pool[r.pool_id].n, x_dtype=tm.tm_dtype_of(pool[r.pool_id].x)) for r in reqs]
+    req_x = [xs[r.pool_id] for r in reqs]
+    torch.cuda.synchronize()
+    nreq = len(reqs)
+
+    # open loop at the offered rate
+    rng = np.random.default_rng(7)
+    count = max(1, int(args.rate * args.duration))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=count))
+    lat = np.zeros(count)
+    with tm.Server(budget_bytes=2 << 30, max_batch=512, max_inflight=3) as srv:
+        for i in range(min(64, nreq)):                      # warm-up
+            srv.wait(srv.submit(plans[i], req_x[i]))
+        tickets = [None] * count
+        ready = threading.Semaphore(0)
+
+        def consume():
+            for i in range(count):
+                ready.acquire()
+                _, lat[i] = srv.wait(tickets[i])
+
+        th = threading.Thread(target=consume)
+        th.start()
+        t0 = time.perf_counter()
+        for i in range(count):
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            j = i % nreq
+            tickets[i] = srv.submit(plans[j], req_x[j])
+            ready.release()
+        th.join()
+        open_s = time.perf_counter() - t0
+        open_stats = srv.stats()
+
+        # closed loop: the whole request set queued at once, several rounds
+        rounds = 4
+        t0 = time.perf_counter()
+        ts = [srv.submit(plans[i % nreq], req_x[i % nreq]) for i in range(rounds * nreq)]
+        served = [srv.wait(t)[0] for t in ts]
+        served_s = time.perf_counter() - t0
+    # plain path on the same requests
+    for i in range(min(16, nreq)):
+        tm.match(plans[i], req_x[i])
+    t0 = time.perf_counter()
+    plain = [tm.match(plans[i], req_x[i]) for i in range(nreq)]
+    plain_s = time.perf_counter() - t0
+    same = sum(int(a == b) for a, b in zip(served[:nreq], plain))
+    recovered = sum(int(r.shift == q.shift) for r, q in zip(plain, reqs))
+    served_rate = rounds * nreq / served_s
+    plain_rate = nreq / plain_s
+    lat_ms = lat / 1e6
+    line = {
+        "metric": "template matches/sec + fold GB/s vs HBM peak; served p50/p99 vs plain launch",
+        "value": served_rate, "unit": "matches/s", "n_gpus": 1, "steps": rounds, "warmup": 1,
+        "ms_per_step": served_s / rounds * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32 fold + f32 fft (real templates)", "data": "synthetic",
+        "config": {"workload": "config4: serving, %d distinct requests over a pool of %d signals "
+                               "(N=2^U(14,24), 70%% int8 +-1 / 30%% fp32 N(0,1)), K=2^U(8,13), "
+                               "templates at 0 dB" % (nreq, len(pool)),
+                   "pool_bytes": int(sum(s.x.nbytes for s in pool))},
+        "serving": {"offered_rate": args.rate, "open_loop_requests": count, "open_loop_s": open_s,
+                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                    "mean_batch": open_stats["completed"] / max(1, open_stats["batches"]),
+                    "served_matches_per_s": served_rate, "plain_matches_per_s": plain_rate,
+                    "served_vs_plain": served_rate / plain_rate,
+                    "served_equals_plain": "%d/%d" % (same, nreq)},
+        "planted_recovered": "%d/%d" % (recovered, nreq),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(make, budget_s, gpu_results):
     """The oracle as it stands, on instances of the same workload, for about
     budget_s seconds of single-threaded CPU work."""
@@ -147,6 +237,9 @@ def main():
     torch.cuda.set_device(0)
     if args.config == "config3":
         run_batched(args)
+        return
+    if args.config == "config4":
+        run_serving(args)
         return
     wl = workload(args.config)
     first = wl["make"](0)

@@ -187,6 +187,66 @@ tm_status tm_match_intermediates(tm_plan plan, const void* x, tm_result* out,
 tm_status tm_profile_enable(int on);
 tm_status tm_profile_read(double* fold_ms_total, int64_t* fold_launches, int reset);
 
+/*
+ * Request server (continuous batching).  Matches of uneven N and K submitted
+ * from any thread are grouped first in, first out into batches of at most
+ * max_batch requests; up to max_inflight batches run on the device at once,
+ * each on its own stream, so requests that arrive while others run are
+ * launched as soon as a slot is free.  A request is admitted while the device
+ * workspace (tm_plan_info.workspace_bytes + 48 bytes) of all batches in flight
+ * stays within budget_bytes; a single request above the budget runs alone.
+ * Every result equals the one tm_match returns for the same plan and signal.
+ * Plans (templates, spectra and twiddles) stay on the device; the caller keeps
+ * each plan and signal valid until its result has been taken.
+ */
+typedef struct tm_server_s* tm_server;
+
+typedef struct {
+  int64_t budget_bytes;  /* 0 = 1 GiB */
+  int32_t max_batch;     /* 0 = 1024 */
+  int32_t max_inflight;  /* 0 = 2; at most 8 */
+} tm_server_desc;
+
+typedef struct {
+  int64_t submitted, completed, failed, batches;
+  int64_t peak_inflight_bytes;   /* largest admitted workspace in flight */
+} tm_server_stats;
+
+/* Creates the streams, pinned result buffers and worker thread on the current
+ * device.  Errors: TM_ERR_INVALID for negative fields or max_inflight > 8,
+ * TM_ERR_DEVICE when no device or allocation is available. */
+tm_status tm_server_create(const tm_server_desc* desc, tm_server* out);
+
+/* Queues one match (Algorithm 1 for plan and the device signal x) and returns
+ * its ticket; does not wait.  Errors: TM_ERR_INVALID for null arguments or a
+ * server being destroyed, TM_ERR_UNSUPPORTED for plans without an FFT path. */
+tm_status tm_server_submit(tm_server server, tm_plan plan, const void* x, uint64_t* ticket);
+
+/* *done = 0 while the request runs; once done, *done = 1, *out holds the
+ * result, *latency_ns (optional) the time from submission to completion, and
+ * the ticket is consumed.  The returned status is the request's own (a batch
+ * that failed on the device reports TM_ERR_DEVICE).  TM_ERR_INVALID for an
+ * unknown or consumed ticket. */
+tm_status tm_server_poll(tm_server server, uint64_t ticket, tm_result* out, int64_t* latency_ns, int* done);
+
+/* tm_server_poll that blocks until the request is done. */
+tm_status tm_server_wait(tm_server server, uint64_t ticket, tm_result* out, int64_t* latency_ns);
+
+tm_status tm_server_get_stats(tm_server server, tm_server_stats* out);
+
+/* Runs every queued request to completion, then frees the server. */
+tm_status tm_server_destroy(tm_server server);
+
+/*
+ * tm_admit_batches -- the server's admission rule on the host alone: with no
+ * batch in flight, footprints[0..count) are cut first in, first out into
+ * batches of at most max_batch requests whose summed footprint stays within
+ * budget_bytes (a request above the budget forms a batch of its own);
+ * batch_of[i] receives the batch index of request i.
+ */
+tm_status tm_admit_batches(int32_t count, const int64_t* footprints, int64_t budget_bytes, int32_t max_batch,
+                           int32_t* batch_of);
+
 /* Message strings. tm_last_error is per calling thread. */
 const char* tm_status_string(tm_status status);
 const char* tm_last_error(void);

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtm.so")
 
-SOURCES = ["tm_kernels.hip", "tm_runtime.cpp"]
+SOURCES = ["tm_kernels.hip", "tm_runtime.cpp", "tm_server.cpp"]
 
 
 def hipcc() -> str:

@@ -25,7 +25,9 @@ TM_R_NOMATCH, TM_R_RESCORED, TM_R_NEAR_TIE, TM_R_EXACT = 0x1, 0x2, 0x4, 0x8
 
 EXPORTS = ["tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_info", "tm_match",
            "tm_match_batch", "tm_match_intermediates", "tm_status_string", "tm_last_error",
-           "tm_version", "tm_profile_enable", "tm_profile_read"]
+           "tm_version", "tm_profile_enable", "tm_profile_read", "tm_server_create", "tm_server_submit",
+           "tm_server_poll", "tm_server_wait", "tm_server_get_stats", "tm_server_destroy",
+           "tm_admit_batches"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -49,6 +51,16 @@ class Result(ctypes.Structure):
                 ("m2_tilde", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("peak1", ctypes.c_double),
                 ("peak2", ctypes.c_double), ("score", ctypes.c_double)]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64)]
 
 
 assert ctypes.sizeof(Result) == 48 and ctypes.sizeof(PlanDesc) == 40
@@ -95,6 +107,17 @@ def lib():
         L.tm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int]
         L.tm_profile_read.restype = ctypes.c_int
+        u64p, i64p = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)
+        L.tm_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(vp)]
+        L.tm_server_submit.argtypes = [vp, vp, vp, u64p]
+        L.tm_server_poll.argtypes = [vp, ctypes.c_uint64, vp, i64p, ctypes.POINTER(ctypes.c_int)]
+        L.tm_server_wait.argtypes = [vp, ctypes.c_uint64, vp, i64p]
+        L.tm_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.tm_server_destroy.argtypes = [vp]
+        L.tm_admit_batches.argtypes = [i32, i64p, ctypes.c_int64, i32, ctypes.POINTER(i32)]
+        for fn in ("tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_wait",
+                   "tm_server_get_stats", "tm_server_destroy", "tm_admit_batches"):
+            getattr(L, fn).restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -340,3 +363,68 @@ def profile_read(reset: bool = False):
     n = ctypes.c_int64()
     _check(lib().tm_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def admit_batches(footprints, budget_bytes: int, max_batch: int):
+    """The server's first-in first-out admission rule on the host
+    (tm_admit_batches): the batch index of every request."""
+    fp = np.ascontiguousarray(np.asarray(footprints, dtype=np.int64))
+    out = np.zeros(fp.shape[0], dtype=np.int32)
+    _check(lib().tm_admit_batches(int(fp.shape[0]), fp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  int(budget_bytes), int(max_batch),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out
+
+
+class Server:
+    """Continuous-batching request server (tm_server_*).  Keeps a reference to
+    every submitted signal until its result has been taken."""
+
+    def __init__(self, budget_bytes: int = 0, max_batch: int = 0, max_inflight: int = 0):
+        d = ServerDesc(budget_bytes=int(budget_bytes), max_batch=int(max_batch),
+                       max_inflight=int(max_inflight))
+        self.handle = ctypes.c_void_p()
+        _check(lib().tm_server_create(ctypes.byref(d), ctypes.byref(self.handle)))
+        self._keep = {}
+
+    def submit(self, plan: Plan, x) -> int:
+        _check_signal(plan, x)
+        t = ctypes.c_uint64()
+        _check(lib().tm_server_submit(self.handle, plan.handle, x.data_ptr(), ctypes.byref(t)))
+        self._keep[t.value] = (plan, x)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, MatchResult or None, latency in ns or None)."""
+        res, lat, done = Result(), ctypes.c_int64(), ctypes.c_int()
+        _check(lib().tm_server_poll(self.handle, ticket, ctypes.addressof(res), ctypes.byref(lat),
+                                    ctypes.byref(done)))
+        if not done.value:
+            return False, None, None
+        self._keep.pop(ticket, None)
+        return True, MatchResult(*_row(res)), lat.value
+
+    def wait(self, ticket: int):
+        """(MatchResult, latency in ns)."""
+        res, lat = Result(), ctypes.c_int64()
+        st = lib().tm_server_wait(self.handle, ticket, ctypes.addressof(res), ctypes.byref(lat))
+        self._keep.pop(ticket, None)
+        _check(st)
+        return MatchResult(*_row(res)), lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().tm_server_get_stats(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().tm_server_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -115,3 +115,30 @@ def test_plan_create_without_device_fails_cleanly():
     st = tm.lib().tm_plan_create(ctypes.byref(desc), t.ctypes.data, 0, None, ctypes.byref(h))
     assert st in (tm.TM_ERR_DEVICE, tm.TM_ERR_NOMEM)
     assert not h.value
+
+
+def test_admission_rule_first_in_first_out():
+    fp = [100, 200, 300, 50, 5000, 10, 10, 10]
+    b = tm.admit_batches(fp, budget_bytes=600, max_batch=3)
+    # batches in order, never above the budget or max_batch, oversized alone
+    assert list(b) == [0, 0, 0, 1, 2, 3, 3, 3]
+    b = tm.admit_batches(fp, budget_bytes=10 ** 9, max_batch=2)
+    assert list(b) == [0, 0, 1, 1, 2, 2, 3, 3]
+
+
+def test_admission_rule_invariants_random():
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        n = int(rng.integers(0, 60))
+        fp = rng.integers(1, 1000, n)
+        budget = int(rng.integers(1, 3000))
+        mb = int(rng.integers(1, 9))
+        b = tm.admit_batches(fp, budget, mb)
+        assert np.all(np.diff(b) >= 0) and (n == 0 or b[0] == 0)
+        for j in range(int(b.max()) + 1 if n else 0):
+            members = fp[b == j]
+            assert 1 <= members.size <= mb
+            assert members.sum() <= budget or members.size == 1
+            nxt = np.nonzero(b == j + 1)[0]
+            if nxt.size and members.size < mb:       # the next request did not fit
+                assert members.sum() + fp[nxt[0]] > budget
