@@ -167,6 +167,17 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
                          tm_result* out, void* stream);
 
 /*
+ * tm_match_many -- one template, `count` signals of the plan's N (Algorithm 1
+ * per signal).  xs is a host array of count device pointers; out holds count
+ * results (host or device, as tm_match).  For exact int8 plans (K <= 2^14,
+ * folds of at most 2^13 rows) the correlations of all signals are one banded
+ * Toeplitz product computed with int8 MFMA (the folds split into base-128 int8
+ * digits, exact int32/int64 sums); every result equals tm_match's bit for bit.
+ * Other plans run as tm_match_batch with the plan repeated.
+ */
+tm_status tm_match_many(tm_plan plan, int32_t count, const void* const* xs, tm_result* out, void* stream);
+
+/*
  * tm_match_intermediates -- tm_match that also writes the intermediate vectors
  * (for parity checks): y1[0..M1+K-1) and y2[0..M2+K-1) are the literal folds of
  * Algorithm 1 step 3 (after the fold_store rounding on the real path),

@@ -120,6 +120,28 @@ constexpr int kGfftThreads = 256;                   // literal-fold and final wo
 constexpr int kGfftMaxLog2 = 21;                    // P up to 2^21 (rows of <= 4096)
 constexpr int kGfftMaxQ = 9;                        // column transforms of <= 512
 
+// shared-template correlation as an int8 MFMA GEMM (k_many_*)
+constexpr int kGemmPad = 128;                       // zero bytes around the template
+constexpr int kGemmTile = 64;                       // signals and shifts per workgroup
+constexpr int kGemmMaxLimbs = 3;                    // balanced base-128 digits of the folds
+
+// Arguments of the shared-template kernels (one plan, `count` signals).
+struct ManyArgs {
+  Inst base;              // the plan's instance record (x, out, workspace unset)
+  const void* const* xs;  // device array of count signal pointers
+  tm_result* out;         // count results (device)
+  int* yp;                // bucket sums, yp_stride ints per signal, zero between launches
+  int64_t yp_stride;
+  int8_t* ylimb;          // [2 folds][kGemmMaxLimbs][rows][lp] limbs of the literal folds
+  int64_t rows;           // count rounded up to kGemmTile
+  int32_t lp;             // padded fold length (multiple of 64)
+  int32_t count;
+  int32_t nkb;            // shift blocks per fold: ceil(mb / 64)
+  int32_t pad0;
+  int* maxabs;            // largest |y| of the launch (for the limb count)
+  double* part;           // [2][count][nkb][2]: best value and its shift per block
+};
+
 constexpr int kReduceThreads = 256;
 constexpr int kFinishThreads = 512;     // largest finish workgroup (P / 16 threads)
 constexpr int kFftMid = 5;              // stages of the FFT's twiddle-free middle pass
@@ -148,6 +170,7 @@ hipError_t launch_twiddles(void* tw, int p_log2, int as_double, hipStream_t s);
 hipError_t launch_spectrum(const void* t, int t_dtype, int k, int p_log2, const double* tw64,
                            double* scratch, void* spec, int as_double, int row_log2, hipStream_t s);
 size_t gfft_part_bytes();
+hipError_t launch_many(const ManyArgs& a, hipStream_t s);   // literal folds .. results
 hipError_t launch_gfft(const Inst& one, hipStream_t s);   // literal folds .. result, one instance
 
 }  // namespace tmi

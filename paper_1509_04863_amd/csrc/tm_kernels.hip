@@ -1751,6 +1751,175 @@ hipError_t launch_gfft(const Inst& one, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
+// many signals, one template: correlation as an int8 MFMA GEMM
+// --------------------------------------------------------------------------
+//
+// For signals y_i sharing the template t, r_i[k] = sum_l y_i[l] t[l - k] is a
+// matrix product R = Y T with Y[i][l] the literal folds and T[l][k] = t[l - k]
+// (a banded Toeplitz matrix).  The folds are split into balanced base-128 digits
+// (int8 limbs; |y| <= 128 L), each limb product runs on v_mfma_i32_16x16x64_i8
+// with exact int32 sums, and the limbs are recombined in int64.  The B operand
+// (16 consecutive l of column k) is t[l - k .. l - k + 15]: read aligned from one
+// of 16 byte-shifted copies of the zero-padded template in LDS, so the band's
+// edges come out as zeros.  Each wave produces a 16-signal x 64-shift tile and
+// keeps only its per-signal best (value, lowest shift); a last kernel reduces
+// the blocks in shift order and resolves each signal (steps 7-9).
+
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_many_prep(ManyArgs a) {
+  const Inst& b = a.base;
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y, f = blockIdx.z;
+  const int ma = b.va.m, mb = b.vb.m, K = b.k;
+  const int M = f ? mb : ma;
+  const int64_t L = f ? b.vb.l : b.va.l, N = b.n;
+  const int rho = (int)(N - (L - 1) * M);
+  const bool general = N < (int64_t)max(ma, mb);
+  const int8_t* x = reinterpret_cast<const int8_t*>(a.xs[i]);
+  const GAS int* yp = G(a.yp) + (int64_t)i * a.yp_stride + (f ? ma : 0);
+  int val = 0;
+  if (u < M + K - 1) {
+    const int s = u < M ? u : u - M;
+    const bool wrap = s >= rho, ext = u >= M;
+    const int yb = yp[s];
+    const int xw = G(x)[wrap ? mod_small((int64_t)(s - rho), N, general) : 0];
+    const int x1 = G(x)[ext ? mod_small((int64_t)s + M - rho, N, general) : 0];
+    const int x0 = G(x)[ext ? s : 0];
+    const int bias = b.sfold ? 128 * ((int)L - 1 + (s < rho ? 1 : 0)) : 0;
+    val = yb - bias + (wrap ? xw : 0) + (ext ? x1 - x0 : 0);
+  }
+  if (u < a.lp) {
+    int rest = val;
+#pragma unroll
+    for (int l = 0; l < kGemmMaxLimbs; ++l) {
+      const int digit = l + 1 < kGemmMaxLimbs ? ((rest + 64) & 127) - 64 : rest;
+      rest = (rest - digit) >> 7;
+      G(a.ylimb)[(((int64_t)f * kGemmMaxLimbs + l) * a.rows + i) * a.lp + u] = (int8_t)digit;
+    }
+  }
+  int m = val < 0 ? -val : val;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0 && m) __hip_atomic_fetch_max(G(a.maxabs), m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NL>
+__device__ __forceinline__ void many_gemm_tile(const ManyArgs& a, const int8_t* cs, int lt) {
+  const Inst& b = a.base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int f = blockIdx.z;
+  const int M = f ? b.vb.m : b.va.m, K = b.k;
+  const int k0 = blockIdx.y * kGemmTile;
+  const int sg = blockIdx.x * kGemmTile + wave * 16;
+  const GAS int8_t* rowp[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+    rowp[l] = G(a.ylimb) + (((int64_t)f * kGemmMaxLimbs + l) * a.rows + sg + c) * a.lp + 16 * g;
+  v4i_t acc[NL][4];
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
+  for (int l0 = k0; l0 < k0 + kGemmTile - 1 + K; l0 += 64) {
+    v4i_t bt[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int j = l0 + 16 * g - (k0 + 16 * nt + c) + kGemmPad;   // t index + pad
+      const int sh = (-j) & 15;
+      bt[nt] = *reinterpret_cast<const v4i_t*>(cs + sh * lt + j + sh);
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const v4i_t av = *reinterpret_cast<const GAS v4i_t*>(rowp[l] + l0);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bt[nt], acc[l][nt], 0, 0, 0);
+    }
+  }
+  // lane holds rows (signals) 4g + j and column (shift) c of each 16 x 16 tile
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    VI best{-INFINITY, 0x7fffffff};
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      int64_t r = 0, w = 1;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) { r += w * (int64_t)acc[l][nt][j]; w *= 128; }
+      const int k = k0 + 16 * nt + c;
+      if (k < M && vi_better(VI{(double)r, k}, best)) best = VI{(double)r, k};
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
+      if (vi_better(other, best)) best = other;
+    }
+    const int sig = sg + 4 * g + j;
+    if (c == 0 && sig < a.count) {
+      double* pp = a.part + (((int64_t)f * a.count + sig) * a.nkb + blockIdx.y) * 2;
+      G(pp)[0] = best.v;
+      G(pp)[1] = (double)best.i;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_many_gemm(ManyArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const Inst& b = a.base;
+  const int K = b.k;
+  const int lt = (K + 2 * kGemmPad + 32 + 15) & ~15;
+  int8_t* cs = reinterpret_cast<int8_t*>(lds);
+  const int8_t* t = reinterpret_cast<const int8_t*>(b.t);
+  for (int idx = threadIdx.x; idx < 16 * lt; idx += blockDim.x) {
+    const int sh = idx / lt, j = idx - sh * lt;
+    const int src = j - sh - kGemmPad;
+    cs[idx] = src >= 0 && src < K ? G(t)[src] : (int8_t)0;
+  }
+  __syncthreads();
+  const int M = blockIdx.z ? b.vb.m : b.va.m;
+  if ((int)blockIdx.y * kGemmTile >= M) return;
+  const int mx = *G(a.maxabs);
+  const int nl = mx < 64 ? 1 : (mx < 64 + 128 * 63 ? 2 : 3);
+  if (nl == 1) many_gemm_tile<1>(a, cs, lt);
+  else if (nl == 2) many_gemm_tile<2>(a, cs, lt);
+  else many_gemm_tile<3>(a, cs, lt);
+}
+
+__global__ void __launch_bounds__(64) k_many_finish(ManyArgs a) {
+  __shared__ __align__(16) unsigned char scratch[64 * 16];
+  __shared__ VI fin[2];
+  const int i = blockIdx.x;
+  Inst d = a.base;
+  d.x = a.xs[i];
+  d.out = a.out + i;
+  const int ma = d.va.m, mb = d.vb.m;
+  if (threadIdx.x < 2) {
+    const int f = threadIdx.x;
+    const int nb = ((f ? mb : ma) + kGemmTile - 1) / kGemmTile;
+    const double* pp = a.part + ((int64_t)f * a.count + i) * a.nkb * 2;
+    VI best{-INFINITY, 0x7fffffff};
+    for (int blk = 0; blk < nb; ++blk) {
+      const VI v{G(pp)[2 * blk], (int)G(pp)[2 * blk + 1]};
+      if (vi_better(v, best)) best = v;
+    }
+    fin[f] = best;
+  }
+  int* yp = a.yp + (int64_t)i * a.yp_stride;
+  for (int s = threadIdx.x; s < ma + mb; s += blockDim.x) G(yp)[s] = 0;   // buckets consumed
+  __syncthreads();
+  resolve_and_report<int8_t>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+}
+
+hipError_t launch_many(const ManyArgs& a, hipStream_t s) {
+  const int K = a.base.k;
+  const int lt = (K + 2 * kGemmPad + 32 + 15) & ~15;
+  hipLaunchKernelGGL(k_many_prep, dim3((a.lp + 255) / 256, a.count, 2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_many_gemm, dim3((unsigned)(a.rows / kGemmTile), a.nkb, 2), dim3(256), (size_t)16 * lt, s, a);
+  hipLaunchKernelGGL(k_many_finish, dim3(a.count), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // plan-time kernels
 // --------------------------------------------------------------------------
 

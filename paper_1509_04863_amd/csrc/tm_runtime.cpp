@@ -831,6 +831,104 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   return TM_OK;
 }
 
+// One template, many signals of the plan's N: folds as in a batch, then the
+// correlation as an int8 MFMA GEMM (exact int8 plans with K <= 2^14 and folds
+// of at most 2^13 rows); other plans, or TM_MANY_FFT=1, take tm_match_batch.
+tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_result* out, void* stream) {
+  if (!p || count < 0) return fail(TM_ERR_INVALID, "null plan or negative count");
+  if (count == 0) return TM_OK;
+  if (!xs || !out) return fail(TM_ERR_INVALID, "null argument");
+  tm_status st = check_plan_for_match(p);
+  if (st != TM_OK) return st;
+  for (int32_t i = 0; i < count; ++i) {
+    st = check_x(p, xs[i]);
+    if (st != TM_OK) return fail(st, "signal " + std::to_string(i) + ": " + g_err);
+  }
+  const Core& c = p->core;
+  const bool gemm = c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.mode == MODE_EXACT && c.k <= (1 << 14) &&
+                    std::max(c.va.l, c.vb.l) <= (1 << 13) && env_int("TM_MANY_FFT", 0) == 0;
+  if (!gemm) {
+    std::vector<tm_plan> plans((size_t)count, p);
+    return tm_match_batch(count, plans.data(), xs, out, stream);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dev_out = is_device_pointer(out);
+  const int64_t rows = ceil_div(count, kGemmTile) * kGemmTile;
+  const int32_t lp = (int32_t)(ceil_div((int64_t)std::max(c.ma, c.mb) + c.k + 128, 64) * 64);
+  const int32_t nkb = (int32_t)ceil_div(std::max(c.ma, c.mb), kGemmTile);
+  // layout: [workspaces][limbs][partials][maxabs][results][table][signal pointers]
+  const size_t ws = c.ws_bytes * (size_t)count;
+  const size_t off_limb = align256(ws);
+  const size_t off_part = align256(off_limb + (size_t)2 * kGemmMaxLimbs * rows * lp);
+  const size_t off_max = align256(off_part + (size_t)2 * count * nkb * 2 * sizeof(double));
+  const size_t off_res = align256(off_max + sizeof(int));
+  const size_t off_tab = align256(off_res + (dev_out ? 0 : sizeof(tm_result) * (size_t)count));
+  const size_t tab_bytes = sizeof(Inst) * (size_t)count;
+  const size_t off_xs = off_tab + tab_bytes;
+  const size_t xs_bytes = sizeof(void*) * (size_t)count;
+  const size_t total = off_xs + xs_bytes;
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamPool& pool = g_pools[{p->device, s}];
+  st = ensure_device(pool, total, s);
+  if (st != TM_OK) return st;
+  st = ensure_acc(pool, c.acc_bytes * (size_t)count, s);
+  if (st != TM_OK) return st;
+  int slot = 0;
+  st = ensure_host(pool, tab_bytes + xs_bytes, &slot);
+  if (st != TM_OK) return st;
+  char* base = static_cast<char*>(pool.dev);
+  Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
+  const void** host_xs = reinterpret_cast<const void**>(static_cast<char*>(pool.host[slot]) + tab_bytes);
+  tm_result* dout = dev_out ? out : reinterpret_cast<tm_result*>(base + off_res);
+  for (int32_t i = 0; i < count; ++i) {
+    Inst& in = host_tab[i];
+    fill_inst(p, xs[i], &in);
+    place_workspace(c, base + c.ws_bytes * (size_t)i, static_cast<char*>(pool.acc) + c.acc_bytes * (size_t)i, &in);
+    in.tile_base = c.ntiles * i;
+    in.seg_base = c.nseg * i;
+    in.band_base = c.nband * i;
+    in.red_base = 0;
+    in.out = dout + i;
+    host_xs[i] = xs[i];
+  }
+  TM_HIP(hipMemcpyAsync(base + off_tab, pool.host[slot], tab_bytes + xs_bytes, hipMemcpyHostToDevice, s));
+  TM_HIP(hipEventRecord(pool.staged[slot], s));
+  pool.staged_pending[slot] = true;
+
+  InstTable tab{};
+  tab.table = reinterpret_cast<const Inst*>(base + off_tab);
+  tab.count = count;
+  FoldWork fw;
+  fw.tiles = c.ntiles * count;
+  fw.lds = c.fold_lds;
+  fw.segs = c.nseg * count;
+  fw.bands = c.nband * count;
+  TM_HIP(timed_fold(tab, fw, s));
+  pool.acc_dirty = true;
+  ManyArgs a{};
+  fill_inst(p, nullptr, &a.base);
+  a.xs = reinterpret_cast<const void* const*>(base + off_xs);
+  a.out = dout;
+  a.yp = static_cast<int*>(pool.acc);
+  a.yp_stride = (int64_t)(c.acc_bytes / sizeof(int));
+  a.ylimb = reinterpret_cast<int8_t*>(base + off_limb);
+  a.rows = rows;
+  a.lp = lp;
+  a.count = count;
+  a.nkb = nkb;
+  a.maxabs = reinterpret_cast<int*>(base + off_max);
+  a.part = reinterpret_cast<double*>(base + off_part);
+  TM_HIP(hipMemsetAsync(a.maxabs, 0, sizeof(int), s));
+  TM_HIP(launch_many(a, s));
+  pool.acc_dirty = false;
+  if (!dev_out) {
+    TM_HIP(hipMemcpyAsync(out, dout, sizeof(tm_result) * (size_t)count, hipMemcpyDeviceToHost, s));
+    TM_HIP(hipStreamSynchronize(s));
+  }
+  return TM_OK;
+}
+
 tm_status tm_profile_enable(int on) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_prof_on = on != 0;

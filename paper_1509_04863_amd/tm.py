@@ -27,7 +27,7 @@ EXPORTS = ["tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_i
            "tm_match_batch", "tm_match_intermediates", "tm_status_string", "tm_last_error",
            "tm_version", "tm_profile_enable", "tm_profile_read", "tm_server_create", "tm_server_submit",
            "tm_server_poll", "tm_server_wait", "tm_server_get_stats", "tm_server_destroy",
-           "tm_admit_batches"]
+           "tm_admit_batches", "tm_match_many"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -115,6 +115,8 @@ def lib():
         L.tm_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
         L.tm_server_destroy.argtypes = [vp]
         L.tm_admit_batches.argtypes = [i32, i64p, ctypes.c_int64, i32, ctypes.POINTER(i32)]
+        L.tm_match_many.argtypes = [vp, i32, ctypes.POINTER(vp), vp, vp]
+        L.tm_match_many.restype = ctypes.c_int
         for fn in ("tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_wait",
                    "tm_server_get_stats", "tm_server_destroy", "tm_admit_batches"):
             getattr(L, fn).restype = ctypes.c_int
@@ -428,3 +430,26 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Many:
+    """One plan, a fixed list of signals (tm_match_many); run() enqueues with
+    results in a device buffer, match() returns host results."""
+
+    def __init__(self, plan: Plan, xs: Sequence):
+        for x in xs:
+            _check_signal(plan, x)
+        self.plan, self.xs = plan, list(xs)
+        self.count = len(self.xs)
+        self._x = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in self.xs])
+
+    def run(self, out, stream=None):
+        """out: CUDA uint8 tensor of 48*count bytes (device results, no wait)."""
+        _check(lib().tm_match_many(self.plan.handle, self.count, self._x, out.data_ptr(),
+                                   _stream_handle(stream)))
+
+    def match(self, stream=None):
+        res = (Result * self.count)()
+        _check(lib().tm_match_many(self.plan.handle, self.count, self._x, ctypes.addressof(res),
+                                   _stream_handle(stream)))
+        return [MatchResult(*_row(r)) for r in res]

@@ -1,0 +1,85 @@
+"""One template, many signals: the int8 MFMA GEMM correlation (tm_match_many)
+must give every signal the result tm_match gives it, bit for bit, and the
+oracle's shift, residues and peaks."""
+
+import numpy as np
+import pytest
+
+from oracle import ftm as O
+from paper_1509_04863_amd import datagen as G
+from paper_1509_04863_amd import tm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _case(*a):
+    print("case:", *a, flush=True)
+
+
+def _check_many(insts, plan, oracle_every=7):
+    xs = [torch.from_numpy(s.x).cuda() for s in insts]
+    many = tm.Many(plan, xs).match()
+    single = [tm.match(plan, x) for x in xs]
+    for a, b in zip(many, single):
+        assert a == b
+    for s, r in list(zip(insts, many))[::oracle_every]:
+        ref = O.ftm(s.x, s.t, plan.m1, plan.m2)
+        assert (r.shift, r.m1_tilde, r.m2_tilde, r.n_candidates) == \
+            (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
+        assert r.peak1 == float(ref.peak1) and r.peak2 == float(ref.peak2)
+        assert r.flags & tm.TM_R_EXACT
+    return many
+
+
+@pytest.mark.parametrize("count,n,k,flip", [(100, 1 << 16, 512, 0.0), (64, 1 << 18, 1024, 0.05),
+                                            (37, 50000, 300, 0.1), (130, 1 << 15, 1000, 0.0)])
+def test_shared_template_gemm(count, n, k, flip):
+    insts = G.config5b_batch(count=count, n=n, k=k, flip_frac=flip)
+    plan = tm.Plan(insts[0].t, n=n)
+    _case("many", count, n, k, flip)
+    many = _check_many(insts, plan)
+    if flip == 0.0:
+        hits = sum(int(r.shift == s.shift) for r, s in zip(many, insts))
+        print("planted recovered", hits, "/", count)
+
+
+def test_general_int8_values_need_three_limbs():
+    rng = np.random.default_rng(12)
+    n, k = 3 << 16, 700
+    t = rng.integers(-128, 128, k).astype(np.int8)
+    insts = []
+    for i in range(20):
+        x = rng.integers(-128, 128, n).astype(np.int8)
+        if i % 2:
+            x[: n // 2] = 127          # long runs: fold values far above 8128
+        insts.append(G.Instance(x=x, t=t, shift=-1, config_id=0, index=i))
+    plan = tm.Plan(t, n=n)
+    _case("many general")
+    _check_many(insts, plan, oracle_every=5)
+
+
+def test_explicit_moduli_and_ties():
+    n, k = 30000, 200
+    t = np.ones(k, dtype=np.int8)
+    insts = [G.Instance(x=np.ones(n, dtype=np.int8), t=t, shift=-1, config_id=0, index=0)]
+    insts += G.config5b_batch(count=9, n=n, k=k)
+    for s in insts[1:]:
+        s.t = t
+    for m1, m2 in ((0, 0), (211, 307)):
+        plan = tm.Plan(t, n=n, m1=m1, m2=m2)
+        _case("many moduli", m1, m2)
+        _check_many(insts, plan, oracle_every=1)
+
+
+def test_fft_and_gemm_paths_agree(monkeypatch):
+    insts = G.config5b_batch(count=48, n=1 << 16, k=512, flip_frac=0.05)
+    plan = tm.Plan(insts[0].t, n=1 << 16)
+    xs = [torch.from_numpy(s.x).cuda() for s in insts]
+    gemm = tm.Many(plan, xs).match()
+    monkeypatch.setenv("TM_MANY_FFT", "1")
+    fft = tm.Many(plan, xs).match()
+    assert gemm == fft
