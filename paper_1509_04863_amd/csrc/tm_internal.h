@@ -138,7 +138,7 @@ struct ManyArgs {
   int32_t count;
   int32_t nkb;            // shift blocks per fold: ceil(mb / 64)
   int32_t pad0;
-  int* maxabs;            // largest |y| of the launch (for the limb count)
+  int* maxabs;            // [2][count] largest |y| per fold and signal (limb counts)
   double* part;           // [2][count][nkb][2]: best value and its shift per block
 };
 

@@ -1798,10 +1798,17 @@ __global__ void __launch_bounds__(256) k_many_prep(ManyArgs a) {
       G(a.ylimb)[(((int64_t)f * kGemmMaxLimbs + l) * a.rows + i) * a.lp + u] = (int8_t)digit;
     }
   }
+  // largest |y| of this fold and signal: wave, then workgroup, then one atomic
+  __shared__ int wmax[4];
   int m = val < 0 ? -val : val;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0 && m) __hip_atomic_fetch_max(G(a.maxabs), m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    if (m) __hip_atomic_fetch_max(G(a.maxabs) + (int64_t)f * a.count + i, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 template <int NL>
@@ -1876,9 +1883,18 @@ __global__ void __launch_bounds__(256) k_many_gemm(ManyArgs a) {
     cs[idx] = src >= 0 && src < K ? G(t)[src] : (int8_t)0;
   }
   __syncthreads();
+  // limbs needed by this workgroup's 64 signals
+  __shared__ int tmax;
+  if (threadIdx.x == 0) tmax = 0;
+  __syncthreads();
+  if (threadIdx.x < kGemmTile) {
+    const int sig = blockIdx.x * kGemmTile + threadIdx.x;
+    if (sig < a.count) atomicMax(&tmax, G(a.maxabs)[(int64_t)blockIdx.z * a.count + sig]);
+  }
+  __syncthreads();
   const int M = blockIdx.z ? b.vb.m : b.va.m;
   if ((int)blockIdx.y * kGemmTile >= M) return;
-  const int mx = *G(a.maxabs);
+  const int mx = tmax;
   const int nl = mx < 64 ? 1 : (mx < 64 + 128 * 63 ? 2 : 3);
   if (nl == 1) many_gemm_tile<1>(a, cs, lt);
   else if (nl == 2) many_gemm_tile<2>(a, cs, lt);

@@ -861,7 +861,7 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   const size_t off_limb = align256(ws);
   const size_t off_part = align256(off_limb + (size_t)2 * kGemmMaxLimbs * rows * lp);
   const size_t off_max = align256(off_part + (size_t)2 * count * nkb * 2 * sizeof(double));
-  const size_t off_res = align256(off_max + sizeof(int));
+  const size_t off_res = align256(off_max + sizeof(int) * 2 * (size_t)count);
   const size_t off_tab = align256(off_res + (dev_out ? 0 : sizeof(tm_result) * (size_t)count));
   const size_t tab_bytes = sizeof(Inst) * (size_t)count;
   const size_t off_xs = off_tab + tab_bytes;
@@ -919,7 +919,7 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   a.nkb = nkb;
   a.maxabs = reinterpret_cast<int*>(base + off_max);
   a.part = reinterpret_cast<double*>(base + off_part);
-  TM_HIP(hipMemsetAsync(a.maxabs, 0, sizeof(int), s));
+  TM_HIP(hipMemsetAsync(a.maxabs, 0, sizeof(int) * 2 * (size_t)count, s));
   TM_HIP(launch_many(a, s));
   pool.acc_dirty = false;
   if (!dev_out) {
