@@ -413,21 +413,6 @@ __device__ __forceinline__ void seg_read_row(const unsigned char* lds, int abase
 }
 
 template <int NSL>
-__device__ __forceinline__ void seg_accumulate(const uint32_t (&w0)[NSL], const uint32_t (&w1)[NSL],
-                                               uint32_t sel_even, uint32_t top_even, uint32_t top_odd,
-                                               uint32_t (&lo)[NSL], uint32_t (&hi)[NSL]) {
-  const uint32_t sel_odd = sel_even + 0x00010001u;
-#pragma unroll
-  for (int s = 0; s < NSL; ++s) {
-    uint32_t e = __builtin_amdgcn_perm(w1[s], w0[s], sel_even);   // bytes c, c+2 of {w0, w1}
-    uint32_t o = __builtin_amdgcn_perm(w1[s], w0[s], sel_odd);    // bytes c+1, c+3
-    if (s == NSL - 1) { e &= top_even; o &= top_odd; }             // buckets past M
-    lo[s] += e;
-    hi[s] += o;
-  }
-}
-
-template <int NSL>
 __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, unsigned char* lds) {
   const int tid = threadIdx.x;
   const int u0 = tid & (kSegHalf - 1);
@@ -438,7 +423,7 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
   g.delta = (int)(xa & 15);
   g.nch = (N + g.delta + 15) >> 4;
   g.c_begin = (int64_t)seg * d.seg_chunks;
-  g.c_end = min(g.nch, g.c_begin + d.seg_chunks);
+  g.c_end = seg == d.nseg - 1 ? g.nch : min(g.nch, g.c_begin + d.seg_chunks);   // the last takes the tail
   const int64_t mmax = max(d.va.m, d.vb.m);
   g.c_stage = g.c_end + (mmax + 16 + 15) / 16;
   const int nproc = g.c_end > g.c_begin ? (int)((g.c_end - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks) : 0;
@@ -460,9 +445,15 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
 #pragma unroll
   for (int s = 0; s < NSL; ++s) { lo[s] = 0; hi[s] = 0; }
 
+  // prologue: the first two pieces' loads in flight together
   uint4 v[kSegLoads];
-  if (nstage > 0) { seg_load(g, 0, v); seg_store(g, N, 0, v, lds); }
-  if (nstage > 1) { seg_load(g, 1, v); seg_store(g, N, 1, v, lds); }
+  {
+    uint4 v1[kSegLoads];
+    if (nstage > 0) seg_load(g, 0, v);
+    if (nstage > 1) seg_load(g, 1, v1);
+    if (nstage > 0) seg_store(g, N, 0, v, lds);
+    if (nstage > 1) seg_store(g, N, 1, v1, lds);
+  }
   if (nstage > 2) seg_load(g, 2, v);
   __syncthreads();
 
@@ -470,24 +461,40 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
     const int64_t Bp = B0 + (int64_t)j * kSegPiece;
     const int64_t Bend = min(Bp + kSegPiece, B1);
     const int ring = (j & 1) * kSegPiece;              // LDS offset of byte b: ring + (b - Bp)
-    if (k < L && rb < Bend) {
-      uint32_t a0[NSL], a1[NSL], b0[NSL], b1[NSL];
-      int off = ring + (int)(rb - Bp);
-      seg_read_row<NSL>(lds, off & ~3, u0, a0, a1);
-      while (true) {
-        const uint32_t c = (uint32_t)off & 3u;
-        const uint32_t sel = 0x0C000C00u | c | ((c + 2u) << 16);
-        const int64_t k1 = k + 1, rb1 = rb + M;
-        const bool more = k1 < L && rb1 < Bend;
-        const int off1 = ring + (int)(rb1 - Bp);
-        if (more) seg_read_row<NSL>(lds, off1 & ~3, u0, b0, b1);
-        seg_accumulate<NSL>(a0, a1, sel, top_even, top_odd, lo, hi);
-        k = k1; rb = rb1; off = off1;
-        if (!more) break;
+    // rows starting in this piece, G at a time (all their reads in flight
+    // together); rows past the piece's end read offset 0 with an all-zero
+    // byte selector
+    constexpr int GR = NSL <= 2 ? 4 : (NSL <= 4 ? 2 : 1);
+    while (k < L && rb < Bend) {
+      uint32_t w0[GR][NSL], w1[GR][NSL], sel[GR];
 #pragma unroll
-        for (int s = 0; s < NSL; ++s) { a0[s] = b0[s]; a1[s] = b1[s]; }
+      for (int r = 0; r < GR; ++r) {
+        const int64_t rr = rb + (int64_t)r * M;
+        const bool ok = k + r < L && rr < Bend;
+        const int off = ok ? ring + (int)(rr - Bp) : 0;
+        const uint32_t c = (uint32_t)off & 3u;
+        sel[r] = ok ? (0x0C000C00u | c | ((c + 2u) << 16)) : 0x0C0C0C0Cu;
+        seg_read_row<NSL>(lds, off & ~3, u0, w0[r], w1[r]);
       }
+#pragma unroll
+      for (int r = 0; r < GR; ++r) {
+        const uint32_t se = sel[r];
+        const uint32_t so = se == 0x0C0C0C0Cu ? se : se + 0x00010001u;
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) {
+          uint32_t e = __builtin_amdgcn_perm(w1[r][s], w0[r][s], se);
+          uint32_t o = __builtin_amdgcn_perm(w1[r][s], w0[r][s], so);
+          if (s == NSL - 1) { e &= top_even; o &= top_odd; }
+          lo[s] += e;
+          hi[s] += o;
+        }
+      }
+      k += GR;
+      rb += (int64_t)GR * M;
     }
+    // the group may have stepped past the piece: back to the first row not yet folded
+    while (k > 0 && (k - 1 >= L || (k - 1) * M + g.delta >= Bend)) --k;
+    rb = k * M + g.delta;
     __syncthreads();
     if (j + 2 < nstage) {
       seg_store(g, N, j + 2, v, lds);

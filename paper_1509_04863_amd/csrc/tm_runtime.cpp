@@ -93,6 +93,11 @@ View make_view(int64_t n, int64_t m, int eb) {
   return v;
 }
 
+// Segments of the streaming int8 fold: x spans at most N/16 + 1 chunks at any
+// alignment; the last segment also takes the one chunk a misaligned x adds
+// (so it holds at most seg_chunks + 1 chunks, within the row limit's margin).
+int32_t segments_of(int64_t n, int64_t sc) { return (int32_t)std::max<int64_t>(1, ceil_div((n + 15) / 16, sc)); }
+
 // Band view of a 4-byte signal: 64-column bands of R rows, R a multiple of
 // kBandUnroll chosen for about 2048 tasks (TM_BAND_ROWS overrides).
 View make_band_view(int64_t n, int64_t m) {
@@ -129,6 +134,15 @@ struct Core {
   size_t fold_lds = 0, finish_lds = 0;
   int fft_in_lds = 1;
 };
+
+// Segment length for a launch: long segments when the launch holds much
+// data (one segment per CU and a few workgroups' worth of bytes amortises
+// each segment's prologue and flush), never above the row limit.
+int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
+  const int64_t cap = std::max<int64_t>(1, (int64_t)kSegMaxRows * std::min(c.ma, c.mb) / 16 - 1);
+  const int64_t want = launch_bytes / 16 / (256 * 8);
+  return std::min(cap, std::max<int64_t>(c.seg_chunks, want));
+}
 
 tm_status compute_core(const tm_plan_desc* d, Core* c) {
   if (!d) return fail(TM_ERR_INVALID, "null plan descriptor");
@@ -219,14 +233,13 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   const int64_t mmin = std::min(c->ma, c->mb), mmax = std::max(c->ma, c->mb);
   if (d->x_dtype == TM_I8 && mmin >= kSegMinM && mmax <= kSegMaxM && ceil_div(d->n, mmin) < (1 << 23) &&
       env_int("TM_FOLD_STREAM", 1) != 0) {
-    const int64_t cap = kSegMaxRows * mmin / 16;
+    const int64_t cap = std::max<int64_t>(1, kSegMaxRows * mmin / 16 - 1);
     int64_t sc = env_int("TM_SEG_BYTES", 0) / 16;
     if (sc <= 0) sc = std::max<int64_t>(ceil_div(d->n, 512 * 16), 4096);
     sc = std::max<int64_t>(1, std::min(sc, cap));
-    const int64_t nch = (d->n + 15) / 16 + 1;            // any alignment of x
     c->sfold = 1;
     c->seg_chunks = (int32_t)sc;
-    c->nseg = (int32_t)ceil_div(nch, sc);
+    c->nseg = segments_of(d->n, sc);
     c->ntiles = 0;
   }
   if (d->x_dtype == TM_I8 && ceil_div(d->n, std::min(c->ma, c->mb)) > (int64_t(1) << 24))
@@ -735,9 +748,11 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
 
   // layout: [instance workspaces][results if host out][table][lists]
   std::vector<size_t> ws_off(count), acc_off(count);
+  std::vector<int32_t> seg_chunks(count), nseg(count);
   size_t ws = 0, accb = 0;
-  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0;
+  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, launch_bytes = 0;
   size_t fold_lds = 0;
+  for (int32_t i = 0; i < count; ++i) launch_bytes += plans[i]->core.n * dtype_bytes(plans[i]->core.x_dtype);
   for (int32_t i = 0; i < count; ++i) {
     const Core& c = plans[i]->core;
     ws_off[i] = ws;
@@ -745,7 +760,13 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     acc_off[i] = accb;
     accb += c.acc_bytes;
     tiles += c.ntiles;
-    segs += c.nseg;
+    seg_chunks[i] = c.seg_chunks;
+    nseg[i] = c.nseg;
+    if (c.sfold) {
+      seg_chunks[i] = (int32_t)launch_seg_chunks(c, launch_bytes);
+      nseg[i] = segments_of(c.n, seg_chunks[i]);
+    }
+    segs += nseg[i];
     bands += c.nband;
     chunks += c.nred;
     fold_lds = std::max(fold_lds, c.fold_lds);
@@ -788,9 +809,11 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     in.tile_base = tile_base;
     in.red_base = red_base;
     in.seg_base = seg_base;
+    in.seg_chunks = seg_chunks[i];
+    in.nseg = nseg[i];
     in.band_base = band_base;
     tile_base += p->core.ntiles;
-    seg_base += p->core.nseg;
+    seg_base += nseg[i];
     band_base += p->core.nband;
     red_base += p->core.nred;
     in.out = dev_out ? out + i : reinterpret_cast<tm_result*>(base + off_res) + i;
@@ -881,12 +904,16 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
   const void** host_xs = reinterpret_cast<const void**>(static_cast<char*>(pool.host[slot]) + tab_bytes);
   tm_result* dout = dev_out ? out : reinterpret_cast<tm_result*>(base + off_res);
+  const int32_t sc = c.sfold ? (int32_t)launch_seg_chunks(c, c.n * dtype_bytes(c.x_dtype) * count) : c.seg_chunks;
+  const int32_t ns = c.sfold ? segments_of(c.n, sc) : c.nseg;
   for (int32_t i = 0; i < count; ++i) {
     Inst& in = host_tab[i];
     fill_inst(p, xs[i], &in);
     place_workspace(c, base + c.ws_bytes * (size_t)i, static_cast<char*>(pool.acc) + c.acc_bytes * (size_t)i, &in);
     in.tile_base = c.ntiles * i;
-    in.seg_base = c.nseg * i;
+    in.seg_chunks = sc;
+    in.nseg = ns;
+    in.seg_base = ns * i;
     in.band_base = c.nband * i;
     in.red_base = 0;
     in.out = dout + i;
@@ -902,7 +929,7 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   FoldWork fw;
   fw.tiles = c.ntiles * count;
   fw.lds = c.fold_lds;
-  fw.segs = c.nseg * count;
+  fw.segs = ns * count;
   fw.bands = c.nband * count;
   TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;

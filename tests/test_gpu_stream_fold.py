@@ -91,7 +91,7 @@ def test_row_limit_per_segment(monkeypatch):
     x = np.full(n, 127, dtype=np.int8)
     t = np.ones(k, dtype=np.int8)
     info = _plan_kind(n, k)
-    assert info["fold_segments"] == -(-(n // 16 + 1) // (256 * info["m1"] // 16))
+    assert info["fold_segments"] == -(-((n + 15) // 16) // (256 * info["m1"] // 16 - 1))
     _case("row limit")
     assert_exact_parity(x, t)
 
