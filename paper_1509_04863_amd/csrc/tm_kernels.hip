@@ -369,14 +369,20 @@ struct SegGeom {
   int64_t c_begin;   // first chunk of the segment
   int64_t c_end;     // one past its last chunk
   int64_t c_stage;   // one past the last chunk staged (segment plus look-ahead)
+  // the same bounds relative to c_begin, in 32 bits
+  uintptr_t xseg;    // address of chunk c_begin
+  int stage_rel;     // chunks staged
+  int x_rel;         // chunks of x from c_begin on (clamped)
+  int first_rel;     // chunk 0 of x relative to c_begin (edge: bytes before x), or -1
+  int last_rel;      // last chunk of x relative to c_begin (edge: bytes after x), or -1
 };
 
 __device__ __forceinline__ void seg_load(const SegGeom& g, int piece, uint4 (&v)[kSegLoads]) {
 #pragma unroll
   for (int u = 0; u < kSegLoads; ++u) {
-    const int64_t c = g.c_begin + (int64_t)piece * kSegPieceChunks + threadIdx.x + u * kSegThreads;
-    const bool ok = c < g.c_stage && c < g.nch;
-    v[u] = gload16(g.xc + (ok ? (uintptr_t)c * 16 : 0));    // chunk 0 always holds x[0]
+    const int cr = piece * kSegPieceChunks + (int)threadIdx.x + u * kSegThreads;
+    const bool ok = cr < g.stage_rel && cr < g.x_rel;
+    v[u] = gload16(ok ? g.xseg + (uintptr_t)(unsigned)cr * 16 : g.xc);    // chunk 0 always holds x[0]
   }
 }
 
@@ -385,15 +391,16 @@ __device__ __forceinline__ void seg_store(const SegGeom& g, int64_t n, int piece
   const int half = piece & 1;
 #pragma unroll
   for (int u = 0; u < kSegLoads; ++u) {
-    const int cl = threadIdx.x + u * kSegThreads;
-    const int64_t c = g.c_begin + (int64_t)piece * kSegPieceChunks + cl;
-    if (c >= g.c_stage) continue;
+    const int cl = (int)threadIdx.x + u * kSegThreads;
+    const int cr = piece * kSegPieceChunks + cl;
+    if (cr >= g.stage_rel) continue;
     uint4 w = make_uint4(0, 0, 0, 0);
-    if (c < g.nch) {
+    if (cr < g.x_rel) {
       w = make_uint4(v[u].x ^ 0x80808080u, v[u].y ^ 0x80808080u, v[u].z ^ 0x80808080u, v[u].w ^ 0x80808080u);
-      const int64_t b0 = c * 16;
-      if (b0 < g.delta || b0 + 16 > g.delta + n)
+      if (cr == g.first_rel || cr == g.last_rel) {
+        const int64_t b0 = (g.c_begin + cr) * 16;
         w = keep_bytes(w, (int)max((int64_t)0, g.delta - b0), (int)min((int64_t)16, g.delta + n - b0));
+      }
     }
     *reinterpret_cast<uint4*>(lds + half * kSegPiece + cl * 16) = w;
     if (half == 0 && cl * 16 < kSegLook) *reinterpret_cast<uint4*>(lds + 2 * kSegPiece + cl * 16) = w;
@@ -426,6 +433,11 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
   g.c_end = seg == d.nseg - 1 ? g.nch : min(g.nch, g.c_begin + d.seg_chunks);   // the last takes the tail
   const int64_t mmax = max(d.va.m, d.vb.m);
   g.c_stage = g.c_end + (mmax + 16 + 15) / 16;
+  g.xseg = g.xc + (uintptr_t)g.c_begin * 16;
+  g.stage_rel = (int)(g.c_stage - g.c_begin);
+  g.x_rel = (int)min(g.nch - g.c_begin, (int64_t)1 << 30);
+  g.first_rel = g.c_begin == 0 ? 0 : -1;
+  g.last_rel = g.nch - 1 - g.c_begin < g.stage_rel ? (int)(g.nch - 1 - g.c_begin) : -1;
   const int nproc = g.c_end > g.c_begin ? (int)((g.c_end - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks) : 0;
   const int nstage = g.c_end > g.c_begin ? (int)((g.c_stage - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks) : 0;
 
@@ -461,40 +473,41 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
     const int64_t Bp = B0 + (int64_t)j * kSegPiece;
     const int64_t Bend = min(Bp + kSegPiece, B1);
     const int ring = (j & 1) * kSegPiece;              // LDS offset of byte b: ring + (b - Bp)
-    // rows starting in this piece, G at a time (all their reads in flight
-    // together); rows past the piece's end read offset 0 with an all-zero
+    // rows starting in this piece (first byte in [Bp, Bend), row < L): counted
+    // once, then folded G at a time with 32-bit offsets, all reads of a group
+    // in flight together; rows past the count read offset 0 with an all-zero
     // byte selector
     constexpr int GR = NSL <= 2 ? 4 : (NSL <= 4 ? 2 : 1);
-    while (k < L && rb < Bend) {
+    int nr = 0;
+    if (k < L && rb < Bend) nr = (int)min(L - k, (Bend - rb + M - 1) / M);
+    const int M32 = (int)M;
+    int rel = ring + (int)(rb - Bp);             // LDS offset of the next row's first byte
+    for (int r = 0; r < nr; r += GR) {
       uint32_t w0[GR][NSL], w1[GR][NSL], sel[GR];
 #pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        const int64_t rr = rb + (int64_t)r * M;
-        const bool ok = k + r < L && rr < Bend;
-        const int off = ok ? ring + (int)(rr - Bp) : 0;
-        const uint32_t c = (uint32_t)off & 3u;
-        sel[r] = ok ? (0x0C000C00u | c | ((c + 2u) << 16)) : 0x0C0C0C0Cu;
-        seg_read_row<NSL>(lds, off & ~3, u0, w0[r], w1[r]);
+      for (int q = 0; q < GR; ++q) {
+        const bool ok = r + q < nr;
+        const int off = ok ? rel + q * M32 : 0;
+        sel[q] = ok ? 0x0C020C00u + ((uint32_t)off & 3u) * 0x00010001u : 0x0C0C0C0Cu;
+        seg_read_row<NSL>(lds, off & ~3, u0, w0[q], w1[q]);
       }
 #pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        const uint32_t se = sel[r];
-        const uint32_t so = se == 0x0C0C0C0Cu ? se : se + 0x00010001u;
+      for (int q = 0; q < GR; ++q) {
+        const uint32_t se = sel[q];                                                  // bytes c, c + 2
+        const uint32_t so = se == 0x0C0C0C0Cu ? se : se + 0x00010001u;               // bytes c + 1, c + 3
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {
-          uint32_t e = __builtin_amdgcn_perm(w1[r][s], w0[r][s], se);
-          uint32_t o = __builtin_amdgcn_perm(w1[r][s], w0[r][s], so);
+          uint32_t e = __builtin_amdgcn_perm(w1[q][s], w0[q][s], se);
+          uint32_t o = __builtin_amdgcn_perm(w1[q][s], w0[q][s], so);
           if (s == NSL - 1) { e &= top_even; o &= top_odd; }
           lo[s] += e;
           hi[s] += o;
         }
       }
-      k += GR;
-      rb += (int64_t)GR * M;
+      rel += GR * M32;
     }
-    // the group may have stepped past the piece: back to the first row not yet folded
-    while (k > 0 && (k - 1 >= L || (k - 1) * M + g.delta >= Bend)) --k;
-    rb = k * M + g.delta;
+    k += nr;
+    rb += (int64_t)nr * M;
     __syncthreads();
     if (j + 2 < nstage) {
       seg_store(g, N, j + 2, v, lds);
