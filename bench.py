@@ -1,13 +1,17 @@
 """Benchmark of the MI355X template matcher.
 
-Default workload: one large instance per step (N = 2^22 +-1 values stored as
-fp32, K = 4096, 10% template sign flips, M1 = 4096, M2 = 4097), one match per
-launch sequence, inputs resident in HBM and rotated over >= 1 GiB of distinct
-signals so the 256 MB memory-side cache does not serve them.
+Default workload (config2): one large instance per step (N = 2^22 +-1 values
+stored as fp32, K = 4096, 10% template sign flips, M1 = 4096, M2 = 4097), one
+match per launch sequence, sequences issued round-robin over a few streams,
+inputs resident in HBM and rotated over >= 1 GiB of distinct signals so the
+256 MB memory-side cache does not serve them.  Other workloads: config1
+(N = 2^16 int8), config3 (4096 uneven int8 instances per launch), config4
+(request server: open-loop p50/p99 and saturation vs plain launch), config5b
+(1024 signals sharing one template: int8 MFMA GEMM vs the FFT path).
 
 Prints one JSON line: whole-job matches/s, the fold kernel's achieved HBM
-bandwidth against the 8 TB/s peak (timed with HIP events around every fold
-launch of the timed region), and the CPU oracle timed on a bounded sample of
+bandwidth against the 8 TB/s peak (HIP events around every fold launch of a
+separate single-stream run), and the CPU oracle timed on a bounded sample of
 the same workload.
 """
 
@@ -23,6 +27,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per fold launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
+# a plain copy's readings (profiles/hbm_traffic_folds_config2_config3.txt);
+# valid for the fold kernels as those counters saw them
+TRAFFIC_BYTES = {"config2": 1.829e7, "config3": 1.561e9}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -30,7 +39,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config5b"])
+                    choices=["config1", "config2", "config3", "config4", "config5b", "copy"])
     ap.add_argument("--pool", type=int, default=96, help="device signals in the config4 pool")
     ap.add_argument("--templates", type=int, default=384, help="distinct config4 requests (plans)")
     ap.add_argument("--rate", type=float, default=20000.0, help="config4 offered load, requests/s")
@@ -40,6 +49,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the fold-kernel event timing")
+    ap.add_argument("--streams", type=int, default=4, help="streams for single-match launch sequences")
+    ap.add_argument("--traffic-bytes", type=float, default=None,
+                    help="HBM bytes per fold launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled)")
     return ap.parse_args()
 
 
@@ -104,8 +116,10 @@ def run_batched(args):
     if fold_n:
         avg_s = fold_ms / fold_n / 1e3
         achieved = x_bytes / avg_s / 1e9
-        line["roofline"] = {"kernel": "k_fold", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        line["roofline"] = {"kernel": "k_fold_s8", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                            "traffic": args.traffic_bytes if args.traffic_bytes is not None
+                            else TRAFFIC_BYTES.get("config3"),
                             "avg_kernel_us": avg_s * 1e6, "algorithmic_bytes_per_launch": x_bytes}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(lambda i: insts[i], args.cpu_seconds, results)
@@ -276,8 +290,8 @@ def cpu_baseline(make, budget_s, gpu_results):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the matcher would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the matcher has no multi-GPU path (matches are "
+              "independent; a deployment runs one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -287,6 +301,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.config == "copy":          # calibration for rocprofv3 FETCH_SIZE / WRITE_SIZE
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(max(1, args.steps)):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 4, "launches": max(1, args.steps)}))
+        return
     if args.config == "config3":
         run_batched(args)
         return
@@ -304,26 +326,46 @@ def main():
     plans = [tm.Plan(s.t, n=s.n, fold_mult=wl["fold_mult"], flags=wl["flags"]) for s in insts]
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
     out = torch.zeros(48 * rot, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
-    for i in range(args.warmup):
-        j = i % rot
-        tm.match_into(plans[j], xs[j], out, j, stream)
-    torch.cuda.synchronize()
+    main_stream = torch.cuda.current_stream()
+    # independent single-match launch sequences, round-robin over the streams:
+    # one match's one-workgroup finish overlaps the next match's fold
+    streams = [torch.cuda.Stream() for _ in range(max(1, args.streams))]
 
+    def issue(count, first_i=0):
+        for i in range(count):
+            j = (first_i + i) % rot
+            tm.match_into(plans[j], xs[j], out, j, streams[i % len(streams)])
+
+    def fence_in():
+        for st in streams:
+            st.wait_stream(main_stream)
+
+    def fence_out():
+        for st in streams:
+            main_stream.wait_stream(st)
+
+    fence_in()
+    issue(args.warmup)
+    fence_out()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(main_stream)
+    fence_in()
+    issue(args.steps)
+    fence_out()
+    stop.record(main_stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+
+    # fold kernel alone: HIP events around every fold launch, one stream, after the timed run
+    fold_ms, fold_n = (0.0, 0)
     if not args.no_profile:
         tm.profile_read(reset=True)
         tm.profile_enable(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for i in range(args.steps):
-        j = i % rot
-        tm.match_into(plans[j], xs[j], out, j, stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    fold_ms, fold_n = (0.0, 0)
-    if not args.no_profile:
+        for i in range(min(args.steps, 100)):
+            j = i % rot
+            tm.match_into(plans[j], xs[j], out, j, main_stream)
+        torch.cuda.synchronize()
         tm.profile_enable(False)
         fold_ms, fold_n = tm.profile_read(reset=True)
 
@@ -332,6 +374,7 @@ def main():
     ms_per_step = total_ms / args.steps
     value = args.steps / (total_ms / 1e3)
     info = plans[0].info
+    p_len = 1 << info["fft_log2"]
     line = {
         "metric": "template matches/sec + fold GB/s vs HBM peak; served p50/p99 vs plain launch",
         "value": value, "unit": "matches/s", "n_gpus": 1, "steps": args.steps,
@@ -340,17 +383,20 @@ def main():
         "dtype": "i32 fold, f64 fft" if info["exact"] else "f32",
         "data": "synthetic",
         "config": {"workload": args.config + ": " + wl["desc"], "n": first.n, "k": first.k,
-                   "m1": info["m1"], "m2": info["m2"], "fft_len": 1 << info["fft_log2"],
+                   "m1": info["m1"], "m2": info["m2"], "fft_len": p_len,
                    "x_dtype": str(first.x.dtype), "signals_rotated": rot,
-                   "rotated_bytes": rot * x_bytes},
+                   "rotated_bytes": rot * x_bytes, "streams": len(streams),
+                   "fold_kernel": "k_fold_band" if info["fold_bands"] else
+                                  ("k_fold_s8" if info["fold_segments"] else "k_fold")},
         "planted_recovered": "%d/%d" % (planted_ok, rot),
     }
     if fold_n:
         avg_s = fold_ms / fold_n / 1e3
         achieved = x_bytes / avg_s / 1e9
-        line["roofline"] = {"kernel": "k_fold", "bound": "hbm", "achieved": achieved,
+        line["roofline"] = {"kernel": line["config"]["fold_kernel"], "bound": "hbm", "achieved": achieved,
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                            "traffic": None, "avg_kernel_us": avg_s * 1e6,
+                            "traffic": args.traffic_bytes if args.traffic_bytes is not None
+                            else TRAFFIC_BYTES.get(args.config), "avg_kernel_us": avg_s * 1e6,
                             "algorithmic_bytes_per_launch": x_bytes}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl["make"], args.cpu_seconds, results)
