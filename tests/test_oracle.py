@@ -375,3 +375,12 @@ def _binom_band(n, p, alpha):
         acc += pmf[hi]
         hi -= 1
     return lo, hi
+
+
+def test_section5_script_bound_matches_oracle():
+    """The experiment script restates Theorem 5's bound; both forms agree."""
+    from paper_1509_04863_amd import tables
+    for p in range(20, 28):
+        n, k = 1 << p, (1 << p) >> 10
+        assert abs(tables.thm5_success_bound(n, k, k, k + 1) - O.thm5_success_bound(n, k, k, k + 1)) < 1e-12
+    assert tables.thm5_success_bound(1 << 27, 1 << 17, 1 << 17, (1 << 17) + 1) > 0.9
