@@ -60,6 +60,16 @@ typedef enum {
                                 dtypes are TM_I8.  Precondition: every partial sum of x
                                 fits in int32 (e.g. |x_i| * ceil(N/M) < 2^31). */
 #define TM_F_REAL       0x2u /* force the real (FP32 FFT) path even for int8 inputs */
+#define TM_F_ZERO_PAD   0x4u /* Theorem 2 variant (Section 3.2): for each modulus M, x is
+                                padded with zeros to L*M (L = ceil(N/M)); the fold is the
+                                length-M partition fold y[s] = sum_i x[s + i*M] over the
+                                padded signal, the correlation is circular of length M
+                                (r[k] = sum_j t_j y[(k + j) mod M]), and the candidate set
+                                of m~ is {m~ + i*M < N}, so at most one candidate remains.
+                                Identical to the default when M divides N; a template that
+                                wraps past the end of x is not matched by this variant.
+                                The FFT length is not shortened: the two folds share one
+                                transform of length >= max(M1, M2) + K - 1. */
 
 /* result flags */
 #define TM_R_NOMATCH    0x1u /* S_M1 and S_M2 share no element: shift = -1 */
@@ -90,7 +100,8 @@ typedef struct {
   int64_t  shift;        /* m^ in [0, N), or -1 with TM_R_NOMATCH */
   int32_t  m1_tilde;     /* argmax over [0, M1) of the M1-fold correlation (step 7) */
   int32_t  m2_tilde;     /* argmax over [0, M2) of the M2-fold correlation */
-  int32_t  n_candidates; /* |S_M1 cap S_M2| before re-scoring, 0..3 */
+  int32_t  n_candidates; /* |S_M1 cap S_M2| before re-scoring, 0..3 (0..1 with
+                            TM_F_ZERO_PAD) */
   uint32_t flags;        /* TM_R_* */
   double   peak1;        /* r_M1[m1_tilde] (an integer on the exact path) */
   double   peak2;        /* r_M2[m2_tilde] */

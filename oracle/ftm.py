@@ -20,7 +20,15 @@ Readings taken where the paper is silent, ambiguous or inconsistent
       oracle computes the correlation r[k] = sum_j t_j y[k+j].
   R4  When M does not divide N the fold keeps the cyclic indices of
       Algorithm 1 step 3 (Section 2: indices are taken mod N), not the
-      zero padding that Section 3.2 suggests for Theorem 2.
+      zero padding that Section 3.2 suggests for Theorem 2.  The zero-padded
+      variant is available as ftm(..., variant="zero_pad") (reading R4z).
+  R4z Theorem 2 variant: x is padded with zeros to L M (L = ceil(N/M)), the
+      fold is y = [I_M ... I_M] x_pad of length M (the circulant block Phi_M
+      of Theorem 2 taken as the identity, the choice that makes y the
+      partition fold), the correlation is the circular one of length M with
+      T^ = circ([t 0]) read as a correlation (R3), and the candidate set is
+      {m~ + i M : i < L} restricted to [0, N) (positions of the padding are
+      not shifts of x).
   R5  Only r[0..M) is used, so the fold is evaluated for k = 0..M+K-1 and the
       correlation for k = 0..M-1 (both as in step 3 / Theorem 1 with D_{M+K}).
   R6  Step 7 writes i <= M; Section 3.3 writes k < M.  The argmax ranges over
@@ -221,6 +229,35 @@ def correlate_fft(y: np.ndarray, t: np.ndarray, m: int) -> np.ndarray:
     return c
 
 
+def fold_zero_pad(x: np.ndarray, m: int, dt=None) -> np.ndarray:
+    """Theorem 2 variant (Section 3.2, reading R4z): x padded with zeros to
+    L M, L = ceil(N/M), then y[s] = sum_{i<L} x_pad[s + i M] for s in [0, M),
+    i.e. y = [I_M I_M ... I_M] x_pad."""
+    n = x.shape[0]
+    if dt is None:
+        dt = np.int64 if np.issubdtype(x.dtype, np.integer) else np.float64
+    L = -(-n // m)
+    xp = np.zeros(L * m, dtype=dt)
+    xp[:n] = x.astype(dt)
+    y = np.zeros(m, dtype=dt)
+    for i in range(L):
+        y += xp[i * m:(i + 1) * m]
+    return y
+
+
+def correlate_circular(y: np.ndarray, t: np.ndarray, m: int) -> np.ndarray:
+    """r[k] = sum_{j<K} t_j y[(k + j) mod M] for k in [0, M): the M x M
+    circulant T^ = circ([t 0_{M-K}]) of Theorem 2 applied to y, read as a
+    correlation (R3), by direct summation."""
+    dt = np.result_type(y.dtype, np.int64 if np.issubdtype(t.dtype, np.integer) else np.float64)
+    yv = y[:m].astype(dt)
+    tv = t.astype(dt)
+    r = np.zeros(m, dtype=dt)
+    for j in range(tv.shape[0]):
+        r += tv[j] * np.roll(yv, -j)
+    return r
+
+
 # --------------------------------------------------------------------------
 # Algorithm 1 steps 7-9: argmax, candidate sets, intersection
 # --------------------------------------------------------------------------
@@ -231,12 +268,21 @@ def candidate_set(m_tilde: int, m: int, n: int) -> set:
     return {(m_tilde + i * m) % n for i in range(L)}
 
 
-def resolve(x: np.ndarray, t: np.ndarray, m1_tilde: int, m2_tilde: int, m1: int, m2: int):
+def candidate_set_zero_pad(m_tilde: int, m: int, n: int) -> set:
+    """S = {m~ + i M : i = 0..ceil(N/M)-1} with the members inside [0, N)
+    (step 8 as printed, for the zero-padded variant, reading R4z)."""
+    L = -(-n // m)
+    return {m_tilde + i * m for i in range(L) if m_tilde + i * m < n}
+
+
+def resolve(x: np.ndarray, t: np.ndarray, m1_tilde: int, m2_tilde: int, m1: int, m2: int,
+            variant: str = "cyclic"):
     """Step 9: C = S_{M1} cap S_{M2} by literal set intersection; several
     members are re-scored by (Tx)_c (reading R9).  Returns
     (shift, sorted candidates, score of the shift or None)."""
     n = x.shape[0]
-    common = sorted(candidate_set(m1_tilde, m1, n) & candidate_set(m2_tilde, m2, n))
+    cs = candidate_set if variant == "cyclic" else candidate_set_zero_pad
+    common = sorted(cs(m1_tilde, m1, n) & cs(m2_tilde, m2, n))
     if not common:
         return NOMATCH, common, None
     best, best_score = None, None
@@ -269,11 +315,17 @@ class OracleResult:
 
 
 def ftm(x: np.ndarray, t: np.ndarray, m1: Optional[int] = None, m2: Optional[int] = None,
-        fold_mult: int = 1, correlation: str = "direct") -> OracleResult:
+        fold_mult: int = 1, correlation: str = "direct", variant: str = "cyclic") -> OracleResult:
     """Algorithm 1 (FTM) end to end, in the paper's step order.
 
     correlation="direct" is the oracle proper; "fft" swaps in the float64 FFT
-    cross-check of steps 5-6 for large statistical runs."""
+    cross-check of steps 5-6 for large statistical runs.
+    variant="cyclic" is Algorithm 1 as printed (fold of length M + K with
+    indices mod N, Theorem 1); "zero_pad" is the Theorem 2 variant (fold of
+    the zero-padded x of length M, circular correlation of length M, reading
+    R4z).  In the zero_pad result y1, y2 have length M."""
+    if variant not in ("cyclic", "zero_pad"):
+        raise ValueError("variant must be 'cyclic' or 'zero_pad'")
     n, k = x.shape[0], t.shape[0]
     # step 2
     if m1 is None or m2 is None:
@@ -283,17 +335,25 @@ def ftm(x: np.ndarray, t: np.ndarray, m1: Optional[int] = None, m2: Optional[int
         raise ValueError(err)
     dt = work_dtype(x, t)
     # step 3
-    y1 = fold(x, m1, k, dt)
-    y2 = fold(x, m2, k, dt)
+    if variant == "cyclic":
+        y1 = fold(x, m1, k, dt)
+        y2 = fold(x, m2, k, dt)
+    else:
+        y1 = fold_zero_pad(x, m1, dt)
+        y2 = fold_zero_pad(x, m2, dt)
     # steps 4-6
-    corr = correlate if correlation == "direct" else correlate_fft
-    r1 = corr(y1, t, m1)
-    r2 = corr(y2, t, m2)
+    if variant == "cyclic":
+        corr = correlate if correlation == "direct" else correlate_fft
+        r1 = corr(y1, t, m1)
+        r2 = corr(y2, t, m2)
+    else:
+        r1 = correlate_circular(y1, t, m1)
+        r2 = correlate_circular(y2, t, m2)
     # step 7
     i1 = argmax_lowest(r1) if correlation == "direct" else int(np.argmax(r1))
     i2 = argmax_lowest(r2) if correlation == "direct" else int(np.argmax(r2))
     # steps 8-9
-    shift, cands, score = resolve(x, t, i1, i2, m1, m2)
+    shift, cands, score = resolve(x, t, i1, i2, m1, m2, variant)
     return OracleResult(shift=shift, m1_tilde=i1, m2_tilde=i2, candidates=cands, score=score,
                         peak1=r1[i1], peak2=r2[i2], m1=m1, m2=m2, y1=y1, y2=y2, r1=r1, r2=r2)
 

@@ -35,6 +35,8 @@ struct alignas(16) Inst {
   int32_t fold_store;     // tm_dtype used to store the fold on the real path
   int32_t dual;           // 1: mb == ma + 1, fold B comes from view A's diagonals
   int32_t swapped;        // 1: the user's M1 is mb (results are mapped back)
+  int32_t zpad;           // 1: zero-padded variant (partition folds, circular correlation,
+                          //    no wrapped candidates)
   int32_t p_log2;         // FFT length P = 2^p_log2
   View va;                // view with modulus ma (always tiled)
   View vb;                // view with modulus mb (tiled only when !dual)

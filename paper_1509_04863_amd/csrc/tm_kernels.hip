@@ -732,8 +732,10 @@ __device__ __forceinline__ void reduce_wg(const Inst& d, int lc, float* part) {
     for (int i = 0; i < tpe; ++i) sum += part[e * tpe + i];
     const int64_t L = f ? d.vb.l : d.va.l;
     const int64_t N = d.n;
-    if ((int64_t)s + (L - 1) * M >= N) sum += load_as_float(d.x, d.x_dtype, mod_pos((int64_t)s + (L - 1) * M, N));
-    if (uu >= M)
+    // the zero-padded variant keeps the bucket sums: y[M + s] = y[s]
+    if (!d.zpad && (int64_t)s + (L - 1) * M >= N)
+      sum += load_as_float(d.x, d.x_dtype, mod_pos((int64_t)s + (L - 1) * M, N));
+    if (!d.zpad && uu >= M)
       sum += load_as_float(d.x, d.x_dtype, mod_pos((int64_t)s + L * M, N)) - load_as_float(d.x, d.x_dtype, s);
     G(reinterpret_cast<float*>(d.y))[u] = sum;
   }
@@ -1221,7 +1223,8 @@ __device__ FinRed block_finred(FinRed mine, FinRed* scratch) {
 }
 
 // Steps 8-9 (Theorem 4): S_A(a) cap S_B(b) with the candidate sets taken mod
-// N, re-scoring of several candidates by (Tx)_c, and the result record.
+// N (or cut at N for the zero-padded variant of Theorem 2), re-scoring of
+// several candidates by (Tx)_c, and the result record.
 template <typename Tin>
 __device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
   const int tid = threadIdx.x;
@@ -1245,9 +1248,10 @@ __device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t fla
       const int64_t v = a + A * t;
       if (v < N) insert(v);
     }
-    // the wrapped members (a + (La-1) A) mod N and (b + (Lb-1) B) mod N
-    const bool wa = a + (La - 1) * A >= N;
-    const bool wb = b + (Lb - 1) * B >= N;
+    // the wrapped members (a + (La-1) A) mod N and (b + (Lb-1) B) mod N; the
+    // zero-padded variant's sets stop at N
+    const bool wa = !d.zpad && a + (La - 1) * A >= N;
+    const bool wb = !d.zpad && b + (Lb - 1) * B >= N;
     const int64_t va = (a + (La - 1) * A) % N;
     const int64_t vb = (b + (Lb - 1) * B) % N;
     if (wa && ((b < N && va % B == b) || (wb && va == vb))) insert(va);
@@ -1380,7 +1384,8 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
       // every bucket has been read: back to zero for the next launch
       for (int s = tid; s < ma + mb; s += NT) G(d.yp)[s] = 0;
       const bool general = N < (int64_t)max(ma, mb);
-      lit_fix<Tin, T>(d, buf, ma, rhoA, mb, rhoB, K, general);
+      // zero-padded variant: the periodic bucket copy of pass 1 is the fold
+      if (!d.zpad) lit_fix<Tin, T>(d, buf, ma, rhoA, mb, rhoB, K, general);
       __syncthreads();
     }
     // storage rounding (real path), |z|^2 and the optional intermediates
@@ -1554,7 +1559,7 @@ __global__ void __launch_bounds__(kGfftThreads) k_gfft_literal(InstTable tab) {
         const int rho = (int)(N - (L - 1) * M);
         const bool ok = n < nn;
         const int s = n < M ? n : n - M;
-        const bool wrap = ok && s >= rho, ext = ok && n >= M;
+        const bool wrap = ok && !d.zpad && s >= rho, ext = ok && !d.zpad && n >= M;
         const int yb = G(d.yp)[(f ? ma : 0) + (ok ? s : 0)];
         const int xw = ld_int<Tin>(d.x, wrap ? mod_small((int64_t)(s - rho), N, general) : 0);
         const int x1 = ld_int<Tin>(d.x, ext ? mod_small((int64_t)s + M - rho, N, general) : 0);
@@ -1801,7 +1806,7 @@ __global__ void __launch_bounds__(256) k_many_prep(ManyArgs a) {
   int val = 0;
   if (u < M + K - 1) {
     const int s = u < M ? u : u - M;
-    const bool wrap = s >= rho, ext = u >= M;
+    const bool wrap = !b.zpad && s >= rho, ext = !b.zpad && u >= M;
     const int yb = yp[s];
     const int xw = G(x)[wrap ? mod_small((int64_t)(s - rho), N, general) : 0];
     const int x1 = G(x)[ext ? mod_small((int64_t)s + M - rho, N, general) : 0];

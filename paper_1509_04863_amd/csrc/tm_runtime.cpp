@@ -119,7 +119,7 @@ View make_band_view(int64_t n, int64_t m) {
 struct Core {
   int64_t n = 0;
   int32_t k = 0, m1 = 0, m2 = 0, ma = 0, mb = 0;
-  int32_t swapped = 0, dual = 0, mode = MODE_EXACT, p_log2 = 1;
+  int32_t swapped = 0, dual = 0, mode = MODE_EXACT, p_log2 = 1, zpad = 0;
   int32_t x_dtype = 0, t_dtype = 0, fold_store = TM_F32;
   int64_t inv = 0;
   View va{}, vb{};
@@ -154,7 +154,7 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   if (fs != TM_F32 && fs != TM_BF16 && fs != TM_F16)
     return fail(TM_ERR_INVALID, "fold_store must be TM_F32, TM_BF16 or TM_F16");
   if (d->fold_mult < 0 || d->fold_mult > 2) return fail(TM_ERR_INVALID, "fold_mult must be 0, 1 or 2");
-  if (d->flags & ~(TM_F_EXACT | TM_F_REAL)) return fail(TM_ERR_INVALID, "unknown plan flags");
+  if (d->flags & ~(TM_F_EXACT | TM_F_REAL | TM_F_ZERO_PAD)) return fail(TM_ERR_INVALID, "unknown plan flags");
   if ((d->flags & TM_F_EXACT) && (d->flags & TM_F_REAL))
     return fail(TM_ERR_INVALID, "TM_F_EXACT and TM_F_REAL are exclusive");
   if (d->n > (int64_t(1) << 40)) return fail(TM_ERR_INVALID, "N above 2^40 is not supported");
@@ -164,6 +164,7 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   c->x_dtype = d->x_dtype;
   c->t_dtype = d->t_dtype;
   c->fold_store = fs;
+  c->zpad = (d->flags & TM_F_ZERO_PAD) ? 1 : 0;
   int64_t m1 = d->m1, m2 = d->m2;
   if (m1 == 0 && m2 == 0) {
     const int64_t mult = d->fold_mult == 0 ? 1 : d->fold_mult;
@@ -479,6 +480,7 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->fold_store = c.fold_store;
   in->dual = c.dual;
   in->swapped = c.swapped;
+  in->zpad = c.zpad;
   in->p_log2 = c.p_log2;
   in->va = c.va;
   in->vb = c.vb;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libtm.so")
 
 TM_OK, TM_ERR_INVALID, TM_ERR_NOMEM, TM_ERR_DEVICE, TM_ERR_UNSUPPORTED = range(5)
 TM_I8, TM_F32, TM_BF16, TM_F16 = range(4)
-TM_F_EXACT, TM_F_REAL = 0x1, 0x2
+TM_F_EXACT, TM_F_REAL, TM_F_ZERO_PAD = 0x1, 0x2, 0x4
 TM_R_NOMATCH, TM_R_RESCORED, TM_R_NEAR_TIE, TM_R_EXACT = 0x1, 0x2, 0x4, 0x8
 
 EXPORTS = ["tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_info", "tm_match",

@@ -150,6 +150,85 @@ def test_theorem2_when_m_divides_n(n, m, k, seed):
         np.testing.assert_allclose(That @ (phi @ x), phi @ (T @ x), rtol=0, atol=1e-8)
 
 
+@pytest.mark.parametrize("n,m,k,seed", [(23, 5, 3, 0), (40, 7, 7, 1), (36, 6, 2, 2), (11, 16, 4, 3)])
+def test_zero_pad_variant_is_theorem2_on_padded_signal(n, m, k, seed):
+    """Theorem 2 variant (Section 3.2): with x padded to L M, the fold is
+    [I_M ... I_M] x_pad and its length-M circular correlation equals
+    Phi T x_pad for T = circ([t 0]) of length L M (matrices written out)."""
+    rng = _rng(seed)
+    x = rng.integers(-9, 10, n).astype(np.int64)
+    t = rng.integers(-9, 10, k).astype(np.int64)
+    L = -(-n // m)
+    xp = np.concatenate([x, np.zeros(L * m - n, dtype=np.int64)])
+    phi = np.hstack([np.eye(m, dtype=np.int64)] * L)
+    y = O.fold_zero_pad(x, m)
+    assert np.array_equal(y, phi @ xp)
+    That = O.circ(np.concatenate([t, np.zeros(m - k, dtype=np.int64)]))
+    assert np.array_equal(O.correlate_circular(y, t, m), That @ y)
+    assert np.array_equal(O.correlate_circular(y, t, m), phi @ (O.template_matrix(t, L * m) @ xp))
+
+
+@pytest.mark.parametrize("m1,m2,k", [(4, 5, 3), (3, 4, 3), (5, 6, 2)])
+def test_zero_pad_equals_cyclic_when_both_moduli_divide_n(m1, m2, k):
+    """M | N: zero padding adds nothing and no index wraps, so both variants
+    give the same folds on [0, M), correlations, candidates and shift for
+    every planted shift (N = M1 M2)."""
+    n = m1 * m2
+    rng = _rng(n + k)
+    x = rng.integers(-5, 6, n).astype(np.int64)
+    for m in range(n):
+        t = x[(m + np.arange(k)) % n].copy()
+        a = O.ftm(x, t, m1, m2)
+        b = O.ftm(x, t, m1, m2, variant="zero_pad")
+        assert np.array_equal(a.y1[:m1], b.y1) and np.array_equal(a.y2[:m2], b.y2)
+        assert np.array_equal(a.r1, b.r1) and np.array_equal(a.r2, b.r2)
+        assert (a.shift, a.candidates, a.m1_tilde, a.m2_tilde) == (b.shift, b.candidates, b.m1_tilde, b.m2_tilde)
+
+
+def test_zero_pad_candidates_are_residue_classes_and_unique():
+    """The zero-padded candidate set is the residue class of m~ inside [0, N);
+    with M1 M2 >= N two classes share at most one element (Theorem 4)."""
+    for n in range(1, 45):
+        for m1 in range(1, n + 2):
+            m2 = m1 + 1
+            if m1 * m2 < n:
+                continue
+            for a in range(m1):
+                s1 = O.candidate_set_zero_pad(a, m1, n)
+                assert s1 == {c for c in range(n) if c % m1 == a}
+                for b in range(m2):
+                    common = s1 & O.candidate_set_zero_pad(b, m2, n)
+                    assert len(common) <= 1
+                    assert common == {c for c in range(n) if c % m1 == a and c % m2 == b}
+
+
+@pytest.mark.parametrize("n,k", [(16, 3), (31, 4), (50, 7), (9, 9)])
+def test_zero_pad_exhaustive_tiny_shifts(n, k):
+    """Every planted shift: the result is the lowest-index maximum of the
+    padded folded correlation in each fold, the intersection of the two
+    residue classes, and the planted shift whenever it is the unique full-
+    search maximum that dominates its padded buckets (Theorem 3's premise on
+    the padded signal) and the template does not wrap past the end of x."""
+    rng = _rng(n * 7 + k)
+    x = _pm1(n, rng)
+    m1, m2 = O.choose_moduli(n, k)
+    for m in range(n):
+        t = x[(m + np.arange(k)) % n].copy()
+        res = O.ftm(x, t, m1, m2, variant="zero_pad")
+        c = {v for v in range(n) if v % m1 == res.m1_tilde and v % m2 == res.m2_tilde}
+        assert set(res.candidates) == c and res.n_candidates <= 1
+        for M, mt in ((m1, res.m1_tilde), (m2, res.m2_tilde)):
+            L = -(-n // M)
+            xp = np.concatenate([x.astype(np.int64), np.zeros(L * M - n, dtype=np.int64)])
+            fullp = O.full_correlation(xp, t)
+            rr = np.array([sum(fullp[(kk + i * M)] for i in range(L)) for kk in range(M)])
+            assert mt == int(np.argmax(rr))
+            if m + k <= n and _thm3_premise(fullp, m, L) and int(np.argmax(fullp)) == m:
+                assert mt == m % M
+        if res.shift != O.NOMATCH:
+            assert res.shift == min(c)
+
+
 @pytest.mark.parametrize("n,m,k,seed", [(4096, 300, 64, 0), (1000, 101, 100, 1), (777, 50, 3, 2)])
 def test_direct_and_fft_correlation_agree(n, m, k, seed):
     rng = _rng(seed)
