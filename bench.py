@@ -9,10 +9,12 @@ inputs resident in HBM and rotated over >= 1 GiB of distinct signals so the
 (request server: open-loop p50/p99 and saturation vs plain launch), config5b
 (1024 signals sharing one template: int8 MFMA GEMM vs the FFT path).
 
-Prints one JSON line: whole-job matches/s, the fold kernel's achieved HBM
-bandwidth against the 8 TB/s peak (HIP events around every fold launch of a
-separate single-stream run), and the CPU oracle timed on a bounded sample of
-the same workload.
+Prints one JSON line: whole-job matches/s; the roofline of the dominant
+kernel, the fold (HBM bytes against 8 TB/s) or the correlation (int8 matrix
+product: 2 K (M1 + M2) operations per match against 5 POP/s; FFT finish: its
+FFT flops against the FP64 or FP32 vector peak), both timed by HIP events
+around every launch of a separate single-stream run, the other one reported
+beside it; and the CPU oracle timed on a bounded sample of the same workload.
 """
 
 import argparse
@@ -26,11 +28,50 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0      # dense int8 MFMA
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 # HBM bytes per fold launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
 # a plain copy's readings (profiles/hbm_traffic_folds_config2_config3.txt);
 # valid for the fold kernels as those counters saw them
 TRAFFIC_BYTES = {"config2": 1.829e7, "config3": 1.561e9}
+
+
+def corr_roofline(plans, corr_ms, corr_n, traffic=None):
+    """The correlation kernel's roofline from its average launch time: the
+    int8 matrix product against the int8 MFMA peak (algorithmic operations
+    2 K (M1 + M2) per match), or the FFT finish against the vector peak of its
+    precision (2 transforms of 5 P log2 P flops plus 6 P per match)."""
+    avg_s = corr_ms / corr_n / 1e3
+    info = plans[0].info
+    if info["corr_gemm"]:
+        ops = sum(2.0 * p.k * (p.m1 + p.m2) for p in plans)
+        achieved = ops / avg_s / 1e12
+        return {"kernel": "k_cgemm", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                "unit": "TOP/s", "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic,
+                "avg_kernel_us": avg_s * 1e6, "algorithmic_ops_per_launch": ops}
+    flops = 0.0
+    for p in plans:
+        P = 1 << p.info["fft_log2"]
+        flops += 10.0 * P * math.log2(P) + 6.0 * P
+    peak = FP64_PEAK_TFLOPS if info["exact"] else FP32_PEAK_TFLOPS
+    achieved = flops / avg_s / 1e12
+    return {"kernel": "k_finish", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic, "avg_kernel_us": avg_s * 1e6,
+            "algorithmic_flops_per_launch": flops}
+
+
+def pick_roofline(line, fold_roof, corr_roof):
+    """`roofline` is the kernel with the larger average launch time; the other
+    goes into `roofline_other`."""
+    roofs = [r for r in (fold_roof, corr_roof) if r is not None]
+    if not roofs:
+        return
+    roofs.sort(key=lambda r: -r["avg_kernel_us"])
+    line["roofline"] = roofs[0]
+    if len(roofs) > 1:
+        line["roofline_other"] = roofs[1]
 
 
 def parse():
@@ -89,15 +130,17 @@ def run_batched(args):
     stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
-    fold_ms, fold_n = 0.0, 0
+    fold_ms, fold_n, corr_ms, corr_n = 0.0, 0, 0.0, 0
     if not args.no_profile:
         tm.profile_read(reset=True)
+        tm.profile_read_corr(reset=True)
         tm.profile_enable(True)
         for _ in range(args.steps):
             batch.run(out, stream)
         torch.cuda.synchronize()
         tm.profile_enable(False)
         fold_ms, fold_n = tm.profile_read(reset=True)
+        corr_ms, corr_n = tm.profile_read_corr(reset=True)
     results = tm.results_from_device(out)
     x_bytes = sum(s.x.nbytes for s in insts)
     ms_per_step = total_ms / args.steps
@@ -106,21 +149,26 @@ def run_batched(args):
         "value": len(insts) * args.steps / (total_ms / 1e3), "unit": "matches/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "i32 fold, f64 fft", "data": "synthetic",
+        "dtype": "i32 fold, i8 MFMA correlation (exact)" if all(p.info["corr_gemm"] for p in plans)
+        else "i32 fold, f64 fft", "data": "synthetic",
         "config": {"workload": "config3: %d uneven int8 +-1 instances, N=2^U(16,20), K=2^U(9,12), "
                                "flips U[5%%,15%%], one batch per step" % len(insts),
                    "instances": len(insts), "batch_x_bytes": x_bytes},
         "planted_recovered": "%d/%d" % (sum(int(r.shift == s.shift) for r, s in zip(results, insts)),
                                         len(insts)),
     }
+    fold_roof = corr_roof = None
     if fold_n:
         avg_s = fold_ms / fold_n / 1e3
         achieved = x_bytes / avg_s / 1e9
-        line["roofline"] = {"kernel": "k_fold_s8", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                            "traffic": args.traffic_bytes if args.traffic_bytes is not None
-                            else TRAFFIC_BYTES.get("config3"),
-                            "avg_kernel_us": avg_s * 1e6, "algorithmic_bytes_per_launch": x_bytes}
+        fold_roof = {"kernel": "k_fold_s8", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": args.traffic_bytes if args.traffic_bytes is not None
+                     else TRAFFIC_BYTES.get("config3"),
+                     "avg_kernel_us": avg_s * 1e6, "algorithmic_bytes_per_launch": x_bytes}
+    if corr_n:
+        corr_roof = corr_roofline(plans, corr_ms, corr_n, TRAFFIC_BYTES.get("config3_corr"))
+    pick_roofline(line, fold_roof, corr_roof)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(lambda i: insts[i], args.cpu_seconds, results)
     print(json.dumps(line), flush=True)
@@ -176,7 +224,7 @@ def run_serving(args):
         open_stats = srv.stats()
 
         # closed loop: the whole request set queued at once, several rounds
-        rounds = 4
+        rounds = 20
         t0 = time.perf_counter()
         ts = [srv.submit(plans[i % nreq], req_x[i % nreq]) for i in range(rounds * nreq)]
         served = [srv.wait(t)[0] for t in ts]
@@ -186,7 +234,10 @@ def run_serving(args):
         tm.match(plans[i], req_x[i])
     t0 = time.perf_counter()
     plain = [tm.match(plans[i], req_x[i]) for i in range(nreq)]
-    plain_s = time.perf_counter() - t0
+    for _ in range(2):
+        for i in range(nreq):
+            tm.match(plans[i], req_x[i])
+    plain_s = (time.perf_counter() - t0) / 3
     same = sum(int(a == b) for a, b in zip(served[:nreq], plain))
     recovered = sum(int(r.shift == q.shift) for r, q in zip(plain, reqs))
     served_rate = rounds * nreq / served_s
@@ -214,8 +265,10 @@ def run_serving(args):
 
 def run_shared(args):
     """config5b: 1024 int8 +-1 signals of N=2^18 sharing one K=1024 template,
-    one tm_match_many per step: correlation by int8 MFMA GEMM, and the same
-    step through the FFT batch path for comparison."""
+    one tm_match_many per step (one int8 MFMA GEMM against the shared
+    template); the same signals as independent matches (TM_MANY_BATCH=1:
+    per-instance int8 products) and through the FFT correlation (TM_F_FFT) for
+    comparison."""
     import torch
 
     from paper_1509_04863_amd import datagen as G
@@ -240,12 +293,15 @@ def run_shared(args):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
-    ms_gemm = timed(args.steps)
+    ms_gemm = timed(args.steps)             # one GEMM against the shared template
     res_gemm = tm.results_from_device(out)
-    os.environ["TM_MANY_FFT"] = "1"
-    ms_fft = timed(max(5, args.steps // 4))
+    os.environ["TM_MANY_BATCH"] = "1"       # independent matches: per-instance int8 products
+    ms_batch = timed(args.steps)
+    res_batch = tm.results_from_device(out)
+    os.environ.pop("TM_MANY_BATCH")
+    many = tm.Many(tm.Plan(insts[0].t, n=insts[0].n, flags=tm.TM_F_FFT), xs)
+    ms_fft = timed(max(5, args.steps // 4))  # the FFT correlation of steps 4-6
     res_fft = tm.results_from_device(out)
-    os.environ.pop("TM_MANY_FFT")
     x_bytes = sum(s.x.nbytes for s in insts)
     hits = sum(int(r.shift == s.shift) for r, s in zip(res_gemm, insts))
     line = {
@@ -258,6 +314,9 @@ def run_shared(args):
         "fft_path": {"ms_per_step": ms_fft, "matches_per_s": len(xs) / (ms_fft / 1e3),
                      "gemm_speedup": ms_fft / ms_gemm,
                      "same_results": "%d/%d" % (sum(int(a == b) for a, b in zip(res_gemm, res_fft)), len(xs))},
+        "per_instance_gemm_batch": {"ms_per_step": ms_batch, "matches_per_s": len(xs) / (ms_batch / 1e3),
+                                    "same_results": "%d/%d" % (sum(int(a == b) for a, b in zip(res_gemm, res_batch)),
+                                                               len(xs))},
         "planted_recovered": "%d/%d" % (hits, len(xs)),
     }
     print(json.dumps(line), flush=True)
@@ -358,9 +417,10 @@ def main():
     total_ms = start.elapsed_time(stop)
 
     # fold kernel alone: HIP events around every fold launch, one stream, after the timed run
-    fold_ms, fold_n = (0.0, 0)
+    fold_ms, fold_n, corr_ms, corr_n = 0.0, 0, 0.0, 0
     if not args.no_profile:
         tm.profile_read(reset=True)
+        tm.profile_read_corr(reset=True)
         tm.profile_enable(True)
         for i in range(min(args.steps, 100)):
             j = i % rot
@@ -368,6 +428,7 @@ def main():
         torch.cuda.synchronize()
         tm.profile_enable(False)
         fold_ms, fold_n = tm.profile_read(reset=True)
+        corr_ms, corr_n = tm.profile_read_corr(reset=True)
 
     results = tm.results_from_device(out)
     planted_ok = sum(int(r.shift == s.shift) for r, s in zip(results, insts))
@@ -380,7 +441,8 @@ def main():
         "value": value, "unit": "matches/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "i32 fold, f64 fft" if info["exact"] else "f32",
+        "dtype": ("i32 fold, i8 MFMA correlation (exact)" if info["corr_gemm"] else "i32 fold, f64 fft")
+        if info["exact"] else "f32",
         "data": "synthetic",
         "config": {"workload": args.config + ": " + wl["desc"], "n": first.n, "k": first.k,
                    "m1": info["m1"], "m2": info["m2"], "fft_len": p_len,
@@ -390,14 +452,18 @@ def main():
                                   ("k_fold_s8" if info["fold_segments"] else "k_fold")},
         "planted_recovered": "%d/%d" % (planted_ok, rot),
     }
+    fold_roof = corr_roof = None
     if fold_n:
         avg_s = fold_ms / fold_n / 1e3
         achieved = x_bytes / avg_s / 1e9
-        line["roofline"] = {"kernel": line["config"]["fold_kernel"], "bound": "hbm", "achieved": achieved,
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                            "traffic": args.traffic_bytes if args.traffic_bytes is not None
-                            else TRAFFIC_BYTES.get(args.config), "avg_kernel_us": avg_s * 1e6,
-                            "algorithmic_bytes_per_launch": x_bytes}
+        fold_roof = {"kernel": line["config"]["fold_kernel"], "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": args.traffic_bytes if args.traffic_bytes is not None
+                     else TRAFFIC_BYTES.get(args.config), "avg_kernel_us": avg_s * 1e6,
+                     "algorithmic_bytes_per_launch": x_bytes}
+    if corr_n:
+        corr_roof = corr_roofline([plans[0]], corr_ms, corr_n, TRAFFIC_BYTES.get(args.config + "_corr"))
+    pick_roofline(line, fold_roof, corr_roof)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl["make"], args.cpu_seconds, results)
     print(json.dumps(line), flush=True)

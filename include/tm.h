@@ -9,8 +9,10 @@
  * (Eq. (1) with the similarity of Section 3).
  *
  * Every step runs on the GPU: the fold of Algorithm 1 step 3 (Eq. (2)), the
- * correlation of steps 4-6 by FFT, the argmax of step 7 and the candidate
- * intersection of steps 8-9 (Theorem 4, Chinese remaindering).
+ * correlation of steps 4-6 (by FFT, or for exact plans with an int8-valued
+ * template directly as an int8 matrix product on the matrix cores, which gives
+ * the same integers), the argmax of step 7 and the candidate intersection of
+ * steps 8-9 (Theorem 4, Chinese remaindering).
  *
  * Conventions for every entry point
  *   - Sizes are element counts.  Device pointers are HIP device addresses
@@ -70,12 +72,15 @@ typedef enum {
                                 wraps past the end of x is not matched by this variant.
                                 The FFT length is not shortened: the two folds share one
                                 transform of length >= max(M1, M2) + K - 1. */
+#define TM_F_FFT        0x8u /* exact path: always compute the correlation by the FFT of
+                                steps 4-6, never by the direct int8 matrix product */
 
 /* result flags */
 #define TM_R_NOMATCH    0x1u /* S_M1 and S_M2 share no element: shift = -1 */
 #define TM_R_RESCORED   0x2u /* more than one common candidate; chosen by (Tx)_c */
 #define TM_R_NEAR_TIE   0x4u /* real path: an argmax's top-2 gap is below 1e-5 of its fold's peak */
-#define TM_R_EXACT      0x8u /* exact path and the FP64 FFT error bound is below 1/2, so
+#define TM_R_EXACT      0x8u /* exact path and either the int8 matrix product computed the
+                                correlation or the FP64 FFT error bound is below 1/2, so
                                 every correlation value is the exact integer */
 
 typedef struct {
@@ -123,6 +128,11 @@ typedef struct {
   int32_t fold_bands;    /* workgroups of the band fold of 4-byte signals */
   int32_t fft_global;    /* 1 = P above one workgroup's LDS: four-step FFT through
                             global memory (P up to 2^21) */
+  int32_t corr_gemm;     /* 1 = the correlation of steps 4-6 may be computed directly
+                            as an int8 MFMA matrix product (exact plans whose template
+                            holds integers in [-128, 127], K <= 2^17, unless
+                            TM_F_FFT); every correlation value is then exact */
+  int32_t reserved;
   int64_t workspace_bytes; /* device workspace one match of this plan uses */
   int64_t x_bytes;       /* bytes of x read per match */
 } tm_plan_info;
@@ -208,6 +218,10 @@ tm_status tm_match_intermediates(tm_plan plan, const void* x, tm_result* out,
  */
 tm_status tm_profile_enable(int on);
 tm_status tm_profile_read(double* fold_ms_total, int64_t* fold_launches, int reset);
+/* The same for the correlation kernel of tm_match and tm_match_batch: the
+ * int8 matrix-product kernel on that route, the in-LDS FFT finish kernel on
+ * the FFT route (the four-step global FFT is not timed). */
+tm_status tm_profile_read_corr(double* ms_total, int64_t* launches, int reset);
 
 /*
  * Request server (continuous batching).  Matches of uneven N and K submitted

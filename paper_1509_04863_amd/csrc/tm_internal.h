@@ -61,6 +61,17 @@ struct alignas(16) Inst {
   void* gpart;            // argmax partials, one per column workgroup
   const void* tw_cols;    // twiddles for 2^(g_logb + g_q)
   const void* tw_rows;    // twiddles for P2
+  int32_t cgemm;          // 1: correlation as an int8 MFMA GEMM (exact path, int8-valued t)
+  int32_t c_nlcap;        // limbs the literal folds are split into (upper bound of the need)
+  int32_t c_lp;           // bytes per limb row of one fold (multiple of 64)
+  int32_t c_ks;           // 64-deep steps over the template band: ceil((K + 63) / 64) rounded up to 4
+  int32_t c_rta, c_rtb;   // GEMM workgroups (16 rows of 64 shifts) of fold A and fold B
+  int32_t c_lt;           // bytes per shifted template copy in tsh
+  int32_t c_pad0;
+  int8_t* ylimb;          // [2 folds][c_nlcap][c_lp] balanced base-128 digits of the folds
+  void* cpart;            // [2 folds][max(c_rta, c_rtb) * 4] best (value, shift) per wave
+  int* cmax;              // [2] largest |y| per fold (in the zeroed bucket zone)
+  const int8_t* tsh;      // 16 copies of the zero-padded template, copy c shifted by c bytes
   int64_t inv_a_mod_b;    // ma^{-1} mod mb
   // workspace (device)
   void* col_a;            // [va.nrb][ma] column partials
@@ -127,6 +138,13 @@ constexpr int kGemmPad = 128;                       // zero bytes around the tem
 constexpr int kGemmTile = 64;                       // signals and shifts per workgroup
 constexpr int kGemmMaxLimbs = 3;                    // balanced base-128 digits of the folds
 
+// correlation of exact instances as an int8 MFMA GEMM (k_cgemm_*)
+constexpr int kCgPad = 128;                         // zero bytes around the template copies
+constexpr int kCgRows = 16;                         // rows (64-shift blocks) per GEMM workgroup
+constexpr int kCgMaxLimbs = 5;                      // balanced base-128 digits of int32 folds
+constexpr int kCgMaxK = 1 << 17;                    // int32 limb sums stay exact below this K
+constexpr int kCgPrepThreads = 256;
+
 // Arguments of the shared-template kernels (one plan, `count` signals).
 struct ManyArgs {
   Inst base;              // the plan's instance record (x, out, workspace unset)
@@ -173,6 +191,17 @@ hipError_t launch_spectrum(const void* t, int t_dtype, int k, int p_log2, const 
                            double* scratch, void* spec, int as_double, int row_log2, hipStream_t s);
 size_t gfft_part_bytes();
 hipError_t launch_many(const ManyArgs& a, hipStream_t s);   // literal folds .. results
+// exact instances with the GEMM correlation (list: `count` instance indices
+// of the table, or nullptr for tab.one): literal-fold digits in chunks of
+// `chunk` entries; the GEMM with per-wave argmax over gemm_y row-tile tasks
+// per instance (variant by the largest digit count); per instance the argmax
+// reduction and the resolve
+hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int count, int chunk, int prep_y,
+                             hipStream_t s);
+hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
+                             hipStream_t s);
+hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s);
+int cgemm_limbs_for(int64_t maxabs);                   // limbs that hold |y| <= maxabs
 hipError_t launch_gfft(const Inst& one, hipStream_t s);   // literal folds .. result, one instance
 
 }  // namespace tmi

@@ -1961,6 +1961,314 @@ hipError_t launch_many(const ManyArgs& a, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
+// exact instances: the correlation as an int8 MFMA GEMM
+// --------------------------------------------------------------------------
+//
+// For one fold, r[k] = sum_{j<K} t_j y[k + j] (k < M) is the product R = Y T
+// with the shift written k = 64 a + b: Y[a][l] = y[64 a + l] (the literal fold
+// read as rows of stride 64) and T[l][b] = t[l - b] (the banded Toeplitz block
+// of t, l < K + 63, b < 64).  The folds are split into balanced base-128
+// digits so that every digit row is an int8 A operand; the B operand of column
+// b, t[l - b .. l - b + 15], is read 16-byte aligned from one of 16 copies of
+// the zero-padded template shifted by 0..15 bytes (built once per plan and
+// interleaved by 16-byte chunk, so neighbouring columns read neighbouring
+// chunks).  A
+// wave computes a 16 x 16 tile of shifts (rows 16 rt + 0..15, columns
+// 16 nt + 0..15) over the whole band with exact int32 sums per digit, combines
+// the digits in int64 and keeps its best (value, lowest shift); the last
+// kernel reduces the waves of each fold and resolves (steps 7-9).  Every r[k]
+// is the exact integer, so the result always carries TM_R_EXACT.
+
+// |y| < T_n is held by n balanced digits, each in [-64, 63], with T_1 = 64
+// and T_{n+1} = 64 + 128 (T_n - 1)
+__host__ __device__ inline int cg_limbs(int64_t maxabs) {
+  int n = 1;
+  int64_t th = 64;
+  while (n < kCgMaxLimbs && maxabs >= th) {
+    th = 64 + 128 * (th - 1);
+    ++n;
+  }
+  return n;
+}
+
+int cgemm_limbs_for(int64_t maxabs) { return cg_limbs(maxabs); }
+
+// literal fold entries [e0, e0 + chunk) of the pair (fold A entries u < c_lp,
+// then fold B): Algorithm 1 step 3 with Section 2's indices (the zero-padded
+// variant keeps the periodic bucket sums), their digits, the intermediates and
+// each fold's largest |y|
+template <typename Tin>
+__device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
+  __shared__ int wmax[2][kCgPrepThreads / 64];
+  // everything the loop needs in registers: its global stores could alias the
+  // instance table as far as the compiler knows
+  const int lp = d.c_lp, nlc = d.c_nlcap;
+  const int ma = d.va.m, mb = d.vb.m, K = d.k;
+  const int64_t N = d.n, La = d.va.l, Lb = d.vb.l;
+  const bool general = N < (int64_t)max(ma, mb);
+  const bool sfold = d.sfold != 0, zpad = d.zpad != 0;
+  const int rhoA = (int)(N - (La - 1) * ma), rhoB = (int)(N - (Lb - 1) * mb);
+  const int biasA = sfold ? 128 * ((int)La - 1) : 0, biasB = sfold ? 128 * ((int)Lb - 1) : 0;
+  const GAS int* yp = G(d.yp);
+  const void* x = d.x;
+  double* dyA = d.swapped ? d.dbg_y2 : d.dbg_y1;
+  double* dyB = d.swapped ? d.dbg_y1 : d.dbg_y2;
+  GAS int8_t* limb = G(d.ylimb);
+  GAS int* cmax = G(d.cmax);
+  int mx[2] = {0, 0};
+  const int e1 = min(e0 + chunk, 2 * lp);
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += kCgPrepThreads) {
+    const int f = e >= lp ? 1 : 0;
+    const int u = e - f * lp;
+    const int M = f ? mb : ma;
+    const int rho = f ? rhoB : rhoA;
+    int val = 0;
+    if (u < M + K - 1) {
+      const int s = u < M ? u : u - M;
+      val = yp[(f ? ma : 0) + s];
+      if (sfold) val -= (f ? biasB : biasA) + (s < rho ? 128 : 0);
+      if (!zpad) {
+        if (s >= rho) val += ld_int<Tin>(x, mod_small((int64_t)(s - rho), N, general));
+        if (u >= M) val += ld_int<Tin>(x, mod_small((int64_t)s + M - rho, N, general)) - ld_int<Tin>(x, s);
+      }
+      double* dy = f ? dyB : dyA;
+      if (dy) G(dy)[u] = (double)val;
+    }
+    int rest = val;
+    GAS int8_t* dst = limb + (int64_t)f * nlc * lp + u;
+    for (int l = 0; l < nlc; ++l) {
+      const int digit = ((rest + 64) & 127) - 64;
+      rest = (rest - digit) >> 7;
+      dst[(int64_t)l * lp] = (int8_t)digit;
+    }
+    mx[f] = max(mx[f], val < 0 ? -val : val);
+  }
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    int m = mx[f];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) wmax[f][threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int f = threadIdx.x;
+    int m = wmax[f][0];
+    for (int w = 1; w < kCgPrepThreads / 64; ++w) m = max(m, wmax[f][w]);
+    if (m) __hip_atomic_fetch_max(cmax + f, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ void cg_prep_dispatch(const Inst& d, int e0, int chunk) {
+  if (e0 >= 2 * d.c_lp) return;
+  switch (d.x_dtype) {
+    case TM_I8: cg_prep_chunk<int8_t>(d, e0, chunk); break;
+    case TM_F32: cg_prep_chunk<float>(d, e0, chunk); break;
+    case TM_BF16: cg_prep_chunk<bf16_t>(d, e0, chunk); break;
+    default: cg_prep_chunk<f16_t>(d, e0, chunk); break;
+  }
+}
+
+// grid (instances, chunks): blockIdx.x picks the instance from the list,
+// blockIdx.y its chunk of `chunk` entries
+__global__ void __launch_bounds__(kCgPrepThreads) k_cgemm_prep(InstTable tab, const int32_t* list, int chunk) {
+  const int e0 = blockIdx.y * chunk;
+  if (list) cg_prep_dispatch(tab.table[list[blockIdx.x]], e0, chunk);
+  else cg_prep_dispatch(tab.one, e0, chunk);
+}
+
+// the four quarters of a workgroup's 16 x 64 tile summed in LDS (int64), the
+// intermediates, and wave nt's best shift of column tile nt
+template <int NL>
+__device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int M, const v4i_t (&acc)[NL][4],
+                                               long long* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  // digits to int64, this wave's quarter into LDS: red[w][nt][jj][lane]
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      long long r = 0, wt = 1;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) { r += wt * (long long)acc[l][nt][jj]; wt *= 128; }
+      red[((w * 4 + nt) * 4 + jj) * 64 + lane] = r;
+    }
+  __syncthreads();
+  // wave w owns column tile nt = w: lane holds rows 4 g + jj, column c
+  const int nt = w;
+  double* dr = (f != d.swapped) ? d.dbg_r2 : d.dbg_r1;
+  VI best{-INFINITY, 0x7fffffff};
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    long long r = 0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) r += red[((ww * 4 + nt) * 4 + jj) * 64 + lane];
+    const int k = 64 * (kCgRows * rt + 4 * g + jj) + 16 * nt + c;
+    if (k < M) {
+      if (dr) G(dr)[k] = (double)r;
+      if (vi_better(VI{(double)r, k}, best)) best = VI{(double)r, k};
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
+    if (vi_better(other, best)) best = other;
+  }
+  if (lane == 0) {
+    const int rtm = max(d.c_rta, d.c_rtb);
+    double* pp = reinterpret_cast<double*>(d.cpart) + ((int64_t)(f * rtm + rt) * 4 + nt) * 2;
+    G(pp)[0] = best.v;
+    G(pp)[1] = (double)best.i;
+  }
+}
+
+// One workgroup: rows 16 rt .. 16 rt + 15 (64 shifts each) of fold f.  Wave w
+// takes a quarter of the band's steps for all four 16-column tiles; the
+// quarters are summed in LDS (int64) and wave nt then keeps the best of
+// column tile nt.
+template <int NL>
+__device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, long long* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int M = f ? d.vb.m : d.va.m;
+  const int lp = d.c_lp, KS = d.c_ks;
+  const int q = KS >> 2;                     // steps per wave (KS is a multiple of 4)
+  const int st0 = w * q;
+  const GAS int8_t* arow = G(d.ylimb) + (int64_t)f * d.c_nlcap * lp + 64 * (kCgRows * rt + c) + 16 * g;
+  const GAS int8_t* tsh = G(d.tsh);
+  // copies interleaved by 16-byte chunk: chunk m of copy sh at (16 m + sh) * 16,
+  // so the 16 lanes of a column tile read neighbouring chunks
+  auto ld_b = [&](int st, int nt) {
+    const int j = 64 * st + 16 * g - (16 * nt + c) + kCgPad;
+    const int sh = (-j) & 15;
+    return *reinterpret_cast<const GAS v4i_t*>(tsh + (((j + sh) >> 4) * 16 + sh) * 16);
+  };
+  auto ld_a = [&](int st, int l) { return *reinterpret_cast<const GAS v4i_t*>(arow + (int64_t)l * lp + 64 * st); };
+  v4i_t acc[NL][4];
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
+  // the next step's operands are in flight during the current step's MFMAs
+  v4i_t bc[4], ac[NL];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) bc[nt] = ld_b(st0, nt);
+#pragma unroll
+  for (int l = 0; l < NL; ++l) ac[l] = ld_a(st0, l);
+  for (int i = 0; i < q; ++i) {
+    v4i_t bn[4], an[NL];
+    if (i + 1 < q) {
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) bn[nt] = ld_b(st0 + i + 1, nt);
+#pragma unroll
+      for (int l = 0; l < NL; ++l) an[l] = ld_a(st0 + i + 1, l);
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ac[l], bc[nt], acc[l][nt], 0, 0, 0);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bc[nt] = bn[nt];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) ac[l] = an[l];
+  }
+  cg_finish_rows<NL>(d, f, rt, M, acc, red);
+}
+
+// MAXNL: largest digit count this variant is built for (register budget:
+// the int8 signals need at most 3 digits and run on the narrow variant with
+// more waves per SIMD)
+template <int MAXNL>
+__device__ __forceinline__ void cg_gemm_dispatch(const Inst& d, int task, long long* red) {
+  if (task >= d.c_rta + d.c_rtb) return;
+  const int f = task >= d.c_rta ? 1 : 0;
+  const int rt = task - f * d.c_rta;
+  const int nl = min(min(cg_limbs(G(d.cmax)[f]), d.c_nlcap), MAXNL);
+  switch (nl) {
+    case 1: cg_gemm_rows<1>(d, f, rt, red); break;
+    case 2: cg_gemm_rows<2>(d, f, rt, red); break;
+    case 3: cg_gemm_rows<3>(d, f, rt, red); break;
+    case 4: if constexpr (MAXNL >= 4) cg_gemm_rows<4>(d, f, rt, red); break;
+    default: if constexpr (MAXNL >= 5) cg_gemm_rows<5>(d, f, rt, red); break;
+  }
+}
+
+// grid (instances, row-tile tasks of both folds)
+template <int MAXNL>
+__global__ void __launch_bounds__(256) k_cgemm(InstTable tab, const int32_t* list) {
+  __shared__ long long red[4 * 4 * 4 * 64];
+  if (list) cg_gemm_dispatch<MAXNL>(tab.table[list[blockIdx.x]], blockIdx.y, red);
+  else cg_gemm_dispatch<MAXNL>(tab.one, blockIdx.y, red);
+}
+
+template <typename Tin>
+__device__ void cg_final(const Inst& d) {
+  __shared__ __align__(16) unsigned char scratch[16 * 16];
+  __shared__ VI fin[2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < 2) {
+    const int f = wave;
+    const int n = (f ? d.c_rtb : d.c_rta) * 4;
+    const int rtm = max(d.c_rta, d.c_rtb);
+    const double* pp = reinterpret_cast<const double*>(d.cpart) + (int64_t)f * rtm * 4 * 2;
+    VI best{-INFINITY, 0x7fffffff};
+    for (int i = lane; i < n; i += 64) {
+      const VI v{G(pp)[2 * i], (int)G(pp)[2 * i + 1]};
+      if (vi_better(v, best)) best = v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
+      if (vi_better(other, best)) best = other;
+    }
+    if (lane == 0) fin[f] = best;
+  }
+  // the buckets and the fold maxima have been consumed: back to zero
+  const int nz = d.va.m + d.vb.m;
+  for (int s = threadIdx.x; s < nz; s += blockDim.x) G(d.yp)[s] = 0;
+  if (threadIdx.x < 2) G(d.cmax)[threadIdx.x] = 0;
+  __syncthreads();
+  resolve_and_report<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+}
+
+__device__ __forceinline__ void cg_final_dispatch(const Inst& d) {
+  switch (d.x_dtype) {
+    case TM_I8: cg_final<int8_t>(d); break;
+    case TM_F32: cg_final<float>(d); break;
+    case TM_BF16: cg_final<bf16_t>(d); break;
+    default: cg_final<f16_t>(d); break;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_t* list) {
+  if (list) cg_final_dispatch(tab.table[list[blockIdx.x]]);
+  else cg_final_dispatch(tab.one);
+}
+
+hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int count, int chunk, int prep_y,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cgemm_prep, dim3(count, prep_y), dim3(kCgPrepThreads), 0, s, tab, list, chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const dim3 grid(count, gemm_y);
+  if (max_limbs <= 3) hipLaunchKernelGGL(k_cgemm<3>, grid, dim3(256), 0, s, tab, list);
+  else hipLaunchKernelGGL(k_cgemm<5>, grid, dim3(256), 0, s, tab, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cgemm_final, dim3(count), dim3(256), 0, s, tab, list);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // plan-time kernels
 // --------------------------------------------------------------------------
 

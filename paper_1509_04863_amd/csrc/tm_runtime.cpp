@@ -42,6 +42,7 @@ int64_t env_int(const char* name, int64_t dflt) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 int64_t gcd64(int64_t a, int64_t b) {
   while (b) { const int64_t t = a % b; a = b; b = t; }
@@ -130,7 +131,11 @@ struct Core {
   int32_t band = 0, nband = 0;                    // band fold of 4-byte signals
   int32_t gfft = 0, g_q = 0, g_logb = 0;          // FFT through global memory
   size_t off_gz = 0, off_gss = 0, off_gpart = 0;
-  size_t acc_bytes = 0;     // integer bucket zone (int32 [ma + mb]); lives in the zeroed pool
+  size_t acc_bytes = 0;     // integer bucket zone (int32 [ma + mb], then the GEMM path's two
+                            // fold maxima); lives in the zeroed pool
+  // correlation as an int8 MFMA GEMM (exact path, int8-valued template)
+  int32_t cgemm = 0, c_nlcap = 0, c_lp = 0, c_ks = 0, c_rta = 0, c_rtb = 0, c_lt = 0;
+  size_t off_ylimb = 0, off_cpart = 0;
   size_t fold_lds = 0, finish_lds = 0;
   int fft_in_lds = 1;
 };
@@ -144,7 +149,20 @@ int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
   return std::min(cap, std::max<int64_t>(c.seg_chunks, want));
 }
 
-tm_status compute_core(const tm_plan_desc* d, Core* c) {
+// Literal-fold entries per prep workgroup: about 4096 workgroups over the
+// launch's entries, at least 1024 and at most one instance's pair of folds;
+// grid rows = chunks of the largest instance.
+struct CgLaunch { int chunk; int prep_y; };
+CgLaunch cgemm_launch(int64_t total_entries, int64_t max_entries, int64_t count) {
+  (void)count;
+  int64_t chunk = std::max<int64_t>(1024, align_up(ceil_div(total_entries, 4096), 256));
+  chunk = std::min(chunk, align_up(max_entries, 256));
+  return CgLaunch{(int)chunk, (int)ceil_div(max_entries, chunk)};
+}
+
+// t_i8: every template value is an integer in [-128, 127] (known for int8
+// templates without looking at them; checked on the values at plan creation)
+tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8) {
   if (!d) return fail(TM_ERR_INVALID, "null plan descriptor");
   if (d->n < 1) return fail(TM_ERR_INVALID, "N must be >= 1");
   if (d->k < 1 || (int64_t)d->k > d->n) return fail(TM_ERR_INVALID, "need 1 <= K <= N");
@@ -154,7 +172,8 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   if (fs != TM_F32 && fs != TM_BF16 && fs != TM_F16)
     return fail(TM_ERR_INVALID, "fold_store must be TM_F32, TM_BF16 or TM_F16");
   if (d->fold_mult < 0 || d->fold_mult > 2) return fail(TM_ERR_INVALID, "fold_mult must be 0, 1 or 2");
-  if (d->flags & ~(TM_F_EXACT | TM_F_REAL | TM_F_ZERO_PAD)) return fail(TM_ERR_INVALID, "unknown plan flags");
+  if (d->flags & ~(TM_F_EXACT | TM_F_REAL | TM_F_ZERO_PAD | TM_F_FFT))
+    return fail(TM_ERR_INVALID, "unknown plan flags");
   if ((d->flags & TM_F_EXACT) && (d->flags & TM_F_REAL))
     return fail(TM_ERR_INVALID, "TM_F_EXACT and TM_F_REAL are exclusive");
   if (d->n > (int64_t(1) << 40)) return fail(TM_ERR_INVALID, "N above 2^40 is not supported");
@@ -194,9 +213,14 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   while ((int64_t(1) << p) < need) ++p;
   c->p_log2 = p;
   c->fft_in_lds = p <= fft_lds_max_log2(c->mode);
+  // exact folds with an int8-valued template: correlation by the int8 GEMM
+  // unless the FFT is asked for (TM_F_FFT, or TM_CORR_GEMM=0 for the process)
+  c->cgemm = c->mode == MODE_EXACT && t_i8 && d->k <= kCgMaxK && !(d->flags & TM_F_FFT) &&
+             (int64_t)(c->ma + c->mb) * (d->k + 63) <= (int64_t(1) << 32) && std::max(c->ma, c->mb) <= (1 << 25) &&
+             env_int("TM_CORR_GEMM", 1) != 0;
   // TM_FFT_GLOBAL=1 also sends in-LDS lengths of 2^10 and more through global memory
   if (c->fft_in_lds && p >= 10 && env_int("TM_FFT_GLOBAL", 0) != 0) c->fft_in_lds = 0;
-  if (!c->fft_in_lds && p <= kGfftMaxLog2) {
+  if (!c->cgemm && !c->fft_in_lds && p <= kGfftMaxLog2) {
     // P = P1 x P2: blocks of B columns of P1 with B P1 = 4096 at most, rows of P2
     c->gfft = 1;
     c->g_logb = c->mode == MODE_EXACT ? 3 : 4;          // 128-byte row segments
@@ -250,7 +274,7 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
   if (c->acc_int) {
     // integer folds go straight to the bucket zone; the finish kernel forms
     // the literal folds from it
-    c->acc_bytes = align256((size_t)(c->ma + c->mb) * 4);
+    c->acc_bytes = align256((size_t)(c->ma + c->mb + 2) * 4);
     c->nred = 0;
   } else {
     const int nrb = std::max(c->va.nrb, c->dual ? 0 : c->vb.nrb);
@@ -272,6 +296,25 @@ tm_status compute_core(const tm_plan_desc* d, Core* c) {
     c->off_gpart = off;
     off = align256(off + ((P >> c->g_q) >> c->g_logb) * gfft_part_bytes());
   }
+  if (c->cgemm) {
+    // rows of 64 shifts, 16 rows per GEMM workgroup; digit rows long enough
+    // for the last row's band, in whole prep workgroups
+    c->c_ks = (int32_t)align_up(ceil_div(d->k + 63, 64), 4);
+    c->c_rta = (int32_t)ceil_div(ceil_div(c->ma, 64), kCgRows);
+    c->c_rtb = (int32_t)ceil_div(ceil_div(c->mb, 64), kCgRows);
+    const int64_t rtm = std::max(c->c_rta, c->c_rtb);
+    c->c_lp = (int32_t)(ceil_div(64 * kCgRows * rtm + 64 * (int64_t)c->c_ks, kCgPrepThreads) * kCgPrepThreads);
+    // digits needed by the largest possible |y|: L |x| for int8 and half
+    // signals, the int32 range otherwise
+    const int64_t lmax = std::max(ceil_div(d->n, c->ma), ceil_div(d->n, c->mb));
+    int64_t ymax = int64_t(1) << 31;
+    if (d->x_dtype == TM_I8) ymax = 128 * lmax;
+    if (d->x_dtype == TM_F16) ymax = std::min<int64_t>(ymax, 65504 * lmax);
+    c->c_nlcap = cgemm_limbs_for(ymax);
+    c->c_lt = (int32_t)align_up(std::max<int64_t>(d->k + kCgPad + 16, 64 * (int64_t)c->c_ks + kCgPad + 32), 16);
+    c->off_ylimb = off; off = align256(off + (size_t)2 * c->c_nlcap * c->c_lp);
+    c->off_cpart = off; off = align256(off + (size_t)2 * rtm * 4 * 2 * sizeof(double));
+  }
   c->off_res = off; off = align256(off + sizeof(tm_result));
   c->ws_bytes = off;
   c->fold_lds = std::max(fold_lds_bytes(c->va, d->x_dtype), c->dual ? 0 : fold_lds_bytes(c->vb, d->x_dtype));
@@ -289,6 +332,7 @@ void fill_info(const Core& c, tm_plan_info* info) {
   info->dual = c.dual;
   info->fft_in_lds = c.fft_in_lds;
   info->fft_global = c.gfft;
+  info->corr_gemm = c.cgemm;
   info->fold_tiles = c.ntiles;
   info->fold_segments = c.nseg;
   info->fold_bands = c.nband;
@@ -322,6 +366,10 @@ std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_live;   // recorded, not y
 std::vector<hipEvent_t> g_prof_free;
 double g_prof_ms = 0.0;
 int64_t g_prof_n = 0;
+// the correlation kernel (k_cgemm, or k_finish on the FFT path), same scheme
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_corr_live;
+double g_prof_corr_ms = 0.0;
+int64_t g_prof_corr_n = 0;
 
 hipError_t prof_event(hipEvent_t* e) {
   if (!g_prof_free.empty()) { *e = g_prof_free.back(); g_prof_free.pop_back(); return hipSuccess; }
@@ -337,6 +385,21 @@ hipError_t folds(const InstTable& tab, const FoldWork& w, hipStream_t s) {
   if (e != hipSuccess) return e;
   if ((e = launch_fold_s8(tab, w.segs, s)) != hipSuccess) return e;
   return launch_fold_band(tab, w.bands, s);
+}
+
+// events around one launch when profiling
+template <typename F>
+hipError_t timed_corr(hipStream_t s, F&& launch) {
+  if (!g_prof_on) return launch();
+  hipEvent_t a, b;
+  hipError_t e = prof_event(&a);
+  if (e != hipSuccess) return e;
+  if ((e = prof_event(&b)) != hipSuccess) return e;
+  if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
+  if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+  g_prof_corr_live.emplace_back(a, b);
+  return hipSuccess;
 }
 
 hipError_t timed_fold(const InstTable& tab, const FoldWork& w, hipStream_t s) {
@@ -454,6 +517,7 @@ struct tm_plan_s {
   void* tw_cols = nullptr;   // global-memory FFT: column blocks and rows
   void* tw_rows = nullptr;
   void* spec = nullptr;
+  int8_t* tsh = nullptr;     // GEMM path: 16 shifted copies of the zero-padded template
   double tnorm1 = 0.0;
 };
 
@@ -503,6 +567,14 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->tw_cols = p->tw_cols;
   in->tw_rows = p->tw_rows;
   in->tnorm1 = p->tnorm1;
+  in->cgemm = c.cgemm;
+  in->c_nlcap = c.c_nlcap;
+  in->c_lp = c.c_lp;
+  in->c_ks = c.c_ks;
+  in->c_rta = c.c_rta;
+  in->c_rtb = c.c_rtb;
+  in->c_lt = c.c_lt;
+  in->tsh = p->tsh;
 }
 
 void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
@@ -510,6 +582,11 @@ void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
     in->gz = base + c.off_gz;
     in->gss = reinterpret_cast<double*>(base + c.off_gss);
     in->gpart = base + c.off_gpart;
+  }
+  if (c.cgemm) {
+    in->ylimb = reinterpret_cast<int8_t*>(base + c.off_ylimb);
+    in->cpart = base + c.off_cpart;
+    in->cmax = reinterpret_cast<int*>(acc) + c.ma + c.mb;
   }
   if (c.acc_int) {
     in->yp = reinterpret_cast<int*>(acc);
@@ -524,7 +601,7 @@ void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
 
 tm_status check_plan_for_match(tm_plan p) {
   if (!p) return fail(TM_ERR_INVALID, "null plan");
-  if (!p->core.fft_in_lds && !p->core.gfft)
+  if (!p->core.cgemm && !p->core.fft_in_lds && !p->core.gfft)
     return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(p->core.p_log2) +
                                         " exceeds one workgroup's LDS on this build");
   return TM_OK;
@@ -578,7 +655,7 @@ const char* tm_last_error(void) { return g_err.c_str(); }
 tm_status tm_plan_params(const tm_plan_desc* desc, tm_plan_info* info) {
   if (!info) return fail(TM_ERR_INVALID, "null info");
   Core c;
-  const tm_status s = compute_core(desc, &c);
+  const tm_status s = compute_core(desc, &c, desc && desc->t_dtype == TM_I8);
   if (s != TM_OK) return s;
   fill_info(c, info);
   return TM_OK;
@@ -590,11 +667,8 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
   *out = nullptr;
   if (!t) return fail(TM_ERR_INVALID, "null template pointer");
   Core c;
-  tm_status st = compute_core(desc, &c);
+  tm_status st = compute_core(desc, &c, false);
   if (st != TM_OK) return st;
-  if (!c.fft_in_lds && !c.gfft)
-    return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(c.p_log2) + " is above 2^" +
-                                        std::to_string(kGfftMaxLog2));
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
   TM_HIP(hipGetDevice(&dev));
@@ -609,13 +683,20 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
     std::memcpy(th.data(), t, tb);
   }
   double norm1 = 0.0;
+  bool t_i8 = true;
   for (int64_t i = 0; i < c.k; ++i) {
     const double v = host_value(th.data(), c.t_dtype, i);
     if (!std::isfinite(v)) return fail(TM_ERR_INVALID, "template holds a non-finite value");
     if (c.mode == MODE_EXACT && v != std::nearbyint(v))
       return fail(TM_ERR_INVALID, "exact path needs an integer-valued template");
+    t_i8 = t_i8 && v == std::nearbyint(v) && v >= -128.0 && v <= 127.0;
     norm1 += std::fabs(v);
   }
+  st = compute_core(desc, &c, t_i8);
+  if (st != TM_OK) return st;
+  if (!c.cgemm && !c.fft_in_lds && !c.gfft)
+    return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(c.p_log2) + " is above 2^" +
+                                        std::to_string(kGfftMaxLog2));
 
   tm_plan_s* p = new tm_plan_s();
   p->desc = *desc;
@@ -628,6 +709,7 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
     if (z) (void)hipFree(z);
     if (p->t_dev) (void)hipFree(p->t_dev);
     if (p->spec) (void)hipFree(p->spec);
+    if (p->tsh) (void)hipFree(p->tsh);
     delete p;
   };
 #define TM_HIP_PLAN(expr)                                                              \
@@ -641,6 +723,22 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
   } while (0)
   TM_HIP_PLAN(hipMalloc(&p->t_dev, std::max<size_t>(tb, 16)));
   TM_HIP_PLAN(hipMemcpyAsync(p->t_dev, th.data(), tb, hipMemcpyHostToDevice, s));
+  if (c.cgemm) {
+    // the GEMM path needs no spectrum: 16 copies of [0 (pad + sh), t, 0 ...],
+    // byte q of copy sh stored at ((q / 16) * 16 + sh) * 16 + q % 16
+    const size_t lt = (size_t)c.c_lt;
+    std::vector<int8_t> h(16 * lt, 0);
+    for (size_t sh = 0; sh < 16; ++sh)
+      for (int64_t i = 0; i < c.k; ++i) {
+        const size_t q = kCgPad + sh + (size_t)i;
+        h[((q / 16) * 16 + sh) * 16 + q % 16] = (int8_t)host_value(th.data(), c.t_dtype, i);
+      }
+    TM_HIP_PLAN(hipMalloc(&p->tsh, h.size()));
+    TM_HIP_PLAN(hipMemcpyAsync(p->tsh, h.data(), h.size(), hipMemcpyHostToDevice, s));
+    TM_HIP_PLAN(hipStreamSynchronize(s));
+    *out = p;
+    return TM_OK;
+  }
   st = shared_twiddles(dev, c.p_log2, 1, s, &p->tw64);
   if (st == TM_OK && c.mode == MODE_REAL) st = shared_twiddles(dev, c.p_log2, 0, s, &p->tw32);
   if (st == TM_OK && c.gfft) st = shared_twiddles(dev, c.g_logb + c.g_q, c.mode == MODE_EXACT, s, &p->tw_cols);
@@ -667,6 +765,7 @@ tm_status tm_plan_destroy(tm_plan p) {
   TM_HIP(hipDeviceSynchronize());
   if (p->t_dev) TM_HIP(hipFree(p->t_dev));
   if (p->spec) TM_HIP(hipFree(p->spec));
+  if (p->tsh) TM_HIP(hipFree(p->tsh));
   delete p;
   return TM_OK;
 }
@@ -715,8 +814,16 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;                 // until the finish kernel is enqueued
   TM_HIP(launch_reduce(tab, p->core.nred, s));
-  if (p->core.gfft) TM_HIP(launch_gfft(tab.one, s));
-  else TM_HIP(launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2, p->core.finish_lds, s));
+  if (p->core.cgemm) {
+    const CgLaunch cl = cgemm_launch(2 * (int64_t)p->core.c_lp, 2 * (int64_t)p->core.c_lp, 1);
+    TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
+    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, p->core.c_rta + p->core.c_rtb,
+                                                        p->core.c_nlcap, s); }));
+    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
+  }
+  else if (p->core.gfft) TM_HIP(launch_gfft(tab.one, s));
+  else TM_HIP(timed_corr(s, [&] { return launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2,
+                                                        p->core.finish_lds, s); }));
   pool.acc_dirty = false;
   if (!dev_out) {
     TM_HIP(hipMemcpyAsync(out, tab.one.out, sizeof(tm_result), hipMemcpyDeviceToHost, s));
@@ -752,7 +859,7 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   std::vector<size_t> ws_off(count), acc_off(count);
   std::vector<int32_t> seg_chunks(count), nseg(count);
   size_t ws = 0, accb = 0;
-  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, launch_bytes = 0;
+  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, launch_bytes = 0, cps = 0, cp_max = 0, cgs = 0, cg_limbs_max = 0;
   size_t fold_lds = 0;
   for (int32_t i = 0; i < count; ++i) launch_bytes += plans[i]->core.n * dtype_bytes(plans[i]->core.x_dtype);
   for (int32_t i = 0; i < count; ++i) {
@@ -771,16 +878,26 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     segs += nseg[i];
     bands += c.nband;
     chunks += c.nred;
+    if (c.cgemm) {
+      cps += 2 * (int64_t)c.c_lp;
+      cp_max = std::max<int64_t>(cp_max, 2 * (int64_t)c.c_lp);
+      cgs = std::max<int64_t>(cgs, c.c_rta + c.c_rtb);
+      cg_limbs_max = std::max<int64_t>(cg_limbs_max, c.c_nlcap);
+    }
     fold_lds = std::max(fold_lds, c.fold_lds);
   }
-  if (tiles > 0x7fffffff || chunks > 0x7fffffff || segs > 0x7fffffff || bands > 0x7fffffff)
+  if (tiles > 0x7fffffff || chunks > 0x7fffffff || segs > 0x7fffffff || bands > 0x7fffffff ||
+      cps > 0x7fffffff || cgs > 0x7fffffff)
     return fail(TM_ERR_UNSUPPORTED, "batch too large");
-  // finish launches are grouped by (mode, FFT length) so each gets its own LDS size
+  // the GEMM-correlation instances first (one launch sequence for all of
+  // them), then the finish launches grouped by (mode, FFT length) so each gets
+  // its own LDS size
   std::vector<int32_t> order(count);
   for (int32_t i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     const Core& ca = plans[a]->core;
     const Core& cb = plans[b]->core;
+    if (ca.cgemm != cb.cgemm) return ca.cgemm > cb.cgemm;
     return ca.mode != cb.mode ? ca.mode < cb.mode : ca.p_log2 < cb.p_log2;
   });
   const size_t off_res = align256(ws);
@@ -837,7 +954,15 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;                 // until every finish kernel is enqueued
   TM_HIP(launch_reduce(tab, (int)chunks, s));
-  for (int32_t g0 = 0; g0 < count;) {
+  int32_t ncg_inst = 0;
+  while (ncg_inst < count && plans[order[ncg_inst]]->core.cgemm) ++ncg_inst;
+  if (ncg_inst > 0) {
+    const CgLaunch cl = cgemm_launch(cps, cp_max, ncg_inst);
+    TM_HIP(launch_cgemm_prep(tab, dlist, ncg_inst, cl.chunk, cl.prep_y, s));
+    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, dlist, ncg_inst, (int)cgs, (int)cg_limbs_max, s); }));
+    TM_HIP(launch_cgemm_final(tab, dlist, ncg_inst, s));
+  }
+  for (int32_t g0 = ncg_inst; g0 < count;) {
     const Core& c0 = plans[order[g0]]->core;
     int32_t g1 = g0 + 1;
     while (g1 < count && plans[order[g1]]->core.mode == c0.mode && plans[order[g1]]->core.p_log2 == c0.p_log2) ++g1;
@@ -856,9 +981,10 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   return TM_OK;
 }
 
-// One template, many signals of the plan's N: folds as in a batch, then the
-// correlation as an int8 MFMA GEMM (exact int8 plans with K <= 2^14 and folds
-// of at most 2^13 rows); other plans, or TM_MANY_FFT=1, take tm_match_batch.
+// One template, many signals of the plan's N: the signals' folds form the
+// rows of one int8 MFMA GEMM against the shared template (exact int8 plans
+// with K <= 2^14 and folds of at most 2^13 rows, not TM_F_FFT); other plans,
+// or TM_MANY_BATCH=1, take tm_match_batch (independent matches).
 tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_result* out, void* stream) {
   if (!p || count < 0) return fail(TM_ERR_INVALID, "null plan or negative count");
   if (count == 0) return TM_OK;
@@ -871,7 +997,8 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   }
   const Core& c = p->core;
   const bool gemm = c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.mode == MODE_EXACT && c.k <= (1 << 14) &&
-                    std::max(c.va.l, c.vb.l) <= (1 << 13) && env_int("TM_MANY_FFT", 0) == 0;
+                    std::max(c.va.l, c.vb.l) <= (1 << 13) && !(p->desc.flags & TM_F_FFT) &&
+                    env_int("TM_MANY_BATCH", 0) == 0;
   if (!gemm) {
     std::vector<tm_plan> plans((size_t)count, p);
     return tm_match_batch(count, plans.data(), xs, out, stream);
@@ -979,6 +1106,24 @@ tm_status tm_profile_read(double* fold_ms_total, int64_t* fold_launches, int res
   if (fold_ms_total) *fold_ms_total = g_prof_ms;
   if (fold_launches) *fold_launches = g_prof_n;
   if (reset) { g_prof_ms = 0.0; g_prof_n = 0; }
+  return TM_OK;
+}
+
+tm_status tm_profile_read_corr(double* ms_total, int64_t* launches, int reset) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& pr : g_prof_corr_live) {
+    TM_HIP(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    TM_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    g_prof_corr_ms += ms;
+    ++g_prof_corr_n;
+    g_prof_free.push_back(pr.first);
+    g_prof_free.push_back(pr.second);
+  }
+  g_prof_corr_live.clear();
+  if (ms_total) *ms_total = g_prof_corr_ms;
+  if (launches) *launches = g_prof_corr_n;
+  if (reset) { g_prof_corr_ms = 0.0; g_prof_corr_n = 0; }
   return TM_OK;
 }
 

@@ -238,7 +238,7 @@ tm_status tm_server_submit(tm_server s, tm_plan plan, const void* x, uint64_t* t
   tm_plan_info info;
   const tm_status st = tm_plan_get_info(plan, &info);
   if (st != TM_OK) return st;
-  if (!info.fft_in_lds && !info.fft_global) return TM_ERR_UNSUPPORTED;
+  if (!info.fft_in_lds && !info.fft_global && !info.corr_gemm) return TM_ERR_UNSUPPORTED;
   Req r;
   r.plan = plan;
   r.x = x;

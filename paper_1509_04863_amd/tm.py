@@ -20,14 +20,14 @@ LIB_PATH = os.path.join(HERE, "libtm.so")
 
 TM_OK, TM_ERR_INVALID, TM_ERR_NOMEM, TM_ERR_DEVICE, TM_ERR_UNSUPPORTED = range(5)
 TM_I8, TM_F32, TM_BF16, TM_F16 = range(4)
-TM_F_EXACT, TM_F_REAL, TM_F_ZERO_PAD = 0x1, 0x2, 0x4
+TM_F_EXACT, TM_F_REAL, TM_F_ZERO_PAD, TM_F_FFT = 0x1, 0x2, 0x4, 0x8
 TM_R_NOMATCH, TM_R_RESCORED, TM_R_NEAR_TIE, TM_R_EXACT = 0x1, 0x2, 0x4, 0x8
 
 EXPORTS = ["tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_info", "tm_match",
            "tm_match_batch", "tm_match_intermediates", "tm_status_string", "tm_last_error",
            "tm_version", "tm_profile_enable", "tm_profile_read", "tm_server_create", "tm_server_submit",
            "tm_server_poll", "tm_server_wait", "tm_server_get_stats", "tm_server_destroy",
-           "tm_admit_batches", "tm_match_many"]
+           "tm_admit_batches", "tm_match_many", "tm_profile_read_corr"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -43,6 +43,7 @@ class PlanInfo(ctypes.Structure):
                 ("dual", ctypes.c_int32), ("fft_in_lds", ctypes.c_int32),
                 ("fold_tiles", ctypes.c_int32), ("fold_segments", ctypes.c_int32),
                 ("fold_bands", ctypes.c_int32), ("fft_global", ctypes.c_int32),
+                ("corr_gemm", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("x_bytes", ctypes.c_int64)]
 
 
@@ -107,6 +108,8 @@ def lib():
         L.tm_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int]
         L.tm_profile_read.restype = ctypes.c_int
+        L.tm_profile_read_corr.argtypes = L.tm_profile_read.argtypes
+        L.tm_profile_read_corr.restype = ctypes.c_int
         u64p, i64p = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)
         L.tm_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(vp)]
         L.tm_server_submit.argtypes = [vp, vp, vp, u64p]
@@ -355,7 +358,8 @@ def match_intermediates(plan: Plan, x, stream=None):
 
 
 def profile_enable(on: bool = True):
-    """Record HIP events around every fold kernel launch (tm_profile_enable)."""
+    """Record HIP events around every fold kernel launch and every correlation
+    kernel launch (tm_profile_enable)."""
     _check(lib().tm_profile_enable(1 if on else 0))
 
 
@@ -364,6 +368,15 @@ def profile_read(reset: bool = False):
     ms = ctypes.c_double()
     n = ctypes.c_int64()
     _check(lib().tm_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
+
+
+def profile_read_corr(reset: bool = False):
+    """(summed correlation kernel milliseconds, launches) since the last reset:
+    the int8 matrix-product kernel, or the in-LDS FFT finish kernel."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().tm_profile_read_corr(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
 
 

@@ -23,26 +23,39 @@ def gpu_match(x, t, m1=0, m2=0, fold_mult=1, flags=0, fold_store=tm.TM_F32, x_de
 
 
 def assert_exact_parity(x, t, m1=0, m2=0, fold_mult=1, flags=0, x_oracle=None, t_oracle=None, x_dev=None):
-    """Bit-exact comparison of every intermediate and output (integer data)."""
-    res, y1, y2, r1, r2, plan = gpu_match(x, t, m1, m2, fold_mult, flags, x_dev=x_dev)
+    """Bit-exact comparison of every intermediate and output (integer data).
+    When the plan computes the correlation by the int8 matrix product, the FFT
+    correlation (TM_F_FFT) is checked as well: both must match the oracle."""
     xo = x if x_oracle is None else x_oracle
     to = t if t_oracle is None else t_oracle
-    ref = O.ftm(xo, to, plan.m1, plan.m2)
-    k = t.shape[0]
-    assert np.array_equal(y1, ref.y1[:plan.m1 + k - 1].astype(np.float64)), "fold M1"
-    assert np.array_equal(y2, ref.y2[:plan.m2 + k - 1].astype(np.float64)), "fold M2"
-    assert np.array_equal(r1, ref.r1.astype(np.float64)), "correlation M1"
-    assert np.array_equal(r2, ref.r2.astype(np.float64)), "correlation M2"
-    assert (res.m1_tilde, res.m2_tilde) == (ref.m1_tilde, ref.m2_tilde)
-    assert res.n_candidates == ref.n_candidates
-    assert res.shift == ref.shift
-    assert res.peak1 == float(ref.peak1) and res.peak2 == float(ref.peak2)
-    if ref.shift != O.NOMATCH:
-        assert res.score == float(ref.score)
-    assert bool(res.flags & tm.TM_R_NOMATCH) == (ref.shift == O.NOMATCH)
-    assert bool(res.flags & tm.TM_R_RESCORED) == (ref.n_candidates > 1)
-    assert res.flags & tm.TM_R_EXACT
-    return res, ref
+    ref = None
+    out = None
+    variants = [flags] if flags & tm.TM_F_FFT else [flags, flags | tm.TM_F_FFT]
+    for fl in variants:
+        res, y1, y2, r1, r2, plan = gpu_match(x, t, m1, m2, fold_mult, fl, x_dev=x_dev)
+        if ref is None:
+            ref = O.ftm(xo, to, plan.m1, plan.m2)
+        k = t.shape[0]
+        assert np.array_equal(y1, ref.y1[:plan.m1 + k - 1].astype(np.float64)), "fold M1"
+        assert np.array_equal(y2, ref.y2[:plan.m2 + k - 1].astype(np.float64)), "fold M2"
+        assert np.array_equal(r1, ref.r1.astype(np.float64)), "correlation M1"
+        assert np.array_equal(r2, ref.r2.astype(np.float64)), "correlation M2"
+        assert (res.m1_tilde, res.m2_tilde) == (ref.m1_tilde, ref.m2_tilde)
+        assert res.n_candidates == ref.n_candidates
+        assert res.shift == ref.shift
+        assert res.peak1 == float(ref.peak1) and res.peak2 == float(ref.peak2)
+        if ref.shift != O.NOMATCH:
+            assert res.score == float(ref.score)
+        assert bool(res.flags & tm.TM_R_NOMATCH) == (ref.shift == O.NOMATCH)
+        assert bool(res.flags & tm.TM_R_RESCORED) == (ref.n_candidates > 1)
+        assert res.flags & tm.TM_R_EXACT
+        if out is None:
+            out = res
+        else:
+            assert res == out, "GEMM and FFT correlations disagree"
+        if not plan.info["corr_gemm"]:
+            break
+    return out, ref
 
 
 def normwise(a, b):

@@ -70,6 +70,7 @@ def test_explicit_moduli_and_orientation():
     dict(n=100, k=10, fold_store=1 << 5),
     dict(n=100, k=10, flags=0x100),
     dict(n=100, k=10, flags=tm.TM_F_EXACT | tm.TM_F_REAL),
+    dict(n=100, k=10, flags=0x10),
 ])
 def test_invalid_plans_are_rejected(kw):
     with pytest.raises(tm.TMError) as e:
@@ -90,9 +91,11 @@ def test_modes():
 def test_fft_length_limits():
     # exact path keeps P <= 2^13 in one workgroup's LDS, the real path P <= 2^14;
     # above that the four-step transform through global memory takes over, up to 2^21
-    info = tm.plan_params(1 << 22, 4096)
-    assert info["fft_in_lds"] == 1 and info["fft_global"] == 0
-    info = tm.plan_params(1 << 24, 8192)
+    # (TM_F_FFT: exact plans with an int8 template otherwise take the int8 matrix product)
+    F = tm.TM_F_FFT
+    info = tm.plan_params(1 << 22, 4096, flags=F)
+    assert info["fft_in_lds"] == 1 and info["fft_global"] == 0 and info["corr_gemm"] == 0
+    info = tm.plan_params(1 << 24, 8192, flags=F)
     assert info["fft_in_lds"] == 0 and info["fft_global"] == 1
     assert tm.plan_params(1 << 24, 8192, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32)["fft_in_lds"] == 1
     info = tm.plan_params(1 << 24, 1 << 14, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32)
@@ -100,6 +103,22 @@ def test_fft_length_limits():
     assert tm.plan_params(1 << 26, 1 << 16)["fft_global"] == 1          # Section 5 tables: P = 2^17
     info = tm.plan_params(1 << 30, 1 << 21)                              # P = 2^22: no path
     assert info["fft_in_lds"] == 0 and info["fft_global"] == 0
+
+
+def test_correlation_route():
+    # exact int8 plans: the int8 matrix product up to (M1 + M2)(K + 63) <= 2^32
+    # and K <= 2^17; then the FFT; never on the real path
+    info = tm.plan_params(1 << 22, 4096)
+    assert info["corr_gemm"] == 1 and info["fft_global"] == 0
+    assert tm.plan_params(1 << 24, 8192)["corr_gemm"] == 1
+    assert tm.plan_params(1 << 25, 1 << 15)["corr_gemm"] == 1
+    assert tm.plan_params(1 << 26, 1 << 16)["corr_gemm"] == 0
+    assert tm.plan_params(1 << 22, 4096, flags=tm.TM_F_REAL)["corr_gemm"] == 0
+    assert tm.plan_params(1 << 22, 4096, x_dtype=tm.TM_F32, t_dtype=tm.TM_F32)["corr_gemm"] == 0
+    # the workspace holds the digit rows: more than the FFT route needs
+    a = tm.plan_params(1 << 22, 4096)["workspace_bytes"]
+    b = tm.plan_params(1 << 22, 4096, flags=tm.TM_F_FFT)["workspace_bytes"]
+    assert a > b
 
 
 def test_plan_create_without_device_fails_cleanly():

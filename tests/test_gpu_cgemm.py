@@ -1,0 +1,126 @@
+"""The correlation of exact plans as an int8 MFMA matrix product: limb counts
+from one to five digits, extreme int8 values, templates given as float,
+batches that mix it with the FFT correlations, and agreement with TM_F_FFT
+and with the oracle on every intermediate."""
+
+import numpy as np
+import pytest
+
+from oracle import ftm as O
+from paper_1509_04863_amd import datagen as G
+from paper_1509_04863_amd import tm
+
+from _util import assert_exact_parity, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _case(*a):
+    print("case:", *a, flush=True)
+
+
+def test_plan_reports_gemm_route():
+    t = np.ones(512, dtype=np.int8)
+    assert tm.Plan(t, n=1 << 16).info["corr_gemm"] == 1
+    assert tm.Plan(t, n=1 << 16, flags=tm.TM_F_FFT).info["corr_gemm"] == 0
+    tf = np.full(512, 300.0, dtype=np.float32)           # outside int8: FFT route
+    assert tm.Plan(tf, n=1 << 16, x_dtype=tm.TM_F32, flags=tm.TM_F_EXACT).info["corr_gemm"] == 0
+    tf[:] = -128.0
+    assert tm.Plan(tf, n=1 << 16, x_dtype=tm.TM_F32, flags=tm.TM_F_EXACT).info["corr_gemm"] == 1
+    assert tm.Plan(tf, n=1 << 16, x_dtype=tm.TM_F32).info["corr_gemm"] == 0   # real path
+
+
+@pytest.mark.parametrize("lo,hi,n,k,label", [
+    (-1, 2, 60000, 700, "1-2 digits"),
+    (-128, 128, 3 << 16, 700, "3 digits (int8 extremes)"),
+    (-128, 128, 1 << 20, 300, "3 digits, raised M"),
+])
+def test_int8_value_ranges(lo, hi, n, k, label):
+    rng = np.random.default_rng(n + k)
+    x = rng.integers(lo, hi, n).astype(np.int8)
+    x[: n // 3] = 127 if hi > 2 else x[: n // 3]          # long runs: large fold values
+    t = rng.integers(lo, hi, k).astype(np.int8)
+    t[:5] = -128 if lo <= -128 else t[:5]
+    _case(label, n, k)
+    assert_exact_parity(x, t)
+
+
+@pytest.mark.parametrize("scale,label", [(3000, "4 digits"), (1000000, "5 digits")])
+def test_fp32_integer_signals_need_more_digits(scale, label):
+    # nearly constant signals: every fold entry is close to L * scale
+    # (L = 400: 1.2e6 needs four base-128 digits, 4e8 five); a sparse template
+    # keeps the FFT variant's exactness bound below 1/2 as well
+    rng = np.random.default_rng(scale)
+    n, k = 200000, 500
+    x = np.full(n, scale, dtype=np.float32)
+    x[rng.choice(n, n // 100, replace=False)] = -scale
+    t = np.zeros(k, dtype=np.float32)
+    t[rng.choice(k, 5, replace=False)] = rng.choice([-127.0, 127.0], 5)
+    _case(label, n, k)
+    assert_exact_parity(x, t, flags=tm.TM_F_EXACT)
+
+
+def test_swapped_and_explicit_moduli():
+    inst = G.planted_pm1(300000, 600, config_id=91, index=0, flip_frac=0.05, shift=299000)
+    _case("swapped")
+    assert_exact_parity(inst.x, inst.t, m1=701, m2=700)
+    _case("non-consecutive")
+    assert_exact_parity(inst.x, inst.t, m1=1000, m2=1003)
+
+
+def test_small_moduli_and_tiny_signals():
+    for n, k in [(10, 3), (64, 64), (200, 7), (1000, 1)]:
+        inst = G.planted_pm1(n, k, config_id=91, index=n, flip_frac=0.0, shift=n // 3)
+        _case("tiny", n, k)
+        assert_exact_parity(inst.x, inst.t)
+
+
+def test_mixed_batch_gemm_fft_real():
+    rng = np.random.default_rng(5)
+    plans, xs, refs = [], [], []
+    for i in range(24):
+        n = int(rng.integers(3000, 200000))
+        k = int(rng.integers(1, min(n, 3000)))
+        kind = i % 4
+        inst = G.planted_pm1(n, k, config_id=92, index=i, flip_frac=0.05)
+        if kind == 0:                        # int8: GEMM
+            x, t, flags = inst.x, inst.t, 0
+        elif kind == 1:                      # int8 forced FFT
+            x, t, flags = inst.x, inst.t, tm.TM_F_FFT
+        elif kind == 2:                      # fp32 exact: GEMM
+            x, t, flags = inst.x.astype(np.float32), inst.t.astype(np.float32), tm.TM_F_EXACT
+        else:                                # fp32 real: FFT in FP32
+            x = rng.standard_normal(n).astype(np.float32)
+            t, flags = x[:k].copy(), 0
+        plans.append(tm.Plan(t, n=n, x_dtype=tm.tm_dtype_of(x), flags=flags))
+        xs.append(to_device(x))
+        refs.append((x, t, kind))
+    _case("mixed batch")
+    out = tm.match_batch(plans, xs)
+    single = [tm.match(p, x) for p, x in zip(plans, xs)]
+    assert out == single
+    for (x, t, kind), p, r in zip(refs, plans, out):
+        if kind == 3:
+            continue
+        ref = O.ftm(x.astype(np.int64), t.astype(np.int64), p.m1, p.m2)
+        assert (r.shift, r.m1_tilde, r.m2_tilde, r.n_candidates) == \
+            (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
+        assert r.peak1 == float(ref.peak1) and r.peak2 == float(ref.peak2)
+        assert r.flags & tm.TM_R_EXACT
+
+
+def test_repeat_determinism_and_bucket_reset():
+    inst = G.config2(0)
+    plan = tm.Plan(inst.t.astype(np.float32), n=inst.x.shape[0], x_dtype=tm.TM_F32, flags=tm.TM_F_EXACT)
+    assert plan.info["corr_gemm"] == 1
+    xd = to_device(inst.x.astype(np.float32))
+    _case("config2 repeat")
+    first = tm.match(plan, xd)
+    for _ in range(5):
+        assert tm.match(plan, xd) == first
+    ref = O.ftm(inst.x, inst.t, plan.m1, plan.m2, correlation="fft")
+    assert (first.shift, first.m1_tilde, first.m2_tilde) == (ref.shift, ref.m1_tilde, ref.m2_tilde)

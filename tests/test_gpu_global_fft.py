@@ -42,7 +42,7 @@ EXACT = [
 @pytest.mark.parametrize("n,k,m1,m2,dt", EXACT)
 def test_global_fft_exact(n, k, m1, m2, dt):
     inst = G.planted_pm1(n, k, 95, n + k, flip_frac=0.1, x_dtype=dt)
-    flags = tm.TM_F_EXACT if dt == np.float32 else 0
+    flags = (tm.TM_F_EXACT if dt == np.float32 else 0) | tm.TM_F_FFT
     info = tm.plan_params(n, k, m1=m1, m2=m2, x_dtype=tm.tm_dtype_of(inst.x), t_dtype=tm.tm_dtype_of(inst.t),
                           flags=flags)
     assert info["fft_global"] == 1 and info["exact"] == 1
@@ -92,7 +92,7 @@ def test_global_fft_fold_storage(store, bound):
 def test_batch_with_global_and_lds_instances():
     shapes = [(1 << 20, 6000), (70000, 700), (3 << 18, 9000), (1 << 18, 2048), (20000, 8000)]
     insts = [G.planted_pm1(n, k, 97, i, flip_frac=0.07) for i, (n, k) in enumerate(shapes)]
-    plans = [tm.Plan(s.t, n=s.n) for s in insts]
+    plans = [tm.Plan(s.t, n=s.n, flags=tm.TM_F_FFT) for s in insts]
     assert sum(p.info["fft_global"] for p in plans) == 3
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
     _case("global batch")

@@ -1,6 +1,6 @@
-"""One template, many signals: the int8 MFMA GEMM correlation (tm_match_many)
-must give every signal the result tm_match gives it, bit for bit, and the
-oracle's shift, residues and peaks."""
+"""One template, many signals: the shared-template int8 MFMA GEMM correlation
+(tm_match_many) must give every signal the result tm_match gives it, bit for
+bit, and the oracle's shift, residues and peaks."""
 
 import numpy as np
 import pytest
@@ -79,7 +79,8 @@ def test_fft_and_gemm_paths_agree(monkeypatch):
     insts = G.config5b_batch(count=48, n=1 << 16, k=512, flip_frac=0.05)
     plan = tm.Plan(insts[0].t, n=1 << 16)
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
-    gemm = tm.Many(plan, xs).match()
-    monkeypatch.setenv("TM_MANY_FFT", "1")
-    fft = tm.Many(plan, xs).match()
-    assert gemm == fft
+    shared = tm.Many(plan, xs).match()
+    fft = tm.Many(tm.Plan(insts[0].t, n=1 << 16, flags=tm.TM_F_FFT), xs).match()
+    monkeypatch.setenv("TM_MANY_BATCH", "1")
+    per_instance = tm.Many(plan, xs).match()
+    assert shared == fft == per_instance
