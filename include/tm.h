@@ -97,6 +97,14 @@ typedef struct {
   int32_t fold_store; /* real path only: storage format of the folded signal fed to
                          the FFT: TM_F32 (default), TM_BF16 or TM_F16 */
   uint32_t flags;     /* TM_F_* */
+  int32_t top_t;      /* 0 or 1: steps 8-9 as printed.  2..4: top-T re-scoring, a
+                         robustness option beyond the paper: the T largest entries of
+                         each correlation (lowest index first among equal values)
+                         give T x T residue pairs, and the union of their candidate
+                         sets is re-scored by (Tx)_c (exact on the exact path, FP64
+                         otherwise).  m1_tilde / m2_tilde and the peaks stay the
+                         argmaxes of step 7; n_candidates counts the union. */
+  int32_t reserved;   /* 0 */
 } tm_plan_desc;
 
 typedef struct tm_plan_s* tm_plan;
@@ -106,7 +114,7 @@ typedef struct {
   int32_t  m1_tilde;     /* argmax over [0, M1) of the M1-fold correlation (step 7) */
   int32_t  m2_tilde;     /* argmax over [0, M2) of the M2-fold correlation */
   int32_t  n_candidates; /* |S_M1 cap S_M2| before re-scoring, 0..3 (0..1 with
-                            TM_F_ZERO_PAD) */
+                            TM_F_ZERO_PAD; up to 3 T^2 with top-T) */
   uint32_t flags;        /* TM_R_* */
   double   peak1;        /* r_M1[m1_tilde] (an integer on the exact path) */
   double   peak2;        /* r_M2[m2_tilde] */

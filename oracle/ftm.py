@@ -39,6 +39,10 @@ Readings taken where the paper is silent, ambiguous or inconsistent
   R9  Step 9 assumes a single common element.  With several, each candidate c
       is re-scored by (Tx)_c and the largest wins (lowest index on ties);
       with none, the result is -1 ("no match").
+  R9T Top-T re-scoring (a robustness option beyond the paper, off by
+      default): the T largest entries of each correlation (lowest index on
+      ties) give T x T residue pairs; the union of their candidate sets is
+      re-scored by (Tx)_c as in R9.  T = 1 is step 9 itself.
   R11 Step 2 asks for M1 M2 > N with M1 = K, M2 = K + 1 (Section 4); when
       K (K + 1) <= N that choice is infeasible, and the automatic rule raises
       M1 to the least m with m (m + 1) > N.  fold_mult c in {1, 2} scales the
@@ -275,14 +279,28 @@ def candidate_set_zero_pad(m_tilde: int, m: int, n: int) -> set:
     return {m_tilde + i * m for i in range(L) if m_tilde + i * m < n}
 
 
-def resolve(x: np.ndarray, t: np.ndarray, m1_tilde: int, m2_tilde: int, m1: int, m2: int,
+def top_indices(r: np.ndarray, count: int) -> List[int]:
+    """The `count` largest entries of r by value, lowest index first among
+    equal values (R7 extended to the runners-up, reading R9T)."""
+    order = sorted(range(r.shape[0]), key=lambda i: (-r[i], i))
+    return [int(i) for i in order[:count]]
+
+
+def resolve(x: np.ndarray, t: np.ndarray, m1_tilde, m2_tilde, m1: int, m2: int,
             variant: str = "cyclic"):
     """Step 9: C = S_{M1} cap S_{M2} by literal set intersection; several
-    members are re-scored by (Tx)_c (reading R9).  Returns
-    (shift, sorted candidates, score of the shift or None)."""
+    members are re-scored by (Tx)_c (reading R9).  m1_tilde and m2_tilde may
+    be lists of residues (top-T, reading R9T): C is then the union over all
+    pairs.  Returns (shift, sorted candidates, score of the shift or None)."""
     n = x.shape[0]
     cs = candidate_set if variant == "cyclic" else candidate_set_zero_pad
-    common = sorted(cs(m1_tilde, m1, n) & cs(m2_tilde, m2, n))
+    a_list = m1_tilde if isinstance(m1_tilde, (list, tuple)) else [m1_tilde]
+    b_list = m2_tilde if isinstance(m2_tilde, (list, tuple)) else [m2_tilde]
+    common = set()
+    for a in a_list:
+        for b in b_list:
+            common |= cs(a, m1, n) & cs(b, m2, n)
+    common = sorted(common)
     if not common:
         return NOMATCH, common, None
     best, best_score = None, None
@@ -315,7 +333,8 @@ class OracleResult:
 
 
 def ftm(x: np.ndarray, t: np.ndarray, m1: Optional[int] = None, m2: Optional[int] = None,
-        fold_mult: int = 1, correlation: str = "direct", variant: str = "cyclic") -> OracleResult:
+        fold_mult: int = 1, correlation: str = "direct", variant: str = "cyclic",
+        top_t: int = 1) -> OracleResult:
     """Algorithm 1 (FTM) end to end, in the paper's step order.
 
     correlation="direct" is the oracle proper; "fft" swaps in the float64 FFT
@@ -323,7 +342,9 @@ def ftm(x: np.ndarray, t: np.ndarray, m1: Optional[int] = None, m2: Optional[int
     variant="cyclic" is Algorithm 1 as printed (fold of length M + K with
     indices mod N, Theorem 1); "zero_pad" is the Theorem 2 variant (fold of
     the zero-padded x of length M, circular correlation of length M, reading
-    R4z).  In the zero_pad result y1, y2 have length M."""
+    R4z).  In the zero_pad result y1, y2 have length M.
+    top_t > 1 re-scores the candidates of the T x T pairs of runners-up
+    (reading R9T); m1_tilde and m2_tilde stay the argmaxes of step 7."""
     if variant not in ("cyclic", "zero_pad"):
         raise ValueError("variant must be 'cyclic' or 'zero_pad'")
     n, k = x.shape[0], t.shape[0]
@@ -353,7 +374,15 @@ def ftm(x: np.ndarray, t: np.ndarray, m1: Optional[int] = None, m2: Optional[int
     i1 = argmax_lowest(r1) if correlation == "direct" else int(np.argmax(r1))
     i2 = argmax_lowest(r2) if correlation == "direct" else int(np.argmax(r2))
     # steps 8-9
-    shift, cands, score = resolve(x, t, i1, i2, m1, m2, variant)
+    if top_t > 1:
+        a_list, b_list = top_indices(r1, top_t), top_indices(r2, top_t)
+        if correlation == "direct":
+            assert a_list[0] == i1 and b_list[0] == i2
+        else:
+            i1, i2 = a_list[0], b_list[0]
+        shift, cands, score = resolve(x, t, a_list, b_list, m1, m2, variant)
+    else:
+        shift, cands, score = resolve(x, t, i1, i2, m1, m2, variant)
     return OracleResult(shift=shift, m1_tilde=i1, m2_tilde=i2, candidates=cands, score=score,
                         peak1=r1[i1], peak2=r2[i2], m1=m1, m2=m2, y1=y1, y2=y2, r1=r1, r2=r2)
 

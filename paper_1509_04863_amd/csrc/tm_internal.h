@@ -37,6 +37,8 @@ struct alignas(16) Inst {
   int32_t swapped;        // 1: the user's M1 is mb (results are mapped back)
   int32_t zpad;           // 1: zero-padded variant (partition folds, circular correlation,
                           //    no wrapped candidates)
+  int32_t top_t;          // runners-up per fold whose residue pairs are re-scored (1: step 9)
+  int32_t top_pad;
   int32_t p_log2;         // FFT length P = 2^p_log2
   View va;                // view with modulus ma (always tiled)
   View vb;                // view with modulus mb (tiled only when !dual)
@@ -72,6 +74,7 @@ struct alignas(16) Inst {
   void* cpart;            // [2 folds][max(c_rta, c_rtb) * 4] best (value, shift) per wave
   int* cmax;              // [2] largest |y| per fold (in the zeroed bucket zone)
   const int8_t* tsh;      // 16 copies of the zero-padded template, copy c shifted by c bytes
+  double* rtop;           // top-T on the GEMM and four-step routes: r of fold A [ma], then B [mb]
   int64_t inv_a_mod_b;    // ma^{-1} mod mb
   // workspace (device)
   void* col_a;            // [va.nrb][ma] column partials
@@ -144,6 +147,7 @@ constexpr int kCgRows = 16;                         // rows (64-shift blocks) pe
 constexpr int kCgMaxLimbs = 5;                      // balanced base-128 digits of int32 folds
 constexpr int kCgMaxK = 1 << 17;                    // int32 limb sums stay exact below this K
 constexpr int kCgPrepThreads = 256;
+constexpr int kTopTMax = 4;                         // runners-up per fold for top-T re-scoring
 
 // Arguments of the shared-template kernels (one plan, `count` signals).
 struct ManyArgs {

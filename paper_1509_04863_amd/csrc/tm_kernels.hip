@@ -1223,43 +1223,47 @@ __device__ FinRed block_finred(FinRed mine, FinRed* scratch) {
 }
 
 // Steps 8-9 (Theorem 4): S_A(a) cap S_B(b) with the candidate sets taken mod
-// N (or cut at N for the zero-padded variant of Theorem 2), re-scoring of
-// several candidates by (Tx)_c, and the result record.
+// N (or cut at N for the zero-padded variant of Theorem 2), for every pair of
+// the given residues of fold A and fold B (one each for step 9 itself; the
+// runners-up for top-T re-scoring), the union re-scored by (Tx)_c, and the
+// result record.
 template <typename Tin>
-__device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
+__device__ void resolve_lists(const Inst& d, const VI* A, int na, const VI* B, int nb, uint32_t flags,
+                              void* scratch) {
   const int tid = threadIdx.x;
   const int ma = d.va.m, mb = d.vb.m;
-  __shared__ long long cand[4];
+  __shared__ long long cand[3 * kTopTMax * kTopTMax];
   __shared__ int ncand;
   if (tid == 0) {
     const int64_t N = d.n;
-    const int64_t A = ma, B = mb, La = d.va.l, Lb = d.vb.l;
-    const int64_t a = amax.i, b = bmax.i;
-    long long c0 = -1, c1 = -1, c2 = -1;   // ascending, -1 = unused
-    auto insert = [&](long long v) {
-      if (v == c0 || v == c1 || v == c2) return;
-      if (c0 < 0 || v < c0) { c2 = c1; c1 = c0; c0 = v; }
-      else if (c1 < 0 || v < c1) { c2 = c1; c1 = v; }
-      else c2 = v;
-    };
-    // regular members {a + iA < N} and {b + jB < N}: Chinese remaindering
-    if (a < N && b < N) {
-      const int64_t t = ((((b - a) % B) + B) % B) * d.inv_a_mod_b % B;
-      const int64_t v = a + A * t;
-      if (v < N) insert(v);
-    }
-    // the wrapped members (a + (La-1) A) mod N and (b + (Lb-1) B) mod N; the
-    // zero-padded variant's sets stop at N
-    const bool wa = !d.zpad && a + (La - 1) * A >= N;
-    const bool wb = !d.zpad && b + (Lb - 1) * B >= N;
-    const int64_t va = (a + (La - 1) * A) % N;
-    const int64_t vb = (b + (Lb - 1) * B) % N;
-    if (wa && ((b < N && va % B == b) || (wb && va == vb))) insert(va);
-    if (wb && (a < N && vb % A == a)) insert(vb);
+    const int64_t Am = ma, Bm = mb, La = d.va.l, Lb = d.vb.l;
     int w = 0;
-    if (c0 >= 0) cand[w++] = c0;
-    if (c1 >= 0) cand[w++] = c1;
-    if (c2 >= 0) cand[w++] = c2;
+    auto insert = [&](long long v) {          // ascending, no repeats
+      int p = 0;
+      while (p < w && cand[p] < v) ++p;
+      if (p < w && cand[p] == v) return;
+      for (int q = w; q > p; --q) cand[q] = cand[q - 1];
+      cand[p] = v;
+      ++w;
+    };
+    for (int ia = 0; ia < na; ++ia)
+      for (int ib = 0; ib < nb; ++ib) {
+        const int64_t a = A[ia].i, b = B[ib].i;
+        // regular members {a + i A < N} and {b + j B < N}: Chinese remaindering
+        if (a < N && b < N) {
+          const int64_t t = ((((b - a) % Bm) + Bm) % Bm) * d.inv_a_mod_b % Bm;
+          const int64_t v = a + Am * t;
+          if (v < N) insert(v);
+        }
+        // the wrapped members (a + (La-1) A) mod N and (b + (Lb-1) B) mod N; the
+        // zero-padded variant's sets stop at N
+        const bool wa = !d.zpad && a + (La - 1) * Am >= N;
+        const bool wb = !d.zpad && b + (Lb - 1) * Bm >= N;
+        const int64_t va = (a + (La - 1) * Am) % N;
+        const int64_t vb = (b + (Lb - 1) * Bm) % N;
+        if (wa && ((b < N && va % Bm == b) || (wb && va == vb))) insert(va);
+        if (wb && (a < N && vb % Am == a)) insert(vb);
+      }
     ncand = w;
   }
   __syncthreads();
@@ -1272,6 +1276,7 @@ __device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t fla
   }
   if (nc == 0) flags |= TM_R_NOMATCH;
   if (nc > 1) flags |= TM_R_RESCORED;
+  const VI amax = A[0], bmax = B[0];
   if (tid == 0) {
     GAS tm_result* r = G(d.out);
     r->shift = best;
@@ -1283,6 +1288,53 @@ __device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t fla
     r->peak2 = d.swapped ? amax.v : bmax.v;
     r->score = nc ? best_score : 0.0;
   }
+}
+
+template <typename Tin>
+__device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
+  resolve_lists<Tin>(d, &amax, 1, &bmax, 1, flags, scratch);
+}
+
+// Runners-up of one fold for top-T (reading of the option: value descending,
+// lowest index first among equal values): top[0] holds the argmax; passes
+// p = 1..T-1 take the best entry not yet taken.  Returns how many exist
+// (fewer than T when M < T).  value_of(n) gives r[n] for n < m.
+template <typename F>
+__device__ int block_top_t(F value_of, int m, int T, VI (&top)[kTopTMax], VI* scratch) {
+  int got = 1;
+#pragma unroll
+  for (int p = 1; p < kTopTMax; ++p) {
+    if (p >= T) break;                       // uniform over the block
+    VI mine{-INFINITY, 0x7fffffff};
+    for (int n = threadIdx.x; n < m; n += blockDim.x) {
+      bool taken = false;
+#pragma unroll
+      for (int q = 0; q < kTopTMax; ++q)
+        if (q < p && top[q].i == n) taken = true;
+      if (taken) continue;
+      const VI v{value_of(n), n};
+      if (vi_better(v, mine)) mine = v;
+    }
+    const VI r = block_argmax(mine, scratch);
+    if (r.i == 0x7fffffff) break;            // uniform: every thread sees the same r
+    top[p] = r;
+    got = p + 1;
+  }
+  return got;
+}
+
+// top-T re-scoring from the whole correlations in `rtop` (fold A at 0, fold B
+// at ma), given both argmaxes
+template <typename Tin>
+__device__ void resolve_top_t(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
+  const int ma = d.va.m, mb = d.vb.m;
+  const GAS double* r = G(d.rtop);
+  VI A[kTopTMax], B[kTopTMax];
+  A[0] = amax;
+  B[0] = bmax;
+  const int na = block_top_t([&](int n) { return r[n]; }, ma, d.top_t, A, reinterpret_cast<VI*>(scratch));
+  const int nb = block_top_t([&](int n) { return r[ma + n]; }, mb, d.top_t, B, reinterpret_cast<VI*>(scratch));
+  resolve_lists<Tin>(d, A, na, B, nb, flags, scratch);
 }
 
 template <typename T, typename Tin>
@@ -1451,6 +1503,17 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
     if (bound < 0.5) flags |= TM_R_EXACT;
   }
 
+  if (d.top_t > 1) {
+    VI A[kTopTMax], B[kTopTMax];
+    A[0] = amax;
+    B[0] = bmax;
+    const int na = block_top_t([&](int n) {
+      return exact ? rint((double)buf[padi(n)].x) : (double)buf[padi(n)].x; }, ma, d.top_t, A, vs);
+    const int nb = block_top_t([&](int n) {
+      return exact ? rint((double)buf[padi(n)].y) : (double)buf[padi(n)].y; }, mb, d.top_t, B, vs);
+    resolve_lists<Tin>(d, A, na, B, nb, flags, scratch);
+    return;
+  }
   resolve_and_report<Tin>(d, amax, bmax, flags, scratch);
 }
 
@@ -1694,11 +1757,13 @@ __global__ void __launch_bounds__(kFinishThreads) k_gfft_icols(InstTable tab) {
     if (n < ma) {
       const double r = exact ? rint((double)v.x) : (double)v.x;
       if (dra) G(dra)[n] = r;
+      if (d.rtop) G(d.rtop)[n] = r;
       top2_add(ta, r, n);
     }
     if (n < mb) {
       const double r = exact ? rint((double)v.y) : (double)v.y;
       if (drb) G(drb)[n] = r;
+      if (d.rtop) G(d.rtop)[ma + n] = r;
       top2_add(tb, r, n);
     }
   }
@@ -1739,7 +1804,8 @@ __global__ void __launch_bounds__(kGfftThreads) k_gfft_final(InstTable tab) {
   } else if (a.v1 - a.v2 <= 1e-5 * a.mag || b.v1 - b.v2 <= 1e-5 * b.mag) {
     flags |= TM_R_NEAR_TIE;
   }
-  resolve_and_report<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch);
+  if (d.top_t > 1) resolve_top_t<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch);
+  else resolve_and_report<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch);
 }
 
 template <typename T, typename Tin>
@@ -2107,6 +2173,7 @@ __device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int
     const int k = 64 * (kCgRows * rt + 4 * g + jj) + 16 * nt + c;
     if (k < M) {
       if (dr) G(dr)[k] = (double)r;
+      if (d.rtop) G(d.rtop)[(f ? d.va.m : 0) + k] = (double)r;
       if (vi_better(VI{(double)r, k}, best)) best = VI{(double)r, k};
     }
   }
@@ -2229,7 +2296,8 @@ __device__ void cg_final(const Inst& d) {
   for (int s = threadIdx.x; s < nz; s += blockDim.x) G(d.yp)[s] = 0;
   if (threadIdx.x < 2) G(d.cmax)[threadIdx.x] = 0;
   __syncthreads();
-  resolve_and_report<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+  if (d.top_t > 1) resolve_top_t<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+  else resolve_and_report<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
 }
 
 __device__ __forceinline__ void cg_final_dispatch(const Inst& d) {

@@ -44,6 +44,9 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+static_assert(sizeof(tm_plan_desc) == 48, "tm_plan_desc layout is part of the ABI");
+static_assert(sizeof(tm_result) == 48, "tm_result layout is part of the ABI");
+
 int64_t gcd64(int64_t a, int64_t b) {
   while (b) { const int64_t t = a % b; a = b; b = t; }
   return a;
@@ -120,7 +123,7 @@ View make_band_view(int64_t n, int64_t m) {
 struct Core {
   int64_t n = 0;
   int32_t k = 0, m1 = 0, m2 = 0, ma = 0, mb = 0;
-  int32_t swapped = 0, dual = 0, mode = MODE_EXACT, p_log2 = 1, zpad = 0;
+  int32_t swapped = 0, dual = 0, mode = MODE_EXACT, p_log2 = 1, zpad = 0, top_t = 1;
   int32_t x_dtype = 0, t_dtype = 0, fold_store = TM_F32;
   int64_t inv = 0;
   View va{}, vb{};
@@ -135,7 +138,7 @@ struct Core {
                             // fold maxima); lives in the zeroed pool
   // correlation as an int8 MFMA GEMM (exact path, int8-valued template)
   int32_t cgemm = 0, c_nlcap = 0, c_lp = 0, c_ks = 0, c_rta = 0, c_rtb = 0, c_lt = 0;
-  size_t off_ylimb = 0, off_cpart = 0;
+  size_t off_ylimb = 0, off_cpart = 0, off_rtop = 0;
   size_t fold_lds = 0, finish_lds = 0;
   int fft_in_lds = 1;
 };
@@ -184,6 +187,9 @@ tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8) {
   c->t_dtype = d->t_dtype;
   c->fold_store = fs;
   c->zpad = (d->flags & TM_F_ZERO_PAD) ? 1 : 0;
+  if (d->top_t < 0 || d->top_t > kTopTMax) return fail(TM_ERR_INVALID, "top_t must be in 0..4");
+  if (d->reserved != 0) return fail(TM_ERR_INVALID, "reserved descriptor field must be 0");
+  c->top_t = d->top_t == 0 ? 1 : d->top_t;
   int64_t m1 = d->m1, m2 = d->m2;
   if (m1 == 0 && m2 == 0) {
     const int64_t mult = d->fold_mult == 0 ? 1 : d->fold_mult;
@@ -314,6 +320,11 @@ tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8) {
     c->c_lt = (int32_t)align_up(std::max<int64_t>(d->k + kCgPad + 16, 64 * (int64_t)c->c_ks + kCgPad + 32), 16);
     c->off_ylimb = off; off = align256(off + (size_t)2 * c->c_nlcap * c->c_lp);
     c->off_cpart = off; off = align256(off + (size_t)2 * rtm * 4 * 2 * sizeof(double));
+  }
+  if (c->top_t > 1 && (c->cgemm || c->gfft)) {
+    // routes without the whole correlation in LDS keep it for the runner-up scan
+    c->off_rtop = off;
+    off = align256(off + (size_t)(c->ma + c->mb) * sizeof(double));
   }
   c->off_res = off; off = align256(off + sizeof(tm_result));
   c->ws_bytes = off;
@@ -545,6 +556,7 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->dual = c.dual;
   in->swapped = c.swapped;
   in->zpad = c.zpad;
+  in->top_t = c.top_t;
   in->p_log2 = c.p_log2;
   in->va = c.va;
   in->vb = c.vb;
@@ -583,6 +595,7 @@ void place_workspace(const Core& c, char* base, char* acc, Inst* in) {
     in->gss = reinterpret_cast<double*>(base + c.off_gss);
     in->gpart = base + c.off_gpart;
   }
+  if (c.top_t > 1 && (c.cgemm || c.gfft)) in->rtop = reinterpret_cast<double*>(base + c.off_rtop);
   if (c.cgemm) {
     in->ylimb = reinterpret_cast<int8_t*>(base + c.off_ylimb);
     in->cpart = base + c.off_cpart;
@@ -997,7 +1010,7 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   }
   const Core& c = p->core;
   const bool gemm = c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.mode == MODE_EXACT && c.k <= (1 << 14) &&
-                    std::max(c.va.l, c.vb.l) <= (1 << 13) && !(p->desc.flags & TM_F_FFT) &&
+                    std::max(c.va.l, c.vb.l) <= (1 << 13) && !(p->desc.flags & TM_F_FFT) && c.top_t == 1 &&
                     env_int("TM_MANY_BATCH", 0) == 0;
   if (!gemm) {
     std::vector<tm_plan> plans((size_t)count, p);

@@ -34,7 +34,7 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("m1", ctypes.c_int32),
                 ("m2", ctypes.c_int32), ("fold_mult", ctypes.c_int32), ("x_dtype", ctypes.c_int32),
                 ("t_dtype", ctypes.c_int32), ("fold_store", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("top_t", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -64,7 +64,7 @@ class ServerStats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64)]
 
 
-assert ctypes.sizeof(Result) == 48 and ctypes.sizeof(PlanDesc) == 40
+assert ctypes.sizeof(Result) == 48 and ctypes.sizeof(PlanDesc) == 48
 
 RESULT_DTYPE = np.dtype([("shift", "<i8"), ("m1_tilde", "<i4"), ("m2_tilde", "<i4"),
                          ("n_candidates", "<i4"), ("flags", "<u4"), ("peak1", "<f8"),
@@ -149,10 +149,10 @@ def tm_dtype_of(arr) -> int:
     return _NP_TO_TM[np.dtype(arr.dtype)]
 
 
-def _desc(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32, flags=0):
+def _desc(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32, flags=0, top_t=1):
     return PlanDesc(n=int(n), k=int(k), m1=int(m1), m2=int(m2), fold_mult=int(fold_mult),
                     x_dtype=int(x_dtype), t_dtype=int(t_dtype), fold_store=int(fold_store),
-                    flags=int(flags))
+                    flags=int(flags), top_t=int(top_t), reserved=0)
 
 
 def _info_dict(info: PlanInfo) -> dict:
@@ -160,11 +160,11 @@ def _info_dict(info: PlanInfo) -> dict:
 
 
 def plan_params(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32,
-                flags=0) -> dict:
+                flags=0, top_t=1) -> dict:
     """Host-only plan parameters (tm_plan_params)."""
     info = PlanInfo()
     _check(lib().tm_plan_params(ctypes.byref(_desc(n, k, m1, m2, fold_mult, x_dtype, t_dtype,
-                                                   fold_store, flags)), ctypes.byref(info)))
+                                                   fold_store, flags, top_t)), ctypes.byref(info)))
     return _info_dict(info)
 
 
@@ -212,7 +212,7 @@ class Plan:
 
     def __init__(self, t, n: int, m1: int = 0, m2: int = 0, fold_mult: int = 1,
                  x_dtype: Optional[int] = None, fold_store: int = TM_F32, flags: int = 0,
-                 stream=None):
+                 stream=None, top_t: int = 1):
         if hasattr(t, "detach"):
             import torch
             tt = t.detach().cpu().contiguous()
@@ -222,7 +222,7 @@ class Plan:
         t_dtype = tm_dtype_of(t)
         if x_dtype is None:
             x_dtype = t_dtype
-        self.desc = _desc(n, t_host.shape[0], m1, m2, fold_mult, x_dtype, t_dtype, fold_store, flags)
+        self.desc = _desc(n, t_host.shape[0], m1, m2, fold_mult, x_dtype, t_dtype, fold_store, flags, top_t)
         self._t_host = np.ascontiguousarray(t_host)
         handle = ctypes.c_void_p()
         _check(lib().tm_plan_create(ctypes.byref(self.desc), self._t_host.ctypes.data, 0,

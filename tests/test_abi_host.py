@@ -71,6 +71,8 @@ def test_explicit_moduli_and_orientation():
     dict(n=100, k=10, flags=0x100),
     dict(n=100, k=10, flags=tm.TM_F_EXACT | tm.TM_F_REAL),
     dict(n=100, k=10, flags=0x10),
+    dict(n=100, k=10, top_t=5),
+    dict(n=100, k=10, top_t=-1),
 ])
 def test_invalid_plans_are_rejected(kw):
     with pytest.raises(tm.TMError) as e:

@@ -423,6 +423,49 @@ def test_nomatch_and_rescore_paths():
     assert O.resolve(xe, t1, a, b, m1, m2)[0] == c[1]
 
 
+# ---------------------------------------------------------------- top-T re-scoring
+
+@pytest.mark.parametrize("n,k", [(20, 3), (31, 5), (12, 12), (40, 1)])
+def test_top_t_covering_every_residue_is_full_search(n, k):
+    """T >= max(M1, M2): every shift is a candidate of some pair, so the
+    re-score picks the full-search maximum (lowest index on ties), computed
+    here by brute force over (Tx)."""
+    rng = _rng(n + 31 * k)
+    x = rng.integers(-3, 4, n).astype(np.int64)
+    for m in (0, n // 2, n - 1):
+        t = x[(m + np.arange(k)) % n].copy()
+        m1, m2 = O.choose_moduli(n, k)
+        res = O.ftm(x, t, m1, m2, top_t=max(m1, m2))
+        full = O.full_correlation(x, t)
+        assert res.candidates == list(range(n))
+        assert res.shift == int(np.argmax(full))
+
+
+def test_top_t_order_and_growth():
+    """Runners-up in (value desc, index asc) order; the candidate set grows
+    with T and the chosen score never drops; T = 1 keeps step 9's set."""
+    r = np.array([3, 7, 7, 1, 9, 7], dtype=np.int64)
+    assert O.top_indices(r, 4) == [4, 1, 2, 5]
+    rng = _rng(99)
+    n, k = 5000, 60
+    x = _pm1(n, rng)
+    t = (x[(1234 + np.arange(k)) % n] * np.where(rng.random(k) < 0.3, -1, 1)).astype(np.int8)
+    m1, m2 = O.choose_moduli(n, k)
+    base = O.ftm(x, t, m1, m2)
+    prev_c, prev_s = set(base.candidates), base.score
+    assert O.ftm(x, t, m1, m2, top_t=1).candidates == base.candidates
+    for tt in (2, 3, 4):
+        res = O.ftm(x, t, m1, m2, top_t=tt)
+        assert set(res.candidates) >= prev_c
+        if prev_s is not None:
+            assert res.score >= prev_s
+        assert (res.m1_tilde, res.m2_tilde) == (base.m1_tilde, base.m2_tilde)
+        full = O.full_correlation(x, t)
+        if res.candidates:
+            assert res.score == max(full[c] for c in res.candidates)
+        prev_c, prev_s = set(res.candidates), res.score
+
+
 # ---------------------------------------------------------------- Table 1
 
 @pytest.mark.slow
