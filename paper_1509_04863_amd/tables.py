@@ -12,7 +12,10 @@ Signals, shifts and noise are drawn on the device from seeded torch generators
 tm_match.  Each point reports the success rate with its binomial standard
 error, the paper's printed value, and (Table 1) the Theorem 5 success bound.
 
-  python -m paper_1509_04863_amd.tables --table 1 --trials 1000
+  python -m paper_1509_04863_amd.tables --table 1 --trials 1000 [--top-t 4]
+
+--top-t T re-scores the candidates of the T x T runner-up pairs (an option
+beyond the paper's step 9).
 """
 
 from __future__ import annotations
@@ -65,7 +68,7 @@ def thm5_success_bound(n: int, k: int, m1: int, m2: int) -> float:
     return out
 
 
-def table1(trials: int, log2ns=(23, 24, 25, 26, 27), progress=True):
+def table1(trials: int, log2ns=(23, 24, 25, 26, 27), progress=True, top_t=1):
     import torch
 
     from paper_1509_04863_amd import tm
@@ -80,13 +83,13 @@ def table1(trials: int, log2ns=(23, 24, 25, 26, 27), progress=True):
             x = _rademacher(n, g)
             m = int(torch.randint(0, n, (1,), generator=g, device="cuda").item())
             t = _window(x, m, k)
-            plan = tm.Plan(t, n=n, m1=m1, m2=m2)
+            plan = tm.Plan(t, n=n, m1=m1, m2=m2, top_t=top_t)
             r = tm.match(plan, x)
             hits += int(r.shift == m)
             del plan
         rate = hits / trials
         se = math.sqrt(max(rate * (1 - rate), 1e-12) / trials)
-        row = {"log2_n": p, "n": n, "k": k, "m1": m1, "m2": m2, "trials": trials, "success": rate,
+        row = {"log2_n": p, "n": n, "k": k, "m1": m1, "m2": m2, "top_t": top_t, "trials": trials, "success": rate,
                "stderr": se, "paper": PAPER_T1[p], "thm5_success_bound": thm5_success_bound(n, k, m1, m2),
                "seconds": time.perf_counter() - t0}
         rows.append(row)
@@ -95,7 +98,7 @@ def table1(trials: int, log2ns=(23, 24, 25, 26, 27), progress=True):
     return rows
 
 
-def table2(trials: int, snrs=(20, 10, 6, 1, -2, -6), log2n=26, log2k=16, progress=True):
+def table2(trials: int, snrs=(20, 10, 6, 1, -2, -6), log2n=26, log2k=16, progress=True, top_t=1):
     import torch
 
     from paper_1509_04863_amd import tm
@@ -112,12 +115,12 @@ def table2(trials: int, snrs=(20, 10, 6, 1, -2, -6), log2n=26, log2k=16, progres
             m = int(torch.randint(0, n, (1,), generator=g, device="cuda").item())
             t = _window(x, m, k).to(torch.float32)
             xe = x.to(torch.float32) + sigma * torch.randn(n, generator=g, device="cuda", dtype=torch.float32)
-            plan = tm.Plan(t, n=n, m1=m1, m2=m2)
+            plan = tm.Plan(t, n=n, m1=m1, m2=m2, top_t=top_t)
             r = tm.match(plan, xe)
             hits += int(r.shift == m)
             del plan, xe
         rate = hits / trials
-        row = {"snr_db": snr, "n": n, "k": k, "trials": trials, "success": rate,
+        row = {"snr_db": snr, "n": n, "k": k, "top_t": top_t, "trials": trials, "success": rate,
                "stderr": math.sqrt(max(rate * (1 - rate), 1e-12) / trials), "paper": PAPER_T2[snr],
                "seconds": time.perf_counter() - t0}
         rows.append(row)
@@ -131,14 +134,15 @@ def main():
     ap.add_argument("--table", type=int, choices=[1, 2], required=True)
     ap.add_argument("--trials", type=int, default=1000)
     ap.add_argument("--points", default="", help="comma list of log2 N (table 1) or SNR dB (table 2)")
+    ap.add_argument("--top-t", type=int, default=1, help="top-T re-scoring (1: the paper's step 9)")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the Section 5 tables run on the GPU"
     pts = [int(v) for v in args.points.split(",") if v]
     if args.table == 1:
-        table1(args.trials, tuple(pts) if pts else (23, 24, 25, 26, 27))
+        table1(args.trials, tuple(pts) if pts else (23, 24, 25, 26, 27), top_t=args.top_t)
     else:
-        table2(args.trials, tuple(pts) if pts else (20, 10, 6, 1, -2, -6))
+        table2(args.trials, tuple(pts) if pts else (20, 10, 6, 1, -2, -6), top_t=args.top_t)
 
 
 if __name__ == "__main__":
