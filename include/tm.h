@@ -104,7 +104,17 @@ typedef struct {
                          sets is re-scored by (Tx)_c (exact on the exact path, FP64
                          otherwise).  m1_tilde / m2_tilde and the peaks stay the
                          argmaxes of step 7; n_candidates counts the union. */
-  int32_t reserved;   /* 0 */
+  int32_t m3;         /* 0: two moduli (Algorithm 1).  Three pairwise co-prime moduli
+                         (Theorem 4 with three moduli, for K(K+1) <= N where two
+                         moduli near K cannot cover N): > 0 is an explicit third
+                         modulus (m1, m2 explicit too; each >= K, pairwise co-prime,
+                         M1*M2*M3 >= N); -1 chooses (m, m+1, m+2) with m the least
+                         odd number >= c*K whose product exceeds N.  The third fold is
+                         folded, correlated and maximised like the others and the
+                         candidate set is the intersection of the three sets; the
+                         result reports the first two folds' residues and peaks.
+                         Not combined with top_t > 1 or TM_F_ZERO_PAD, and not
+                         available to tm_match_intermediates. */
 } tm_plan_desc;
 
 typedef struct tm_plan_s* tm_plan;
@@ -140,7 +150,7 @@ typedef struct {
                             as an int8 MFMA matrix product (exact plans whose template
                             holds integers in [-128, 127], K <= 2^17, unless
                             TM_F_FFT); every correlation value is then exact */
-  int32_t reserved;
+  int32_t m3;            /* third modulus, or 0 for two */
   int64_t workspace_bytes; /* device workspace one match of this plan uses */
   int64_t x_bytes;       /* bytes of x read per match */
 } tm_plan_info;

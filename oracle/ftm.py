@@ -43,6 +43,12 @@ Readings taken where the paper is silent, ambiguous or inconsistent
       default): the T largest entries of each correlation (lowest index on
       ties) give T x T residue pairs; the union of their candidate sets is
       re-scored by (Tx)_c as in R9.  T = 1 is step 9 itself.
+  R11a Three pairwise co-prime moduli (Theorem 4 with alpha = 3), for the
+      regime K (K + 1) <= N where two moduli near K cannot cover N: each fold,
+      correlation and argmax as for two, the candidate set the intersection
+      of the three sets; the automatic choice is (m, m + 1, m + 2) with m the
+      least odd number >= c K whose product exceeds N (consecutive numbers
+      with m odd are pairwise co-prime).
   R11 Step 2 asks for M1 M2 > N with M1 = K, M2 = K + 1 (Section 4); when
       K (K + 1) <= N that choice is infeasible, and the automatic rule raises
       M1 to the least m with m (m + 1) > N.  fold_mult c in {1, 2} scales the
@@ -385,6 +391,53 @@ def ftm(x: np.ndarray, t: np.ndarray, m1: Optional[int] = None, m2: Optional[int
         shift, cands, score = resolve(x, t, i1, i2, m1, m2, variant)
     return OracleResult(shift=shift, m1_tilde=i1, m2_tilde=i2, candidates=cands, score=score,
                         peak1=r1[i1], peak2=r2[i2], m1=m1, m2=m2, y1=y1, y2=y2, r1=r1, r2=r2)
+
+
+def choose_moduli3(n: int, k: int, fold_mult: int = 1):
+    """(m, m + 1, m + 2): m the least odd number >= c K with m (m + 1) (m + 2)
+    > N (reading R11a)."""
+    m = max(fold_mult * k, 1)
+    if m % 2 == 0:
+        m += 1
+    while m * (m + 1) * (m + 2) <= n:
+        m += 2
+    return m, m + 1, m + 2
+
+
+def ftm_multi(x: np.ndarray, t: np.ndarray, moduli: Sequence[int]) -> dict:
+    """Algorithm 1 with alpha pairwise co-prime moduli (Theorem 4, reading
+    R11a): for each M, the fold of step 3, the correlation of steps 4-6 and
+    the argmax of step 7; the candidate set of step 8 is the intersection of
+    the alpha sets (mod N), several members re-scored by (Tx)_c (R9)."""
+    n, k = x.shape[0], t.shape[0]
+    for i, a in enumerate(moduli):
+        if a < k:
+            raise ValueError("every modulus must be >= K")
+        for b in moduli[i + 1:]:
+            if math.gcd(a, b) != 1:
+                raise ValueError("moduli must be pairwise co-prime")
+    if math.prod(moduli) < n:
+        raise ValueError("the product of the moduli must be >= N")
+    dt = work_dtype(x, t)
+    tildes, peaks, rs = [], [], []
+    common = None
+    for m in moduli:
+        y = fold(x, m, k, dt)
+        r = correlate(y, t, m)
+        i = argmax_lowest(r)
+        tildes.append(i)
+        peaks.append(r[i])
+        rs.append(r)
+        s = candidate_set(i, m, n)
+        common = s if common is None else common & s
+    cands = sorted(common)
+    best, best_score = NOMATCH, None
+    for c in cands:
+        sc = correlation_at(x, t, c)
+        if best_score is None or sc > best_score:
+            best, best_score = c, sc
+    return {"shift": int(best), "tildes": tildes, "peaks": peaks, "candidates": cands,
+            "score": best_score, "r": rs}
 
 
 def top2_gap(r: np.ndarray) -> float:

@@ -149,6 +149,17 @@ constexpr int kCgMaxK = 1 << 17;                    // int32 limb sums stay exac
 constexpr int kCgPrepThreads = 256;
 constexpr int kTopTMax = 4;                         // runners-up per fold for top-T re-scoring
 
+// One user instance of a batch that holds three-moduli plans: the indices of
+// its results in the expanded instance list (i2 < 0: a two-moduli plan whose
+// result is copied) and, for three moduli, the user's moduli with
+// m1^{-1} mod m2.  The first pair (m1, m2) is instance i1, the second pair
+// (m3, m1) instance i2.
+struct alignas(8) Combine3 {
+  int32_t i1, i2;
+  int32_t m1, m2, m3, pad;
+  int64_t inv12;
+};
+
 // Arguments of the shared-template kernels (one plan, `count` signals).
 struct ManyArgs {
   Inst base;              // the plan's instance record (x, out, workspace unset)
@@ -206,6 +217,10 @@ hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int coun
                              hipStream_t s);
 hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s);
 int cgemm_limbs_for(int64_t maxabs);                   // limbs that hold |y| <= maxabs
+// Theorem 4 with three moduli: per user instance, S1 cap S2 cap S3 from the two
+// pairs' argmaxes, re-scored by (Tx)_c (one workgroup each)
+hipError_t launch_combine3(const Inst* tab, const Combine3* cmb, const tm_result* res, tm_result* out, int count,
+                           hipStream_t s);
 hipError_t launch_gfft(const Inst& one, hipStream_t s);   // literal folds .. result, one instance
 
 }  // namespace tmi

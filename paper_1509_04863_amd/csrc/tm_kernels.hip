@@ -2337,6 +2337,123 @@ hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int cou
 }
 
 // --------------------------------------------------------------------------
+// three moduli (Theorem 4 with alpha = 3): combine the two pairs' residues
+// --------------------------------------------------------------------------
+//
+// c belongs to S(a, M) = {(a + i M) mod N : i < L} iff c = a mod M (the
+// regular members a + i M < N) or c is the wrapped member (a + (L-1) M) mod N
+// when a + (L-1) M >= N.  The regular classes of the three moduli meet at most
+// once below N (M1 M2 M3 >= N); candidates are the members of the (a1, a2)
+// class below N, found by Chinese remaindering and checked against S3 in
+// parallel, and the three wrapped members checked against all three sets.
+
+struct ResSet { int64_t a, m, w; bool wrap; };
+
+__device__ __forceinline__ ResSet res_set(int64_t a, int64_t m, int64_t n) {
+  const int64_t l = (n + m - 1) / m;
+  const int64_t last = a + (l - 1) * m;
+  return ResSet{a, m, last % n, last >= n};
+}
+
+__device__ __forceinline__ bool in_set(int64_t c, const ResSet& s) {
+  return (c % s.m == s.a) || (s.wrap && c == s.w);
+}
+
+template <typename Tin>
+__device__ void combine3(const Inst& d, const Combine3& cb, const tm_result& r1, const tm_result& r2,
+                         tm_result* out, void* scratch) {
+  constexpr int kMaxCand = 16;
+  __shared__ long long cand[kMaxCand];
+  __shared__ int ncand;
+  const int64_t N = d.n;
+  const ResSet s1 = res_set(r1.m1_tilde, cb.m1, N), s2 = res_set(r1.m2_tilde, cb.m2, N),
+               s3 = res_set(r2.m1_tilde, cb.m3, N);
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
+  auto push = [&](long long v) {
+    const int slot = atomicAdd(&ncand, 1);
+    if (slot < kMaxCand) cand[slot] = v;
+  };
+  if (s1.a < N && s2.a < N) {
+    const int64_t m12 = (int64_t)cb.m1 * cb.m2;
+    const int64_t t = ((((s2.a - s1.a) % cb.m2) + cb.m2) % cb.m2) * cb.inv12 % cb.m2;
+    const int64_t v0 = s1.a + (int64_t)cb.m1 * t;
+    for (int64_t v = v0 + (int64_t)threadIdx.x * m12; v < N; v += (int64_t)blockDim.x * m12)
+      if (in_set(v, s3)) push(v);
+  }
+  if (threadIdx.x == 0) {
+    const ResSet* sets[3] = {&s1, &s2, &s3};
+    for (int i = 0; i < 3; ++i)
+      if (sets[i]->wrap && in_set(sets[i]->w, s1) && in_set(sets[i]->w, s2) && in_set(sets[i]->w, s3))
+        push(sets[i]->w);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {   // ascending, no repeats
+    int w = min(ncand, kMaxCand);
+    for (int i = 1; i < w; ++i)
+      for (int j = i; j > 0 && cand[j - 1] > cand[j]; --j) {
+        const long long tmp = cand[j];
+        cand[j] = cand[j - 1];
+        cand[j - 1] = tmp;
+      }
+    int u = 0;
+    for (int i = 0; i < w; ++i)
+      if (u == 0 || cand[u - 1] != cand[i]) cand[u++] = cand[i];
+    ncand = u;
+  }
+  __syncthreads();
+  const int nc = ncand;
+  int64_t best = -1;
+  double best_score = 0.0;
+  for (int i = 0; i < nc; ++i) {
+    const double sc = score_any_t<Tin>(d, cand[i], scratch);
+    if (i == 0 || sc > best_score) { best = cand[i]; best_score = sc; }
+  }
+  if (threadIdx.x == 0) {
+    uint32_t flags = (r1.flags & r2.flags & TM_R_EXACT) | ((r1.flags | r2.flags) & TM_R_NEAR_TIE);
+    if (nc == 0) flags |= TM_R_NOMATCH;
+    if (nc > 1) flags |= TM_R_RESCORED;
+    tm_result r;
+    r.shift = best;
+    r.m1_tilde = r1.m1_tilde;
+    r.m2_tilde = r1.m2_tilde;
+    r.n_candidates = nc;
+    r.flags = flags;
+    r.peak1 = r1.peak1;
+    r.peak2 = r1.peak2;
+    r.score = nc ? best_score : 0.0;
+    *out = r;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_combine3(const Inst* tab, const Combine3* cmb, const tm_result* res,
+                                                  tm_result* out) {
+  __shared__ __align__(16) unsigned char scratch[16 * 16];
+  const Combine3 cb = cmb[blockIdx.x];
+  const tm_result r1 = res[cb.i1];
+  if (cb.i2 < 0) {
+    if (threadIdx.x == 0) out[blockIdx.x] = r1;
+    return;
+  }
+  const tm_result r2 = res[cb.i2];
+  const Inst& d = tab[cb.i1];
+  tm_result* o = out + blockIdx.x;
+  switch (d.x_dtype) {
+    case TM_I8: combine3<int8_t>(d, cb, r1, r2, o, scratch); break;
+    case TM_F32: combine3<float>(d, cb, r1, r2, o, scratch); break;
+    case TM_BF16: combine3<bf16_t>(d, cb, r1, r2, o, scratch); break;
+    default: combine3<f16_t>(d, cb, r1, r2, o, scratch); break;
+  }
+}
+
+hipError_t launch_combine3(const Inst* tab, const Combine3* cmb, const tm_result* res, tm_result* out, int count,
+                           hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine3, dim3(count), dim3(256), 0, s, tab, cmb, res, out);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // plan-time kernels
 // --------------------------------------------------------------------------
 

@@ -124,6 +124,7 @@ struct Core {
   int64_t n = 0;
   int32_t k = 0, m1 = 0, m2 = 0, ma = 0, mb = 0;
   int32_t swapped = 0, dual = 0, mode = MODE_EXACT, p_log2 = 1, zpad = 0, top_t = 1;
+  int32_t three = 0, m3 = 0;   // three moduli: (m1, m2) here, (m3, m1) in the plan's second core
   int32_t x_dtype = 0, t_dtype = 0, fold_store = TM_F32;
   int64_t inv = 0;
   View va{}, vb{};
@@ -165,7 +166,7 @@ CgLaunch cgemm_launch(int64_t total_entries, int64_t max_entries, int64_t count)
 
 // t_i8: every template value is an integer in [-128, 127] (known for int8
 // templates without looking at them; checked on the values at plan creation)
-tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8) {
+tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8, bool pair_of_three = false) {
   if (!d) return fail(TM_ERR_INVALID, "null plan descriptor");
   if (d->n < 1) return fail(TM_ERR_INVALID, "N must be >= 1");
   if (d->k < 1 || (int64_t)d->k > d->n) return fail(TM_ERR_INVALID, "need 1 <= K <= N");
@@ -188,10 +189,37 @@ tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8) {
   c->fold_store = fs;
   c->zpad = (d->flags & TM_F_ZERO_PAD) ? 1 : 0;
   if (d->top_t < 0 || d->top_t > kTopTMax) return fail(TM_ERR_INVALID, "top_t must be in 0..4");
-  if (d->reserved != 0) return fail(TM_ERR_INVALID, "reserved descriptor field must be 0");
   c->top_t = d->top_t == 0 ? 1 : d->top_t;
   int64_t m1 = d->m1, m2 = d->m2;
-  if (m1 == 0 && m2 == 0) {
+  // three pairwise co-prime moduli (Theorem 4): this core folds (M1, M2) and
+  // the plan's second core (M3, M1); neither pair alone needs to cover N
+  const bool three = d->m3 != 0 && !pair_of_three;
+  if (three) {
+    if (c->top_t > 1) return fail(TM_ERR_INVALID, "three moduli are not combined with top_t > 1");
+    if (c->zpad) return fail(TM_ERR_INVALID, "three moduli are not combined with TM_F_ZERO_PAD");
+    int64_t m3 = d->m3;
+    if (m3 == -1 && m1 == 0 && m2 == 0) {
+      const int64_t mult = d->fold_mult == 0 ? 1 : d->fold_mult;
+      int64_t m = std::max<int64_t>(mult * d->k, 1);
+      if (m % 2 == 0) ++m;
+      while ((double)m * (double)(m + 1) * (double)(m + 2) <= (double)d->n) m += 2;
+      m1 = m;
+      m2 = m + 1;
+      m3 = m + 2;
+    } else if (m3 > 0 && m1 > 0 && m2 > 0) {
+      if (m1 < d->k || m2 < d->k || m3 < d->k) return fail(TM_ERR_INVALID, "need M1, M2, M3 >= K");
+      if (gcd64(m1, m2) != 1 || gcd64(m1, m3) != 1 || gcd64(m2, m3) != 1)
+        return fail(TM_ERR_INVALID, "M1, M2 and M3 must be pairwise co-prime");
+      if ((double)m1 * (double)m2 * (double)m3 < (double)d->n) return fail(TM_ERR_INVALID, "need M1 M2 M3 >= N");
+    } else {
+      return fail(TM_ERR_INVALID, "m3 must be -1 (automatic, with m1 = m2 = 0) or > 0 (with explicit m1, m2)");
+    }
+    if (m3 >= (int64_t(1) << 30)) return fail(TM_ERR_INVALID, "fold lengths above 2^30 are not supported");
+    c->three = 1;
+    c->m3 = (int32_t)m3;
+  } else if (d->m3 != 0 && !pair_of_three) {
+    return fail(TM_ERR_INVALID, "bad m3");
+  } else if (m1 == 0 && m2 == 0) {
     const int64_t mult = d->fold_mult == 0 ? 1 : d->fold_mult;
     m1 = std::max<int64_t>(mult * d->k, least_m0(d->n));
     m2 = m1 + 1;
@@ -199,7 +227,7 @@ tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8) {
     if (m1 < 1 || m2 < 1) return fail(TM_ERR_INVALID, "explicit M1 and M2 must both be >= 1");
     if (m1 < d->k || m2 < d->k) return fail(TM_ERR_INVALID, "need M1 >= K and M2 >= K");
     if (gcd64(m1, m2) != 1) return fail(TM_ERR_INVALID, "M1 and M2 must be co-prime");
-    if (m1 * m2 < d->n) return fail(TM_ERR_INVALID, "need M1 * M2 >= N");
+    if (m1 * m2 < d->n && !pair_of_three) return fail(TM_ERR_INVALID, "need M1 * M2 >= N");
   }
   if (m1 >= (int64_t(1) << 30) || m2 >= (int64_t(1) << 30))
     return fail(TM_ERR_INVALID, "fold lengths above 2^30 are not supported");
@@ -344,6 +372,7 @@ void fill_info(const Core& c, tm_plan_info* info) {
   info->fft_in_lds = c.fft_in_lds;
   info->fft_global = c.gfft;
   info->corr_gemm = c.cgemm;
+  info->m3 = c.m3;
   info->fold_tiles = c.ntiles;
   info->fold_segments = c.nseg;
   info->fold_bands = c.nband;
@@ -530,6 +559,7 @@ struct tm_plan_s {
   void* spec = nullptr;
   int8_t* tsh = nullptr;     // GEMM path: 16 shifted copies of the zero-padded template
   double tnorm1 = 0.0;
+  tm_plan_s* pair2 = nullptr;   // three moduli: the plan of the pair (M3, M1) (owned)
 };
 
 namespace {
@@ -646,6 +676,16 @@ double host_value(const void* t, int dt, int64_t i) {
   }
 }
 
+// the descriptor of a three-moduli plan's second pair (M3, M1)
+tm_plan_desc pair2_desc(const tm_plan_desc& d, const Core& c) {
+  tm_plan_desc d2 = d;
+  d2.m1 = c.m3;
+  d2.m2 = c.m1;
+  d2.m3 = 0;
+  d2.top_t = 1;
+  return d2;
+}
+
 }  // namespace
 
 extern "C" {
@@ -668,19 +708,48 @@ const char* tm_last_error(void) { return g_err.c_str(); }
 tm_status tm_plan_params(const tm_plan_desc* desc, tm_plan_info* info) {
   if (!info) return fail(TM_ERR_INVALID, "null info");
   Core c;
-  const tm_status s = compute_core(desc, &c, desc && desc->t_dtype == TM_I8);
+  const bool t_i8 = desc && desc->t_dtype == TM_I8;
+  tm_status s = compute_core(desc, &c, t_i8);
   if (s != TM_OK) return s;
   fill_info(c, info);
+  if (c.three) {
+    Core c2;
+    const tm_plan_desc d2 = pair2_desc(*desc, c);
+    s = compute_core(&d2, &c2, t_i8, true);
+    if (s != TM_OK) return s;
+    info->workspace_bytes += (int64_t)(c2.ws_bytes + c2.acc_bytes);
+  }
   return TM_OK;
 }
 
+static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t_is_device, void* stream,
+                                  tm_plan* out, bool pair_of_three);
+
 tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_device, void* stream,
                          tm_plan* out) {
+  tm_status st = plan_create_impl(desc, t, t_is_device, stream, out, false);
+  if (st != TM_OK || !(*out)->core.three) return st;
+  // three moduli: the second pair (M3, M1) as a plan of its own
+  const tm_plan_desc d2 = pair2_desc(*desc, (*out)->core);
+  tm_plan p2 = nullptr;
+  st = plan_create_impl(&d2, t, t_is_device, stream, &p2, true);
+  if (st != TM_OK) {
+    const std::string msg = g_err;
+    (void)tm_plan_destroy(*out);
+    *out = nullptr;
+    return fail(st, msg);
+  }
+  (*out)->pair2 = p2;
+  return TM_OK;
+}
+
+static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t_is_device, void* stream,
+                                  tm_plan* out, bool pair_of_three) {
   if (!out) return fail(TM_ERR_INVALID, "null plan output");
   *out = nullptr;
   if (!t) return fail(TM_ERR_INVALID, "null template pointer");
   Core c;
-  tm_status st = compute_core(desc, &c, false);
+  tm_status st = compute_core(desc, &c, false, pair_of_three);
   if (st != TM_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
@@ -705,7 +774,7 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
     t_i8 = t_i8 && v == std::nearbyint(v) && v >= -128.0 && v <= 127.0;
     norm1 += std::fabs(v);
   }
-  st = compute_core(desc, &c, t_i8);
+  st = compute_core(desc, &c, t_i8, pair_of_three);
   if (st != TM_OK) return st;
   if (!c.cgemm && !c.fft_in_lds && !c.gfft)
     return fail(TM_ERR_UNSUPPORTED, "FFT length 2^" + std::to_string(c.p_log2) + " is above 2^" +
@@ -775,6 +844,11 @@ tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_devic
 
 tm_status tm_plan_destroy(tm_plan p) {
   if (!p) return TM_OK;
+  if (p->pair2) {
+    const tm_status st = tm_plan_destroy(p->pair2);
+    p->pair2 = nullptr;
+    if (st != TM_OK) return st;
+  }
   TM_HIP(hipDeviceSynchronize());
   if (p->t_dev) TM_HIP(hipFree(p->t_dev));
   if (p->spec) TM_HIP(hipFree(p->spec));
@@ -786,13 +860,21 @@ tm_status tm_plan_destroy(tm_plan p) {
 tm_status tm_plan_get_info(tm_plan p, tm_plan_info* info) {
   if (!p || !info) return fail(TM_ERR_INVALID, "null argument");
   fill_info(p->core, info);
+  if (p->pair2) info->workspace_bytes += (int64_t)(p->pair2->core.ws_bytes + p->pair2->core.acc_bytes);
   return TM_OK;
 }
+
+tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
+                         void* stream);
 
 static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1, double* y2,
                            double* r1, double* r2, void* stream) {
   tm_status st = check_plan_for_match(p);
   if (st != TM_OK) return st;
+  if (p->core.three) {
+    if (y1 || y2 || r1 || r2) return fail(TM_ERR_UNSUPPORTED, "no intermediates for three-moduli plans");
+    return tm_match_batch(1, &p, &x, out, stream);
+  }
   st = check_x(p, x);
   if (st != TM_OK) return st;
   if (!out) return fail(TM_ERR_INVALID, "null result pointer");
@@ -854,19 +936,16 @@ tm_status tm_match_intermediates(tm_plan p, const void* x, tm_result* out, doubl
   return match_one(p, x, out, y1, y2, r1, r2, stream);
 }
 
-tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
-                         void* stream) {
-  if (count < 0) return fail(TM_ERR_INVALID, "negative count");
-  if (count == 0) return TM_OK;
-  if (!plans || !xs || !out) return fail(TM_ERR_INVALID, "null argument");
-  for (int32_t i = 0; i < count; ++i) {
-    tm_status st = check_plan_for_match(plans[i]);
-    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
-    st = check_x(plans[i], xs[i]);
-    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
-  }
+// One launch sequence for `count` instances.  Without `cmb` the results go
+// to out[0..count); with it the instances are the expanded list of a batch
+// with three-moduli plans: their results stay in device scratch and one
+// combine kernel writes out[0..cmb->size()).
+static tm_status run_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
+                           void* stream, const std::vector<Combine3>* cmb) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dev_out = is_device_pointer(out);
+  const bool scratch_res = !dev_out || cmb;           // instance results in the pool
+  const int32_t n_user = cmb ? (int32_t)cmb->size() : count;
 
   // layout: [instance workspaces][results if host out][table][lists]
   std::vector<size_t> ws_off(count), acc_off(count);
@@ -914,11 +993,14 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     return ca.mode != cb.mode ? ca.mode < cb.mode : ca.p_log2 < cb.p_log2;
   });
   const size_t off_res = align256(ws);
-  const size_t off_tab = align256(off_res + (dev_out ? 0 : sizeof(tm_result) * (size_t)count));
+  // combined user results staged on the device when out is host memory
+  const size_t off_ures = align256(off_res + (scratch_res ? sizeof(tm_result) * (size_t)count : 0));
+  const size_t off_tab = align256(off_ures + (cmb && !dev_out ? sizeof(tm_result) * (size_t)n_user : 0));
   const size_t tab_bytes = sizeof(Inst) * (size_t)count;
   const size_t off_lists = off_tab + tab_bytes;   // sizeof(Inst) keeps the list 16-byte aligned
-  const size_t list_bytes = sizeof(int32_t) * (size_t)count;
-  const size_t total = off_lists + list_bytes;
+  const size_t list_bytes = align_up(sizeof(int32_t) * (size_t)count, 16);
+  const size_t cmb_bytes = cmb ? sizeof(Combine3) * cmb->size() : 0;
+  const size_t total = off_lists + list_bytes + cmb_bytes;
 
   std::lock_guard<std::mutex> lock(g_mu);
   StreamPool& pool = g_pools[{plans[0]->device, s}];
@@ -927,11 +1009,12 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   st = ensure_acc(pool, accb, s);
   if (st != TM_OK) return st;
   int slot = 0;
-  st = ensure_host(pool, tab_bytes + list_bytes, &slot);
+  st = ensure_host(pool, tab_bytes + list_bytes + cmb_bytes, &slot);
   if (st != TM_OK) return st;
   char* base = static_cast<char*>(pool.dev);
   Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
   int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + tab_bytes);
+  if (cmb) std::memcpy(static_cast<char*>(pool.host[slot]) + tab_bytes + list_bytes, cmb->data(), cmb_bytes);
   int32_t tile_base = 0, red_base = 0, seg_base = 0, band_base = 0;
   for (int32_t i = 0; i < count; ++i) {
     const tm_plan_s* p = plans[i];
@@ -948,10 +1031,11 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     seg_base += nseg[i];
     band_base += p->core.nband;
     red_base += p->core.nred;
-    in.out = dev_out ? out + i : reinterpret_cast<tm_result*>(base + off_res) + i;
+    in.out = scratch_res ? reinterpret_cast<tm_result*>(base + off_res) + i : out + i;
     host_list[i] = order[i];
   }
-  TM_HIP(hipMemcpyAsync(base + off_tab, pool.host[slot], tab_bytes + list_bytes, hipMemcpyHostToDevice, s));
+  TM_HIP(hipMemcpyAsync(base + off_tab, pool.host[slot], tab_bytes + list_bytes + cmb_bytes, hipMemcpyHostToDevice,
+                        s));
   TM_HIP(hipEventRecord(pool.staged[slot], s));
   pool.staged_pending[slot] = true;
 
@@ -987,11 +1071,57 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
     g0 = g1;
   }
   pool.acc_dirty = false;
+  tm_result* user_dev = reinterpret_cast<tm_result*>(base + off_res);
+  if (cmb) {
+    user_dev = dev_out ? out : reinterpret_cast<tm_result*>(base + off_ures);
+    TM_HIP(launch_combine3(reinterpret_cast<const Inst*>(base + off_tab),
+                           reinterpret_cast<const Combine3*>(base + off_lists + list_bytes),
+                           reinterpret_cast<const tm_result*>(base + off_res), user_dev, n_user, s));
+  }
   if (!dev_out) {
-    TM_HIP(hipMemcpyAsync(out, base + off_res, sizeof(tm_result) * (size_t)count, hipMemcpyDeviceToHost, s));
+    TM_HIP(hipMemcpyAsync(out, user_dev, sizeof(tm_result) * (size_t)n_user, hipMemcpyDeviceToHost, s));
     TM_HIP(hipStreamSynchronize(s));
   }
   return TM_OK;
+}
+
+tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
+                         void* stream) {
+  if (count < 0) return fail(TM_ERR_INVALID, "negative count");
+  if (count == 0) return TM_OK;
+  if (!plans || !xs || !out) return fail(TM_ERR_INVALID, "null argument");
+  bool any3 = false;
+  for (int32_t i = 0; i < count; ++i) {
+    tm_status st = check_plan_for_match(plans[i]);
+    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+    st = check_x(plans[i], xs[i]);
+    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+    any3 = any3 || plans[i]->core.three;
+  }
+  if (!any3) return run_batch(count, plans, xs, out, stream, nullptr);
+  // three moduli: each such plan runs as its two pairs, then the combine
+  std::vector<tm_plan> ep;
+  std::vector<const void*> ex;
+  std::vector<Combine3> cmb((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    Combine3& cb = cmb[(size_t)i];
+    cb.i1 = (int32_t)ep.size();
+    cb.i2 = -1;
+    ep.push_back(plans[i]);
+    ex.push_back(xs[i]);
+    const Core& c = plans[i]->core;
+    if (c.three) {
+      cb.i2 = (int32_t)ep.size();
+      ep.push_back(plans[i]->pair2);
+      ex.push_back(xs[i]);
+      cb.m1 = c.m1;
+      cb.m2 = c.m2;
+      cb.m3 = c.m3;
+      cb.inv12 = mod_inverse(c.m1, c.m2);
+    }
+  }
+  if (ep.size() > 0x7fffffff) return fail(TM_ERR_UNSUPPORTED, "batch too large");
+  return run_batch((int32_t)ep.size(), ep.data(), ex.data(), out, stream, &cmb);
 }
 
 // One template, many signals of the plan's N: the signals' folds form the
@@ -1011,6 +1141,7 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   const Core& c = p->core;
   const bool gemm = c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.mode == MODE_EXACT && c.k <= (1 << 14) &&
                     std::max(c.va.l, c.vb.l) <= (1 << 13) && !(p->desc.flags & TM_F_FFT) && c.top_t == 1 &&
+                    !c.three &&
                     env_int("TM_MANY_BATCH", 0) == 0;
   if (!gemm) {
     std::vector<tm_plan> plans((size_t)count, p);

@@ -34,7 +34,7 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("m1", ctypes.c_int32),
                 ("m2", ctypes.c_int32), ("fold_mult", ctypes.c_int32), ("x_dtype", ctypes.c_int32),
                 ("t_dtype", ctypes.c_int32), ("fold_store", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("top_t", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("top_t", ctypes.c_int32), ("m3", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -43,7 +43,7 @@ class PlanInfo(ctypes.Structure):
                 ("dual", ctypes.c_int32), ("fft_in_lds", ctypes.c_int32),
                 ("fold_tiles", ctypes.c_int32), ("fold_segments", ctypes.c_int32),
                 ("fold_bands", ctypes.c_int32), ("fft_global", ctypes.c_int32),
-                ("corr_gemm", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("corr_gemm", ctypes.c_int32), ("m3", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64), ("x_bytes", ctypes.c_int64)]
 
 
@@ -149,10 +149,11 @@ def tm_dtype_of(arr) -> int:
     return _NP_TO_TM[np.dtype(arr.dtype)]
 
 
-def _desc(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32, flags=0, top_t=1):
+def _desc(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32, flags=0, top_t=1,
+          m3=0):
     return PlanDesc(n=int(n), k=int(k), m1=int(m1), m2=int(m2), fold_mult=int(fold_mult),
                     x_dtype=int(x_dtype), t_dtype=int(t_dtype), fold_store=int(fold_store),
-                    flags=int(flags), top_t=int(top_t), reserved=0)
+                    flags=int(flags), top_t=int(top_t), m3=int(m3))
 
 
 def _info_dict(info: PlanInfo) -> dict:
@@ -160,11 +161,11 @@ def _info_dict(info: PlanInfo) -> dict:
 
 
 def plan_params(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fold_store=TM_F32,
-                flags=0, top_t=1) -> dict:
+                flags=0, top_t=1, m3=0) -> dict:
     """Host-only plan parameters (tm_plan_params)."""
     info = PlanInfo()
     _check(lib().tm_plan_params(ctypes.byref(_desc(n, k, m1, m2, fold_mult, x_dtype, t_dtype,
-                                                   fold_store, flags, top_t)), ctypes.byref(info)))
+                                                   fold_store, flags, top_t, m3)), ctypes.byref(info)))
     return _info_dict(info)
 
 
@@ -212,7 +213,7 @@ class Plan:
 
     def __init__(self, t, n: int, m1: int = 0, m2: int = 0, fold_mult: int = 1,
                  x_dtype: Optional[int] = None, fold_store: int = TM_F32, flags: int = 0,
-                 stream=None, top_t: int = 1):
+                 stream=None, top_t: int = 1, m3: int = 0):
         if hasattr(t, "detach"):
             import torch
             tt = t.detach().cpu().contiguous()
@@ -222,7 +223,7 @@ class Plan:
         t_dtype = tm_dtype_of(t)
         if x_dtype is None:
             x_dtype = t_dtype
-        self.desc = _desc(n, t_host.shape[0], m1, m2, fold_mult, x_dtype, t_dtype, fold_store, flags, top_t)
+        self.desc = _desc(n, t_host.shape[0], m1, m2, fold_mult, x_dtype, t_dtype, fold_store, flags, top_t, m3)
         self._t_host = np.ascontiguousarray(t_host)
         handle = ctypes.c_void_p()
         _check(lib().tm_plan_create(ctypes.byref(self.desc), self._t_host.ctypes.data, 0,
@@ -248,6 +249,11 @@ class Plan:
     @property
     def m2(self) -> int:
         return int(self.info["m2"])
+
+    @property
+    def m3(self) -> int:
+        """Third modulus of a three-moduli plan, 0 otherwise."""
+        return int(self.info["m3"])
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

@@ -73,12 +73,31 @@ def test_explicit_moduli_and_orientation():
     dict(n=100, k=10, flags=0x10),
     dict(n=100, k=10, top_t=5),
     dict(n=100, k=10, top_t=-1),
+    dict(n=100, k=10, m3=-2),                      # bad third modulus
+    dict(n=100, k=3, m1=3, m2=5, m3=9),            # gcd(3, 9) = 3
+    dict(n=1000, k=3, m1=3, m2=4, m3=5),           # product 60 < N
+    dict(n=100, k=10, m3=-1, top_t=2),             # three moduli with top-T
+    dict(n=100, k=10, m3=-1, flags=tm.TM_F_ZERO_PAD),
+    dict(n=100, k=3, m3=-1, m1=3),                 # automatic with an explicit modulus
 ])
 def test_invalid_plans_are_rejected(kw):
     with pytest.raises(tm.TMError) as e:
         tm.plan_params(**kw)
     assert e.value.status == tm.TM_ERR_INVALID
     assert tm.lib().tm_last_error()
+
+
+def test_three_moduli_params():
+    # automatic: (m, m + 1, m + 2), m the least odd >= K with a product above N
+    info = tm.plan_params(1 << 20, 300, m3=-1)
+    assert (info["m1"], info["m2"], info["m3"]) == (301, 302, 303)
+    info = tm.plan_params(1 << 26, 100, m3=-1)
+    m = info["m1"]
+    assert m % 2 == 1 and m * (m + 1) * (m + 2) > 1 << 26 >= (m - 2) * (m - 1) * m
+    two = tm.plan_params(1 << 20, 300)
+    assert two["m3"] == 0 and two["m1"] == 1024          # two moduli must reach m0(N)
+    explicit = tm.plan_params(1 << 20, 200, m1=211, m2=223, m3=227)
+    assert (explicit["m1"], explicit["m2"], explicit["m3"]) == (211, 223, 227)
 
 
 def test_modes():

@@ -466,6 +466,60 @@ def test_top_t_order_and_growth():
         prev_c, prev_s = set(res.candidates), res.score
 
 
+# ---------------------------------------------------------------- three moduli
+
+def test_choose_moduli3_rule():
+    for n, k in [(1 << 20, 300), (1 << 20, 512), (1000, 3), (30, 1), (1 << 26, 100)]:
+        a, b, c = O.choose_moduli3(n, k)
+        assert a % 2 == 1 and a >= k and (b, c) == (a + 1, a + 2)
+        assert a * b * c > n
+        assert math.gcd(a, b) == math.gcd(a, c) == math.gcd(b, c) == 1
+        if a - 2 >= k:
+            assert (a - 2) * (a - 1) * a <= n
+
+
+@pytest.mark.parametrize("n,k", [(30, 3), (64, 4), (100, 2), (27, 3)])
+def test_three_moduli_exhaustive_tiny(n, k):
+    """Every planted shift: the candidate set is the brute-force intersection
+    of the three residue supports, the shift is its best (Tx)_c, and two of the
+    moduli alone would not determine the shift (M1 M2 < N for these sizes in
+    most cases) while the three do (Theorem 4)."""
+    rng = _rng(n * 3 + k)
+    x = _pm1(n, rng)
+    mods = O.choose_moduli3(n, k)
+    full_cache = None
+    for m in range(n):
+        t = x[(m + np.arange(k)) % n].copy()
+        res = O.ftm_multi(x, t, mods)
+        sets = [O.candidate_set(a, M, n) for a, M in zip(res["tildes"], mods)]
+        brute = [c for c in range(n) if all(c in s for s in sets)]
+        assert res["candidates"] == brute
+        full = O.full_correlation(x, t)
+        if brute:
+            assert res["score"] == max(full[c] for c in brute)
+        # regular members of the three classes meet at most once below N
+        reg = [c for c in range(n) if all(c % M == a for a, M in zip(res["tildes"], mods))]
+        assert len(reg) <= 1
+        for M, a in zip(mods, res["tildes"]):
+            r = np.array([sum(full[(kk + i * M) % n] for i in range(-(-n // M))) for kk in range(M)])
+            assert a == int(np.argmax(r))
+
+
+def test_three_moduli_two_of_them_equal_pairs():
+    """With the third modulus covering N alone (M3 >= N, one-row fold) the
+    three-way set is the pair's set intersected with {m~3}, the full-search
+    argmax when the pair is right."""
+    rng = _rng(5)
+    n, k = 200, 9
+    x = rng.integers(-5, 6, n).astype(np.int64)
+    m = 77
+    t = x[(m + np.arange(k)) % n].copy()
+    res = O.ftm_multi(x, t, (11, 13, 211))
+    full = O.full_correlation(x, t)
+    assert res["tildes"][2] == int(np.argmax(full))
+    assert res["candidates"] in ([], [res["tildes"][2]])
+
+
 # ---------------------------------------------------------------- Table 1
 
 @pytest.mark.slow
