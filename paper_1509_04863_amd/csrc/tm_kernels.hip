@@ -1005,7 +1005,7 @@ __device__ __forceinline__ void fft_pass_of(int i, int p, int& s0, int& kb) {
 // c[n] = sum_j t_j z[(n + j) mod P]: forward transform, product with the
 // spectrum, inverse transform, all in LDS.
 template <typename T>
-__device__ void fft_correlate(cplx<T>* buf, int p, const cplx<T>* tw, const cplx<T>* spec) {
+__device__ __forceinline__ void fft_correlate(cplx<T>* buf, int p, const cplx<T>* tw, const cplx<T>* spec) {
   const int np = fft_npasses<T>(p);
   int s0, kb;
   for (int i = 0; i + 1 < np; ++i) {
@@ -1034,7 +1034,7 @@ __device__ __forceinline__ bool vi_better(const VI& a, const VI& b) {
 }
 
 // wave reduction with xor shuffles, then one value per wave through LDS
-__device__ VI block_argmax(VI mine, VI* scratch) {
+__device__ __forceinline__ VI block_argmax(VI mine, VI* scratch) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) {
     const VI o{__shfl_xor(mine.v, m), __shfl_xor(mine.i, m)};
@@ -1053,7 +1053,7 @@ __device__ VI block_argmax(VI mine, VI* scratch) {
 // fixed pairing (xor butterflies inside a wave, waves in index order): the
 // same inputs always give the same sum
 template <typename S>
-__device__ S block_sum(S mine, S* scratch) {
+__device__ __forceinline__ S block_sum(S mine, S* scratch) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) mine = mine + __shfl_xor(mine, m);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1206,7 +1206,7 @@ __device__ __forceinline__ void finred_dpp(FinRed& r) {
 
 // wave reduction by DPP (the full result lands in lane 63), then the waves'
 // results in wave order through LDS
-__device__ FinRed block_finred(FinRed mine, FinRed* scratch) {
+__device__ __forceinline__ FinRed block_finred(FinRed mine, FinRed* scratch) {
   finred_dpp<0xB1, 0xF>(mine);    // quad_perm [1,0,3,2]
   finred_dpp<0x4E, 0xF>(mine);    // quad_perm [2,3,0,1]
   finred_dpp<0x141, 0xF>(mine);   // row_half_mirror
@@ -1228,7 +1228,7 @@ __device__ FinRed block_finred(FinRed mine, FinRed* scratch) {
 // runners-up for top-T re-scoring), the union re-scored by (Tx)_c, and the
 // result record.
 template <typename Tin>
-__device__ void resolve_lists(const Inst& d, const VI* A, int na, const VI* B, int nb, uint32_t flags,
+__device__ __forceinline__ void resolve_lists(const Inst& d, const VI* A, int na, const VI* B, int nb, uint32_t flags,
                               void* scratch) {
   const int tid = threadIdx.x;
   const int ma = d.va.m, mb = d.vb.m;
@@ -1291,7 +1291,7 @@ __device__ void resolve_lists(const Inst& d, const VI* A, int na, const VI* B, i
 }
 
 template <typename Tin>
-__device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
+__device__ __forceinline__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
   resolve_lists<Tin>(d, &amax, 1, &bmax, 1, flags, scratch);
 }
 
@@ -1300,7 +1300,7 @@ __device__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t fla
 // p = 1..T-1 take the best entry not yet taken.  Returns how many exist
 // (fewer than T when M < T).  value_of(n) gives r[n] for n < m.
 template <typename F>
-__device__ int block_top_t(F value_of, int m, int T, VI (&top)[kTopTMax], VI* scratch) {
+__device__ __forceinline__ int block_top_t(F value_of, int m, int T, VI (&top)[kTopTMax], VI* scratch) {
   int got = 1;
 #pragma unroll
   for (int p = 1; p < kTopTMax; ++p) {
@@ -1326,7 +1326,7 @@ __device__ int block_top_t(F value_of, int m, int T, VI (&top)[kTopTMax], VI* sc
 // top-T re-scoring from the whole correlations in `rtop` (fold A at 0, fold B
 // at ma), given both argmaxes
 template <typename Tin>
-__device__ void resolve_top_t(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
+__device__ __forceinline__ void resolve_top_t(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
   const int ma = d.va.m, mb = d.vb.m;
   const GAS double* r = G(d.rtop);
   VI A[kTopTMax], B[kTopTMax];
@@ -2270,7 +2270,7 @@ __global__ void __launch_bounds__(256) k_cgemm(InstTable tab, const int32_t* lis
 }
 
 template <typename Tin>
-__device__ void cg_final(const Inst& d) {
+__device__ __forceinline__ void cg_final(const Inst& d) {
   __shared__ __align__(16) unsigned char scratch[16 * 16];
   __shared__ VI fin[2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -2360,7 +2360,7 @@ __device__ __forceinline__ bool in_set(int64_t c, const ResSet& s) {
 }
 
 template <typename Tin>
-__device__ void combine3(const Inst& d, const Combine3& cb, const tm_result& r1, const tm_result& r2,
+__device__ __forceinline__ void combine3(const Inst& d, const Combine3& cb, const tm_result& r1, const tm_result& r2,
                          tm_result* out, void* scratch) {
   constexpr int kMaxCand = 16;
   __shared__ long long cand[kMaxCand];
