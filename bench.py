@@ -32,10 +32,11 @@ INT8_PEAK_TOPS = 5000.0      # dense int8 MFMA
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
-# HBM bytes per fold launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
-# a plain copy's readings (profiles/hbm_traffic_folds_config2_config3.txt);
-# valid for the fold kernels as those counters saw them
-TRAFFIC_BYTES = {"config2": 1.829e7, "config3": 1.561e9}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a
+# plain copy's readings (profiles/hbm_traffic_config2_config3.txt): the fold
+# kernel (key = workload) and the int8 correlation kernel (workload + "_corr"),
+# valid for the kernels as those counters saw them
+TRAFFIC_BYTES = {"config2": 1.828e7, "config3": 1.561e9, "config2_corr": 7.845e5, "config3_corr": 7.53e8}
 
 
 def corr_roofline(plans, corr_ms, corr_n, traffic=None):
@@ -430,6 +431,11 @@ def main():
         fold_ms, fold_n = tm.profile_read(reset=True)
         corr_ms, corr_n = tm.profile_read_corr(reset=True)
 
+    # every rotated signal once more (untimed), so that each result slot the
+    # oracle comparison reads holds a match
+    for j in range(rot):
+        tm.match_into(plans[j], xs[j], out, j, main_stream)
+    torch.cuda.synchronize()
     results = tm.results_from_device(out)
     planted_ok = sum(int(r.shift == s.shift) for r, s in zip(results, insts))
     ms_per_step = total_ms / args.steps
