@@ -16,10 +16,20 @@
 //              spectrum conj(FFT(t))/P, inverse FFT (steps 4-6 read as a
 //              cross-correlation), argmax over [0, M) (step 7), candidate
 //              intersection (steps 8-9, Theorem 4) and (Tx) scoring.
+//   k_fold_s8 / k_fold_band   streaming fold of int8 signals through an LDS
+//              ring, band fold of 4-byte signals (both moduli in one pass).
+//   k_gfft_*   the FFT correlation through global memory for P above LDS.
+//   k_cgemm_prep / k_cgemm / k_cgemm_final   exact plans with an int8-valued
+//              template: the correlation of steps 4-6 computed directly as an
+//              int8 MFMA product of the literal folds' base-128 digits with
+//              the banded Toeplitz block of t, argmax, resolve.
+//   k_many_*   one template, many signals: one GEMM against the template.
+//   k_combine3 three moduli: intersection of the three candidate sets.
 //   k_twiddles FP64 twiddles exp(-2 pi i e / P) (stored FP64 or FP32).
 //   k_spectrum plan-time FP64 spectrum of the zero-padded template.
 
 #include <algorithm>
+#include <cstdlib>
 
 #include <hip/hip_fp16.h>
 
@@ -2143,14 +2153,16 @@ __global__ void __launch_bounds__(kCgPrepThreads) k_cgemm_prep(InstTable tab, co
   else cg_prep_dispatch(tab.one, e0, chunk);
 }
 
-// the four quarters of a workgroup's 16 x 64 tile summed in LDS (int64), the
-// intermediates, and wave nt's best shift of column tile nt
-template <int NL>
+// The W parts of a workgroup's 16 x 64 tile summed in LDS (int64; with 8
+// waves, waves 4..7 first hand their parts to waves 0..3 through the same
+// 32 KiB), the intermediates, and wave nt's best shift of column tile nt.
+template <int NL, int W>
 __device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int M, const v4i_t (&acc)[NL][4],
                                                long long* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
-  // digits to int64, this wave's quarter into LDS: red[w][nt][jj][lane]
+  // digits to int64
+  long long part[4][4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -2158,9 +2170,30 @@ __device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int
       long long r = 0, wt = 1;
 #pragma unroll
       for (int l = 0; l < NL; ++l) { r += wt * (long long)acc[l][nt][jj]; wt *= 128; }
-      red[((w * 4 + nt) * 4 + jj) * 64 + lane] = r;
+      part[nt][jj] = r;
     }
+  if constexpr (W == 8) {
+    if (w >= 4)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) red[(((w - 4) * 4 + nt) * 4 + jj) * 64 + lane] = part[nt][jj];
+    __syncthreads();
+    if (w < 4)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) part[nt][jj] += red[((w * 4 + nt) * 4 + jj) * 64 + lane];
+    __syncthreads();
+  }
+  // waves 0..3: their parts into LDS, red[w][nt][jj][lane]
+  if (w < 4)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) red[((w * 4 + nt) * 4 + jj) * 64 + lane] = part[nt][jj];
   __syncthreads();
+  if (w >= 4) return;
   // wave w owns column tile nt = w: lane holds rows 4 g + jj, column c
   const int nt = w;
   double* dr = (f != d.swapped) ? d.dbg_r2 : d.dbg_r1;
@@ -2191,17 +2224,19 @@ __device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int
 }
 
 // One workgroup: rows 16 rt .. 16 rt + 15 (64 shifts each) of fold f.  Wave w
-// takes a quarter of the band's steps for all four 16-column tiles; the
-// quarters are summed in LDS (int64) and wave nt then keeps the best of
-// column tile nt.
-template <int NL>
+// of W takes a contiguous share of the band's steps for all four 16-column
+// tiles; the shares are summed in LDS (int64) and wave nt then keeps the best
+// of column tile nt.  8 waves halve each wave's chain of dependent steps for
+// launches of few instances.
+template <int NL, int W>
 __device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, long long* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int M = f ? d.vb.m : d.va.m;
   const int lp = d.c_lp, KS = d.c_ks;
-  const int q = KS >> 2;                     // steps per wave (KS is a multiple of 4)
-  const int st0 = w * q;
+  const int qw = (KS + W - 1) / W;
+  const int st0 = min(w * qw, KS);
+  const int q = min(qw, KS - st0);           // this wave's steps (may be 0)
   const GAS int8_t* arow = G(d.ylimb) + (int64_t)f * d.c_nlcap * lp + 64 * (kCgRows * rt + c) + 16 * g;
   const GAS int8_t* tsh = G(d.tsh);
   // copies interleaved by 16-byte chunk: chunk m of copy sh at (16 m + sh) * 16,
@@ -2219,10 +2254,11 @@ __device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, long 
     for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
   // the next step's operands are in flight during the current step's MFMAs
   v4i_t bc[4], ac[NL];
+  const int sfirst = min(st0, KS - 1);
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) bc[nt] = ld_b(st0, nt);
+  for (int nt = 0; nt < 4; ++nt) bc[nt] = ld_b(sfirst, nt);
 #pragma unroll
-  for (int l = 0; l < NL; ++l) ac[l] = ld_a(st0, l);
+  for (int l = 0; l < NL; ++l) ac[l] = ld_a(sfirst, l);
   for (int i = 0; i < q; ++i) {
     v4i_t bn[4], an[NL];
     if (i + 1 < q) {
@@ -2240,33 +2276,33 @@ __device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, long 
 #pragma unroll
     for (int l = 0; l < NL; ++l) ac[l] = an[l];
   }
-  cg_finish_rows<NL>(d, f, rt, M, acc, red);
+  cg_finish_rows<NL, W>(d, f, rt, M, acc, red);
 }
 
 // MAXNL: largest digit count this variant is built for (register budget:
 // the int8 signals need at most 3 digits and run on the narrow variant with
 // more waves per SIMD)
-template <int MAXNL>
+template <int MAXNL, int W>
 __device__ __forceinline__ void cg_gemm_dispatch(const Inst& d, int task, long long* red) {
   if (task >= d.c_rta + d.c_rtb) return;
   const int f = task >= d.c_rta ? 1 : 0;
   const int rt = task - f * d.c_rta;
   const int nl = min(min(cg_limbs(G(d.cmax)[f]), d.c_nlcap), MAXNL);
   switch (nl) {
-    case 1: cg_gemm_rows<1>(d, f, rt, red); break;
-    case 2: cg_gemm_rows<2>(d, f, rt, red); break;
-    case 3: cg_gemm_rows<3>(d, f, rt, red); break;
-    case 4: if constexpr (MAXNL >= 4) cg_gemm_rows<4>(d, f, rt, red); break;
-    default: if constexpr (MAXNL >= 5) cg_gemm_rows<5>(d, f, rt, red); break;
+    case 1: cg_gemm_rows<1, W>(d, f, rt, red); break;
+    case 2: cg_gemm_rows<2, W>(d, f, rt, red); break;
+    case 3: cg_gemm_rows<3, W>(d, f, rt, red); break;
+    case 4: if constexpr (MAXNL >= 4) cg_gemm_rows<4, W>(d, f, rt, red); break;
+    default: if constexpr (MAXNL >= 5) cg_gemm_rows<5, W>(d, f, rt, red); break;
   }
 }
 
-// grid (instances, row-tile tasks of both folds)
-template <int MAXNL>
-__global__ void __launch_bounds__(256) k_cgemm(InstTable tab, const int32_t* list) {
+// grid (instances, row-tile tasks of both folds), W waves per workgroup
+template <int MAXNL, int W>
+__global__ void __launch_bounds__(64 * W) k_cgemm(InstTable tab, const int32_t* list) {
   __shared__ long long red[4 * 4 * 4 * 64];
-  if (list) cg_gemm_dispatch<MAXNL>(tab.table[list[blockIdx.x]], blockIdx.y, red);
-  else cg_gemm_dispatch<MAXNL>(tab.one, blockIdx.y, red);
+  if (list) cg_gemm_dispatch<MAXNL, W>(tab.table[list[blockIdx.x]], blockIdx.y, red);
+  else cg_gemm_dispatch<MAXNL, W>(tab.one, blockIdx.y, red);
 }
 
 template <typename Tin>
@@ -2321,12 +2357,25 @@ hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int coun
   return hipGetLastError();
 }
 
+// TM_CGEMM_WAVES=4 keeps 4 waves per workgroup for every launch
+static int env_int_dev(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v && *v ? std::atoi(v) : dflt;
+}
+
 hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const dim3 grid(count, gemm_y);
-  if (max_limbs <= 3) hipLaunchKernelGGL(k_cgemm<3>, grid, dim3(256), 0, s, tab, list);
-  else hipLaunchKernelGGL(k_cgemm<5>, grid, dim3(256), 0, s, tab, list);
+  // few instances: 8 waves per workgroup, half the dependent steps per wave
+  const bool wide = count * gemm_y < 512 && env_int_dev("TM_CGEMM_WAVES", 8) == 8;
+  if (wide) {
+    if (max_limbs <= 3) hipLaunchKernelGGL((k_cgemm<3, 8>), grid, dim3(512), 0, s, tab, list);
+    else hipLaunchKernelGGL((k_cgemm<5, 8>), grid, dim3(512), 0, s, tab, list);
+  } else {
+    if (max_limbs <= 3) hipLaunchKernelGGL((k_cgemm<3, 4>), grid, dim3(256), 0, s, tab, list);
+    else hipLaunchKernelGGL((k_cgemm<5, 4>), grid, dim3(256), 0, s, tab, list);
+  }
   return hipGetLastError();
 }
 

@@ -154,12 +154,12 @@ int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
 }
 
 // Literal-fold entries per prep workgroup: about 4096 workgroups over the
-// launch's entries, at least 1024 and at most one instance's pair of folds;
+// launch's entries, at least 256 and at most one instance's pair of folds;
 // grid rows = chunks of the largest instance.
 struct CgLaunch { int chunk; int prep_y; };
 CgLaunch cgemm_launch(int64_t total_entries, int64_t max_entries, int64_t count) {
   (void)count;
-  int64_t chunk = std::max<int64_t>(1024, align_up(ceil_div(total_entries, 4096), 256));
+  int64_t chunk = std::max<int64_t>(256, align_up(ceil_div(total_entries, 4096), 256));
   chunk = std::min(chunk, align_up(max_entries, 256));
   return CgLaunch{(int)chunk, (int)ceil_div(max_entries, chunk)};
 }
