@@ -193,6 +193,17 @@ size_t finish_lds_bytes(int p_log2, int mode);
 int fft_lds_max_log2(int mode);         // largest P (log2) whose FFT fits one workgroup
 int finish_threads(int p_log2);         // finish workgroup size for FFT length 2^p_log2
 
+// Kernel timing: while `stop` is set, every kernel launched on this thread
+// carries the two events on its own dispatch (hipExtLaunchKernel), so their
+// elapsed time covers the kernels' execution only, not the host's launch
+// gaps. The first launch takes `start` and clears it; every launch re-takes
+// `stop`, so a region of several kernels spans first start to last end.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
 // Kernel launchers (tm_kernels.hip).
 hipError_t configure_kernels();        // raise dynamic LDS limits on the current device
 hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStream_t s);

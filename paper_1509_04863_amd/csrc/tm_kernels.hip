@@ -31,11 +31,26 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
 #include "tm_internal.h"
 
 namespace tmi {
+
+thread_local LaunchEvents g_launch_events;
+
+// every launch goes through here: a plain launch unless a timed region is open
+#define TM_LAUNCH(K, GRID, BLOCK, LDS, S, ...)                                                  \
+  do {                                                                                          \
+    LaunchEvents& ev_ = g_launch_events;                                                        \
+    if (ev_.stop) {                                                                             \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, (uint32_t)(LDS), S, ev_.start, ev_.stop, 0u, __VA_ARGS__); \
+      ev_.start = nullptr;                                                                      \
+    } else {                                                                                    \
+      hipLaunchKernelGGL(K, GRID, BLOCK, LDS, S, __VA_ARGS__);                                \
+    }                                                                                           \
+  } while (0)
 
 // --------------------------------------------------------------------------
 // element types and conversions
@@ -1829,11 +1844,11 @@ hipError_t launch_gfft_t(const Inst& one, hipStream_t s) {
   const int cols_threads = std::min(kFinishThreads, std::max(64, (B << q) >> 4));
   const size_t cols_lds = (size_t)padded_len(B << q) * sizeof(cplx<T>) + (size_t)(kFinishThreads / 64) * sizeof(Top2);
   const int mode = one.mode;
-  hipLaunchKernelGGL((k_gfft_literal<T, Tin>), dim3(P / kGfftThreads), dim3(kGfftThreads), 0, s, tab);
-  hipLaunchKernelGGL(k_gfft_cols<T>, dim3(P2 / B), dim3(cols_threads), cols_lds, s, tab);
-  hipLaunchKernelGGL(k_gfft_rows<T>, dim3(1 << q), dim3(finish_threads(bb)), finish_lds_bytes(bb, mode), s, tab);
-  hipLaunchKernelGGL(k_gfft_icols<T>, dim3(P2 / B), dim3(cols_threads), cols_lds, s, tab);
-  hipLaunchKernelGGL(k_gfft_final<Tin>, dim3(1), dim3(kGfftThreads), 0, s, tab);
+  TM_LAUNCH((k_gfft_literal<T, Tin>), dim3(P / kGfftThreads), dim3(kGfftThreads), 0, s, tab);
+  TM_LAUNCH(k_gfft_cols<T>, dim3(P2 / B), dim3(cols_threads), cols_lds, s, tab);
+  TM_LAUNCH(k_gfft_rows<T>, dim3(1 << q), dim3(finish_threads(bb)), finish_lds_bytes(bb, mode), s, tab);
+  TM_LAUNCH(k_gfft_icols<T>, dim3(P2 / B), dim3(cols_threads), cols_lds, s, tab);
+  TM_LAUNCH(k_gfft_final<Tin>, dim3(1), dim3(kGfftThreads), 0, s, tab);
   return hipGetLastError();
 }
 
@@ -2030,9 +2045,9 @@ __global__ void __launch_bounds__(64) k_many_finish(ManyArgs a) {
 hipError_t launch_many(const ManyArgs& a, hipStream_t s) {
   const int K = a.base.k;
   const int lt = (K + 2 * kGemmPad + 32 + 15) & ~15;
-  hipLaunchKernelGGL(k_many_prep, dim3((a.lp + 255) / 256, a.count, 2), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_many_gemm, dim3((unsigned)(a.rows / kGemmTile), a.nkb, 2), dim3(256), (size_t)16 * lt, s, a);
-  hipLaunchKernelGGL(k_many_finish, dim3(a.count), dim3(64), 0, s, a);
+  TM_LAUNCH(k_many_prep, dim3((a.lp + 255) / 256, a.count, 2), dim3(256), 0, s, a);
+  TM_LAUNCH(k_many_gemm, dim3((unsigned)(a.rows / kGemmTile), a.nkb, 2), dim3(256), (size_t)16 * lt, s, a);
+  TM_LAUNCH(k_many_finish, dim3(a.count), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2353,7 +2368,7 @@ __global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_
 hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int count, int chunk, int prep_y,
                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cgemm_prep, dim3(count, prep_y), dim3(kCgPrepThreads), 0, s, tab, list, chunk);
+  TM_LAUNCH(k_cgemm_prep, dim3(count, prep_y), dim3(kCgPrepThreads), 0, s, tab, list, chunk);
   return hipGetLastError();
 }
 
@@ -2370,18 +2385,18 @@ hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int coun
   // few instances: 8 waves per workgroup, half the dependent steps per wave
   const bool wide = count * gemm_y < 512 && env_int_dev("TM_CGEMM_WAVES", 8) == 8;
   if (wide) {
-    if (max_limbs <= 3) hipLaunchKernelGGL((k_cgemm<3, 8>), grid, dim3(512), 0, s, tab, list);
-    else hipLaunchKernelGGL((k_cgemm<5, 8>), grid, dim3(512), 0, s, tab, list);
+    if (max_limbs <= 3) TM_LAUNCH((k_cgemm<3, 8>), grid, dim3(512), 0, s, tab, list);
+    else TM_LAUNCH((k_cgemm<5, 8>), grid, dim3(512), 0, s, tab, list);
   } else {
-    if (max_limbs <= 3) hipLaunchKernelGGL((k_cgemm<3, 4>), grid, dim3(256), 0, s, tab, list);
-    else hipLaunchKernelGGL((k_cgemm<5, 4>), grid, dim3(256), 0, s, tab, list);
+    if (max_limbs <= 3) TM_LAUNCH((k_cgemm<3, 4>), grid, dim3(256), 0, s, tab, list);
+    else TM_LAUNCH((k_cgemm<5, 4>), grid, dim3(256), 0, s, tab, list);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cgemm_final, dim3(count), dim3(256), 0, s, tab, list);
+  TM_LAUNCH(k_cgemm_final, dim3(count), dim3(256), 0, s, tab, list);
   return hipGetLastError();
 }
 
@@ -2498,7 +2513,7 @@ __global__ void __launch_bounds__(256) k_combine3(const Inst* tab, const Combine
 hipError_t launch_combine3(const Inst* tab, const Combine3* cmb, const tm_result* res, tm_result* out, int count,
                            hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_combine3, dim3(count), dim3(256), 0, s, tab, cmb, res, out);
+  TM_LAUNCH(k_combine3, dim3(count), dim3(256), 0, s, tab, cmb, res, out);
   return hipGetLastError();
 }
 
@@ -2576,25 +2591,25 @@ hipError_t configure_kernels() {
 
 hipError_t launch_fold(const InstTable& tab, int total_tiles, size_t lds, hipStream_t s) {
   if (total_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold, dim3(total_tiles), dim3(kFoldThreads), lds, s, tab, total_tiles);
+  TM_LAUNCH(k_fold, dim3(total_tiles), dim3(kFoldThreads), lds, s, tab, total_tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_fold_band(const InstTable& tab, int total_wgs, hipStream_t s) {
   if (total_wgs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold_band, dim3(total_wgs), dim3(64 * kBandWaves), 0, s, tab, total_wgs);
+  TM_LAUNCH(k_fold_band, dim3(total_wgs), dim3(64 * kBandWaves), 0, s, tab, total_wgs);
   return hipGetLastError();
 }
 
 hipError_t launch_fold_s8(const InstTable& tab, int total_segs, hipStream_t s) {
   if (total_segs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold_s8, dim3(total_segs), dim3(kSegThreads), 0, s, tab, total_segs);
+  TM_LAUNCH(k_fold_s8, dim3(total_segs), dim3(kSegThreads), 0, s, tab, total_segs);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const InstTable& tab, int total_wgs, hipStream_t s) {
   if (total_wgs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(total_wgs), dim3(kReduceThreads), 0, s, tab, total_wgs);
+  TM_LAUNCH(k_reduce, dim3(total_wgs), dim3(kReduceThreads), 0, s, tab, total_wgs);
   return hipGetLastError();
 }
 
@@ -2603,22 +2618,22 @@ hipError_t launch_finish(const InstTable& tab, const int32_t* list, int count, i
   if (count <= 0) return hipSuccess;
   const int nt = finish_threads(p_log2);
   if (mode == MODE_EXACT)
-    hipLaunchKernelGGL(k_finish<double>, dim3(count), dim3(nt), lds, s, tab, list, count);
+    TM_LAUNCH(k_finish<double>, dim3(count), dim3(nt), lds, s, tab, list, count);
   else
-    hipLaunchKernelGGL(k_finish<float>, dim3(count), dim3(nt), lds, s, tab, list, count);
+    TM_LAUNCH(k_finish<float>, dim3(count), dim3(nt), lds, s, tab, list, count);
   return hipGetLastError();
 }
 
 hipError_t launch_twiddles(void* tw, int p_log2, int as_double, hipStream_t s) {
   const int half = (1 << p_log2) >> 1;
   const int blocks = (half + 255) / 256;
-  hipLaunchKernelGGL(k_twiddles, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, tw, p_log2, as_double);
+  TM_LAUNCH(k_twiddles, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, tw, p_log2, as_double);
   return hipGetLastError();
 }
 
 hipError_t launch_spectrum(const void* t, int t_dtype, int k, int p_log2, const double* tw64,
                            double* scratch, void* spec, int as_double, int row_log2, hipStream_t s) {
-  hipLaunchKernelGGL(k_spectrum, dim3(1), dim3(1024), 0, s, t, t_dtype, k, p_log2,
+  TM_LAUNCH(k_spectrum, dim3(1), dim3(1024), 0, s, t, t_dtype, k, p_log2,
                      reinterpret_cast<const double2*>(tw64), reinterpret_cast<double2*>(scratch), spec,
                      as_double, row_log2);
   return hipGetLastError();

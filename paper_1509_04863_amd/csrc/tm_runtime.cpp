@@ -427,32 +427,36 @@ hipError_t folds(const InstTable& tab, const FoldWork& w, hipStream_t s) {
   return launch_fold_band(tab, w.bands, s);
 }
 
-// events around one launch when profiling
+// When profiling, the region's kernels carry a pair of events on their own
+// dispatches: the elapsed time is first kernel start to last kernel end.
 template <typename F>
-hipError_t timed_corr(hipStream_t s, F&& launch) {
+hipError_t timed_region(std::vector<std::pair<hipEvent_t, hipEvent_t>>& live, F&& launch) {
   if (!g_prof_on) return launch();
   hipEvent_t a, b;
   hipError_t e = prof_event(&a);
   if (e != hipSuccess) return e;
   if ((e = prof_event(&b)) != hipSuccess) return e;
-  if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
-  if ((e = launch()) != hipSuccess) return e;
-  if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
-  g_prof_corr_live.emplace_back(a, b);
-  return hipSuccess;
+  g_launch_events.start = a;
+  g_launch_events.stop = b;
+  e = launch();
+  const bool launched = g_launch_events.start == nullptr;
+  g_launch_events = LaunchEvents{};
+  if (e == hipSuccess && launched) {
+    live.emplace_back(a, b);
+  } else {
+    g_prof_free.push_back(a);
+    g_prof_free.push_back(b);
+  }
+  return e;
+}
+
+template <typename F>
+hipError_t timed_corr(hipStream_t, F&& launch) {
+  return timed_region(g_prof_corr_live, launch);
 }
 
 hipError_t timed_fold(const InstTable& tab, const FoldWork& w, hipStream_t s) {
-  if (!g_prof_on) return folds(tab, w, s);
-  hipEvent_t a, b;
-  hipError_t e = prof_event(&a);
-  if (e != hipSuccess) return e;
-  if ((e = prof_event(&b)) != hipSuccess) return e;
-  if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
-  if ((e = folds(tab, w, s)) != hipSuccess) return e;
-  if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
-  g_prof_live.emplace_back(a, b);
-  return hipSuccess;
+  return timed_region(g_prof_live, [&] { return folds(tab, w, s); });
 }
 bool g_configured[64] = {};
 
