@@ -13,8 +13,11 @@ Prints one JSON line: whole-job matches/s; the roofline of the dominant
 kernel, the fold (HBM bytes against 8 TB/s) or the correlation (int8 matrix
 product: 2 K (M1 + M2) operations per match against 5 POP/s; FFT finish: its
 FFT flops against the FP64 or FP32 vector peak), both timed by HIP events
-around every launch of a separate single-stream run, the other one reported
-beside it; and the CPU oracle timed on a bounded sample of the same workload.
+carried on the kernels' own dispatches in a separate single-stream run, the
+other one reported beside it; and the CPU oracle timed on a bounded sample of
+the same workload.  Single-match warmup runs every rotated signal's plan once
+on each stream the timed region uses it on: a plan's first match on a stream
+uploads its device copy of the instance.
 """
 
 import argparse
@@ -405,7 +408,9 @@ def main():
             main_stream.wait_stream(st)
 
     fence_in()
-    issue(args.warmup)
+    # every (signal, stream) pair of the timed region at least once
+    warm_matches = max(args.warmup, min(args.steps, math.lcm(rot, len(streams))))
+    issue(warm_matches)
     fence_out()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -453,7 +458,7 @@ def main():
         "config": {"workload": args.config + ": " + wl["desc"], "n": first.n, "k": first.k,
                    "m1": info["m1"], "m2": info["m2"], "fft_len": p_len,
                    "x_dtype": str(first.x.dtype), "signals_rotated": rot,
-                   "rotated_bytes": rot * x_bytes, "streams": len(streams),
+                   "rotated_bytes": rot * x_bytes, "streams": len(streams), "warmup_matches": warm_matches,
                    "fold_kernel": "k_fold_band" if info["fold_bands"] else
                                   ("k_fold_s8" if info["fold_segments"] else "k_fold")},
         "planted_recovered": "%d/%d" % (planted_ok, rot),

@@ -95,14 +95,36 @@ struct alignas(16) Inst {
   double* dbg_r2;
 };
 
-// A launch's view of its instances: a device table, or one instance inline in
-// the kernel arguments (single matches skip the table upload).
+// A launch's view of its instances: a device table (batches), or one
+// device-resident instance (single matches: the kernel arguments stay within
+// 64 bytes, which keeps the host's cost per launch low).  A single match's
+// signal and result slot travel with the launch of its fold kernel, which
+// stores them into the device copy for the kernels that follow on the stream.
 struct InstTable {
-  const Inst* table;      // device pointer, or nullptr to use `one`
+  const Inst* table;      // device table, or nullptr for the single instance at `one`
+  const Inst* one;        // device copy of the single instance
+  const void* x;          // the single instance's signal (fold kernels)
+  tm_result* out;         // its result slot (fold kernels)
   int32_t count;
-  Inst one;
-  __device__ __forceinline__ const Inst& get(int i) const { return table ? table[i] : one; }
+  // fold kernels: the instance with this launch's signal and result slot
+  __device__ __forceinline__ Inst single() const {
+    Inst d = *one;
+    d.x = x;
+    d.out = out;
+    return d;
+  }
+  // kernels after the fold: the device copy, signal and result slot included
+  __device__ __forceinline__ const Inst& resident() const { return *one; }
+  // fold kernels, one thread of the launch: store the signal and result slot
+  // into the device copy (ordinary vector stores; the next kernel on the
+  // stream sees them)
+  __device__ __forceinline__ void publish() const {
+    Inst* w = const_cast<Inst*>(one);
+    w->x = x;
+    w->out = out;
+  }
 };
+static_assert(sizeof(InstTable) <= 40, "single-match kernel arguments stay small");
 
 constexpr int kFoldThreads = 256;
 constexpr int kFoldLoads = 16;          // 16-byte chunks each fold thread stages per tile
@@ -232,6 +254,6 @@ int cgemm_limbs_for(int64_t maxabs);                   // limbs that hold |y| <=
 // pairs' argmaxes, re-scored by (Tx)_c (one workgroup each)
 hipError_t launch_combine3(const Inst* tab, const Combine3* cmb, const tm_result* res, tm_result* out, int count,
                            hipStream_t s);
-hipError_t launch_gfft(const Inst& one, hipStream_t s);   // literal folds .. result, one instance
+hipError_t launch_gfft(const Inst& host, const Inst* dev, hipStream_t s);   // literal folds .. result, one instance
 
 }  // namespace tmi

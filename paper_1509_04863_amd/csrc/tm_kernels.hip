@@ -343,8 +343,9 @@ __device__ __forceinline__ void fold_dispatch(const Inst& d, int lt, unsigned ch
   }
 }
 
-// The table and the inline descriptor take separate paths so that each keeps
-// its own address space (no private copy of the kernel argument).
+// The table and the single instance take separate paths, each inlined on its
+// own.  On the single path, thread 0 of the first workgroup stores the launch's
+// signal and result slot into the instance's device copy for the later kernels.
 __global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_tiles) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int tile = blockIdx.x;
@@ -353,7 +354,8 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_
     const Inst& d = tab.table[find_inst_by_tile(tab, tile)];
     fold_dispatch(d, tile - d.tile_base, lds);
   } else {
-    fold_dispatch(tab.one, tile, lds);
+    if (tile == 0 && threadIdx.x == 0) tab.publish();
+    fold_dispatch(tab.single(), tile, lds);
   }
 }
 
@@ -594,7 +596,8 @@ __global__ void __launch_bounds__(kSegThreads) k_fold_s8(InstTable tab, int tota
     const Inst& d = tab.table[find_inst_by_seg(tab, seg)];
     fold_segment_any(d, seg - d.seg_base, lds);
   } else {
-    fold_segment_any(tab.one, seg, lds);
+    if (seg == 0 && threadIdx.x == 0) tab.publish();
+    fold_segment_any(tab.single(), seg, lds);
   }
 }
 
@@ -703,7 +706,8 @@ __global__ void __launch_bounds__(64 * kBandWaves) k_fold_band(InstTable tab, in
     const Inst& d = tab.table[find_inst_by_band(tab, wg)];
     band_dispatch(d, wg - d.band_base, lds);
   } else {
-    band_dispatch(tab.one, wg, lds);
+    if (wg == 0 && threadIdx.x == 0) tab.publish();
+    band_dispatch(tab.single(), wg, lds);
   }
 }
 
@@ -733,7 +737,10 @@ __device__ __forceinline__ float bucket_part(const Inst& d, int f, int s, int rb
 
 // Threads of a workgroup are split into groups of red_tpe lanes, one group per
 // fold entry; lane t sums row blocks t, t + tpe, ... and lane 0 adds the lanes
-// in order, then the cyclic wrap terms.
+// in order, then the cyclic wrap terms.  (SINGLE only keeps the table and the
+// single-instance call sites apart, so that they are not merged into one call
+// through a pointer that could point at either.)
+template <bool SINGLE>
 __device__ __forceinline__ void reduce_wg(const Inst& d, int lc, float* part) {
   const int tpe = d.red_tpe;
   const int epw = kReduceThreads / tpe;
@@ -777,9 +784,9 @@ __global__ void __launch_bounds__(kReduceThreads) k_reduce(InstTable tab, int to
   if (wg >= total_wgs) return;
   if (tab.table) {
     const Inst& d = tab.table[find_inst_by_red(tab, wg)];
-    reduce_wg(d, wg - d.red_base, part);
+    reduce_wg<false>(d, wg - d.red_base, part);
   } else {
-    reduce_wg(tab.one, wg, part);
+    reduce_wg<true>(tab.resident(), wg, part);
   }
 }
 
@@ -1558,7 +1565,7 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish(InstTable tab, const 
   const int b = blockIdx.x;
   if (b >= count) return;
   if (tab.table) finish_dispatch<T>(tab.table[list ? list[b] : b], lds);
-  else finish_dispatch<T>(tab.one, lds);
+  else finish_dispatch<T>(tab.resident(), lds);
 }
 
 // --------------------------------------------------------------------------
@@ -1627,7 +1634,7 @@ __device__ void fft_batch_inverse(cplx<T>* buf, int lb, int q, const cplx<T>* tw
 
 template <typename T, typename Tin>
 __global__ void __launch_bounds__(kGfftThreads) k_gfft_literal(InstTable tab) {
-  const Inst& d = tab.one;
+  const Inst& d = tab.resident();
   __shared__ double red[kGfftThreads / 64];
   const int n = blockIdx.x * kGfftThreads + threadIdx.x;
   const int P = 1 << d.p_log2;
@@ -1675,7 +1682,7 @@ __global__ void __launch_bounds__(kGfftThreads) k_gfft_literal(InstTable tab) {
 template <typename T>
 __global__ void __launch_bounds__(kFinishThreads) k_gfft_cols(InstTable tab) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const Inst& d = tab.one;
+  const Inst& d = tab.resident();
   const int p = d.p_log2, q = d.g_q, lb = d.g_logb, bb = p - q;
   const int P1 = 1 << q, P2 = 1 << bb, B = 1 << lb;
   const int c0 = blockIdx.x * B;
@@ -1701,7 +1708,7 @@ __global__ void __launch_bounds__(kFinishThreads) k_gfft_cols(InstTable tab) {
 template <typename T>
 __global__ void __launch_bounds__(kFinishThreads) k_gfft_rows(InstTable tab) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const Inst& d = tab.one;
+  const Inst& d = tab.resident();
   const int p = d.p_log2, q = d.g_q, bb = p - q;
   const int P2 = 1 << bb;
   const int j = blockIdx.x;
@@ -1756,7 +1763,7 @@ __device__ Top2 block_top2(Top2 mine, Top2* scratch) {
 template <typename T>
 __global__ void __launch_bounds__(kFinishThreads) k_gfft_icols(InstTable tab) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const Inst& d = tab.one;
+  const Inst& d = tab.resident();
   const int p = d.p_log2, q = d.g_q, lb = d.g_logb, bb = p - q;
   const int P1 = 1 << q, P2 = 1 << bb, B = 1 << lb;
   const int c0 = blockIdx.x * B;
@@ -1803,7 +1810,7 @@ __global__ void __launch_bounds__(kFinishThreads) k_gfft_icols(InstTable tab) {
 
 template <typename Tin>
 __global__ void __launch_bounds__(kGfftThreads) k_gfft_final(InstTable tab) {
-  const Inst& d = tab.one;
+  const Inst& d = tab.resident();
   __shared__ __align__(16) unsigned char scratch[kGfftThreads * 16];
   __shared__ Top2 fa, fb;
   __shared__ double zn2;
@@ -1834,11 +1841,13 @@ __global__ void __launch_bounds__(kGfftThreads) k_gfft_final(InstTable tab) {
 }
 
 template <typename T, typename Tin>
-hipError_t launch_gfft_t(const Inst& one, hipStream_t s) {
+hipError_t launch_gfft_t(const Inst& one, const Inst* dev, hipStream_t s) {
   InstTable tab{};
   tab.table = nullptr;
   tab.count = 1;
-  tab.one = one;
+  tab.one = dev;
+  tab.x = one.x;
+  tab.out = one.out;
   const int p = one.p_log2, q = one.g_q, lb = one.g_logb, bb = p - q;
   const int P = 1 << p, P2 = 1 << bb, B = 1 << lb;
   const int cols_threads = std::min(kFinishThreads, std::max(64, (B << q) >> 4));
@@ -1853,17 +1862,19 @@ hipError_t launch_gfft_t(const Inst& one, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_gfft_x(const Inst& one, hipStream_t s) {
+hipError_t launch_gfft_x(const Inst& one, const Inst* dev, hipStream_t s) {
   switch (one.x_dtype) {
-    case TM_I8: return launch_gfft_t<T, int8_t>(one, s);
-    case TM_F32: return launch_gfft_t<T, float>(one, s);
-    case TM_BF16: return launch_gfft_t<T, bf16_t>(one, s);
-    default: return launch_gfft_t<T, f16_t>(one, s);
+    case TM_I8: return launch_gfft_t<T, int8_t>(one, dev, s);
+    case TM_F32: return launch_gfft_t<T, float>(one, dev, s);
+    case TM_BF16: return launch_gfft_t<T, bf16_t>(one, dev, s);
+    default: return launch_gfft_t<T, f16_t>(one, dev, s);
   }
 }
 
-hipError_t launch_gfft(const Inst& one, hipStream_t s) {
-  return one.mode == MODE_EXACT ? launch_gfft_x<double>(one, s) : launch_gfft_x<float>(one, s);
+// `host` is the instance as the host built it (grid sizes, signal, result
+// slot), `dev` its copy in device memory
+hipError_t launch_gfft(const Inst& host, const Inst* dev, hipStream_t s) {
+  return host.mode == MODE_EXACT ? launch_gfft_x<double>(host, dev, s) : launch_gfft_x<float>(host, dev, s);
 }
 
 // --------------------------------------------------------------------------
@@ -2165,7 +2176,7 @@ __device__ __forceinline__ void cg_prep_dispatch(const Inst& d, int e0, int chun
 __global__ void __launch_bounds__(kCgPrepThreads) k_cgemm_prep(InstTable tab, const int32_t* list, int chunk) {
   const int e0 = blockIdx.y * chunk;
   if (list) cg_prep_dispatch(tab.table[list[blockIdx.x]], e0, chunk);
-  else cg_prep_dispatch(tab.one, e0, chunk);
+  else cg_prep_dispatch(tab.resident(), e0, chunk);
 }
 
 // The W parts of a workgroup's 16 x 64 tile summed in LDS (int64; with 8
@@ -2317,7 +2328,7 @@ template <int MAXNL, int W>
 __global__ void __launch_bounds__(64 * W) k_cgemm(InstTable tab, const int32_t* list) {
   __shared__ long long red[4 * 4 * 4 * 64];
   if (list) cg_gemm_dispatch<MAXNL, W>(tab.table[list[blockIdx.x]], blockIdx.y, red);
-  else cg_gemm_dispatch<MAXNL, W>(tab.one, blockIdx.y, red);
+  else cg_gemm_dispatch<MAXNL, W>(tab.resident(), blockIdx.y, red);
 }
 
 template <typename Tin>
@@ -2362,7 +2373,7 @@ __device__ __forceinline__ void cg_final_dispatch(const Inst& d) {
 
 __global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_t* list) {
   if (list) cg_final_dispatch(tab.table[list[blockIdx.x]]);
-  else cg_final_dispatch(tab.one);
+  else cg_final_dispatch(tab.resident());
 }
 
 hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int count, int chunk, int prep_y,

@@ -551,6 +551,8 @@ bool is_device_pointer(const void* ptr) {
 
 // ---------------------------------------------------------------- plan
 
+constexpr int kResidentSlots = 8;   // stream pools per plan served from the plan's slabs
+
 struct tm_plan_s {
   tm_plan_desc desc{};
   Core core;
@@ -564,6 +566,21 @@ struct tm_plan_s {
   int8_t* tsh = nullptr;     // GEMM path: 16 shifted copies of the zero-padded template
   double tnorm1 = 0.0;
   tm_plan_s* pair2 = nullptr;   // three moduli: the plan of the pair (M3, M1) (owned)
+  // single matches: the instance in device memory, one copy per stream pool
+  // (the first kResidentSlots in slabs made with the plan), each with a pinned
+  // staging copy and the host's image of it (signal and result slot null)
+  struct Resident {
+    const StreamPool* pool = nullptr;
+    Inst* dev = nullptr;
+    Inst* staging = nullptr;
+    hipEvent_t copied = nullptr;   // the last upload from `staging` is done
+    bool pending = false;
+    bool own = false;              // dev / staging allocated for this entry
+    Inst shadow{};
+  };
+  Inst* res_dev = nullptr;
+  Inst* res_host = nullptr;
+  std::vector<Resident> resident;
 };
 
 namespace {
@@ -796,6 +813,8 @@ static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t
     if (p->t_dev) (void)hipFree(p->t_dev);
     if (p->spec) (void)hipFree(p->spec);
     if (p->tsh) (void)hipFree(p->tsh);
+    if (p->res_dev) (void)hipFree(p->res_dev);
+    if (p->res_host) (void)hipHostFree(p->res_host);
     delete p;
   };
 #define TM_HIP_PLAN(expr)                                                              \
@@ -808,6 +827,8 @@ static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t
     }                                                                                  \
   } while (0)
   TM_HIP_PLAN(hipMalloc(&p->t_dev, std::max<size_t>(tb, 16)));
+  TM_HIP_PLAN(hipMalloc(reinterpret_cast<void**>(&p->res_dev), kResidentSlots * sizeof(Inst)));
+  TM_HIP_PLAN(hipHostMalloc(reinterpret_cast<void**>(&p->res_host), kResidentSlots * sizeof(Inst), hipHostMallocDefault));
   TM_HIP_PLAN(hipMemcpyAsync(p->t_dev, th.data(), tb, hipMemcpyHostToDevice, s));
   if (c.cgemm) {
     // the GEMM path needs no spectrum: 16 copies of [0 (pad + sh), t, 0 ...],
@@ -854,6 +875,16 @@ tm_status tm_plan_destroy(tm_plan p) {
     if (st != TM_OK) return st;
   }
   TM_HIP(hipDeviceSynchronize());
+  for (auto& r : p->resident) {
+    if (r.copied) TM_HIP(hipEventDestroy(r.copied));
+    if (r.own) {
+      TM_HIP(hipFree(r.dev));
+      TM_HIP(hipHostFree(r.staging));
+    }
+  }
+  p->resident.clear();
+  if (p->res_dev) TM_HIP(hipFree(p->res_dev));
+  if (p->res_host) TM_HIP(hipHostFree(p->res_host));
   if (p->t_dev) TM_HIP(hipFree(p->t_dev));
   if (p->spec) TM_HIP(hipFree(p->spec));
   if (p->tsh) TM_HIP(hipFree(p->tsh));
@@ -870,6 +901,58 @@ tm_status tm_plan_get_info(tm_plan p, tm_plan_info* info) {
 
 tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
                          void* stream);
+
+// The single-match instance in device memory for a stream's pool.  The copy
+// is rewritten only when the host's instance differs from it, signal and
+// result slot aside (the fold kernel of each match stores those two): through
+// the entry's pinned staging copy, ordered on the stream after the kernels
+// that may still read the old one.  The first match of a plan on a stream, or
+// one after the pool's workspace moved, pays for one small upload.
+static tm_status resident_inst(tm_plan p, StreamPool& pool, const Inst& host, hipStream_t s,
+                               const Inst** dev) {
+  Inst key;
+  std::memcpy(&key, &host, sizeof(Inst));
+  key.x = nullptr;
+  key.out = nullptr;
+  tm_plan_s::Resident* r = nullptr;
+  for (auto& e : p->resident)
+    if (e.pool == &pool) r = &e;
+  if (r && std::memcmp(&r->shadow, &key, sizeof(Inst)) == 0) {
+    *dev = r->dev;
+    return TM_OK;
+  }
+  if (!r) {
+    tm_plan_s::Resident e;
+    e.pool = &pool;
+    const size_t i = p->resident.size();
+    if (i < (size_t)kResidentSlots) {
+      e.dev = p->res_dev + i;
+      e.staging = p->res_host + i;
+    } else {
+      TM_HIP(hipMalloc(reinterpret_cast<void**>(&e.dev), sizeof(Inst)));
+      hipError_t he = hipHostMalloc(reinterpret_cast<void**>(&e.staging), sizeof(Inst), hipHostMallocDefault);
+      if (he != hipSuccess) {
+        (void)hipFree(e.dev);
+        TM_HIP(he);
+      }
+      e.own = true;
+    }
+    p->resident.push_back(e);
+    r = &p->resident.back();
+    TM_HIP(hipEventCreateWithFlags(&r->copied, hipEventDisableTiming));
+  } else if (r->pending) {
+    TM_HIP(hipEventSynchronize(r->copied));   // the staging copy is about to change
+    r->pending = false;
+  }
+  std::memcpy(r->staging, &key, sizeof(Inst));
+  std::memset(&r->shadow, 0, sizeof(Inst));     // no match until the upload is enqueued
+  TM_HIP(hipMemcpyAsync(r->dev, r->staging, sizeof(Inst), hipMemcpyHostToDevice, s));
+  TM_HIP(hipEventRecord(r->copied, s));
+  r->pending = true;
+  std::memcpy(&r->shadow, &key, sizeof(Inst));
+  *dev = r->dev;
+  return TM_OK;
+}
 
 static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1, double* y2,
                            double* r1, double* r2, void* stream) {
@@ -890,26 +973,35 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   if (st != TM_OK) return st;
   st = ensure_acc(pool, p->core.acc_bytes, s);
   if (st != TM_OK) return st;
+  Inst one;
+  fill_inst(p, x, &one);
+  char* base = static_cast<char*>(pool.dev);
+  place_workspace(p->core, base, static_cast<char*>(pool.acc), &one);
+  one.tile_base = 0;
+  one.seg_base = 0;
+  one.band_base = 0;
+  one.red_base = 0;
+  one.out = dev_out ? out : reinterpret_cast<tm_result*>(base + p->core.off_res);
+  one.dbg_y1 = y1;
+  one.dbg_y2 = y2;
+  one.dbg_r1 = r1;
+  one.dbg_r2 = r2;
+  const Inst* dev_one = nullptr;
+  st = resident_inst(p, pool, one, s, &dev_one);
+  if (st != TM_OK) return st;
   InstTable tab{};
   tab.table = nullptr;
   tab.count = 1;
-  fill_inst(p, x, &tab.one);
-  char* base = static_cast<char*>(pool.dev);
-  place_workspace(p->core, base, static_cast<char*>(pool.acc), &tab.one);
-  tab.one.tile_base = 0;
-  tab.one.seg_base = 0;
-  tab.one.band_base = 0;
-  tab.one.red_base = 0;
-  tab.one.out = dev_out ? out : reinterpret_cast<tm_result*>(base + p->core.off_res);
-  tab.one.dbg_y1 = y1;
-  tab.one.dbg_y2 = y2;
-  tab.one.dbg_r1 = r1;
-  tab.one.dbg_r2 = r2;
+  tab.one = dev_one;
+  tab.x = one.x;
+  tab.out = one.out;
   FoldWork fw;
   fw.tiles = p->core.ntiles;
   fw.lds = p->core.fold_lds;
   fw.segs = p->core.nseg;
   fw.bands = p->core.nband;
+  // the fold kernel stores the signal and result slot for the kernels after it
+  if (fw.tiles + fw.segs + fw.bands <= 0) return fail(TM_ERR_INVALID, "plan without fold work");
   TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;                 // until the finish kernel is enqueued
   TM_HIP(launch_reduce(tab, p->core.nred, s));
@@ -920,12 +1012,12 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
                                                         p->core.c_nlcap, s); }));
     TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
   }
-  else if (p->core.gfft) TM_HIP(launch_gfft(tab.one, s));
+  else if (p->core.gfft) TM_HIP(launch_gfft(one, dev_one, s));
   else TM_HIP(timed_corr(s, [&] { return launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2,
                                                         p->core.finish_lds, s); }));
   pool.acc_dirty = false;
   if (!dev_out) {
-    TM_HIP(hipMemcpyAsync(out, tab.one.out, sizeof(tm_result), hipMemcpyDeviceToHost, s));
+    TM_HIP(hipMemcpyAsync(out, one.out, sizeof(tm_result), hipMemcpyDeviceToHost, s));
     TM_HIP(hipStreamSynchronize(s));
   }
   return TM_OK;
@@ -1068,7 +1160,7 @@ static tm_status run_batch(int32_t count, const tm_plan* plans, const void* cons
     int32_t g1 = g0 + 1;
     while (g1 < count && plans[order[g1]]->core.mode == c0.mode && plans[order[g1]]->core.p_log2 == c0.p_log2) ++g1;
     if (c0.gfft) {   // one launch sequence per instance
-      for (int32_t g = g0; g < g1; ++g) TM_HIP(launch_gfft(host_tab[order[g]], s));
+      for (int32_t g = g0; g < g1; ++g) TM_HIP(launch_gfft(host_tab[order[g]], tab.table + order[g], s));
     } else {
       TM_HIP(launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.p_log2, c0.finish_lds, s));
     }
