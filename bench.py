@@ -39,7 +39,7 @@ FP32_PEAK_TFLOPS = 157.3
 # plain copy's readings (profiles/hbm_traffic_config2_config3.txt): the fold
 # kernel (key = workload) and the int8 correlation kernel (workload + "_corr"),
 # valid for the kernels as those counters saw them
-TRAFFIC_BYTES = {"config2": 1.828e7, "config3": 1.561e9, "config2_corr": 8.181e5, "config3_corr": 7.527e8}
+TRAFFIC_BYTES = {"config2": 1.828e7, "config3": 1.561e9, "config2_corr": 8.212e5, "config3_corr": 7.521e8}
 
 
 def corr_roofline(plans, corr_ms, corr_n, traffic=None):
@@ -81,7 +81,7 @@ def pick_roofline(line, fold_roof, corr_roof):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config5b", "copy"])
@@ -356,6 +356,12 @@ def main():
         print("bench.py measures one GPU: the matcher has no multi-GPU path (matches are "
               "independent; a deployment runs one process per GPU)", file=sys.stderr)
         sys.exit(2)
+    # one hardware queue for each launch stream plus the main stream (read by
+    # the HIP runtime when it starts, so set before torch touches the GPU):
+    # with fewer, two streams share a queue and their kernels serialise
+    want_queues = args.streams + 1
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < want_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(want_queues, 16))
 
     import numpy as np
     import torch
@@ -459,6 +465,7 @@ def main():
                    "m1": info["m1"], "m2": info["m2"], "fft_len": p_len,
                    "x_dtype": str(first.x.dtype), "signals_rotated": rot,
                    "rotated_bytes": rot * x_bytes, "streams": len(streams), "warmup_matches": warm_matches,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "fold_kernel": "k_fold_band" if info["fold_bands"] else
                                   ("k_fold_s8" if info["fold_segments"] else "k_fold")},
         "planted_recovered": "%d/%d" % (planted_ok, rot),
