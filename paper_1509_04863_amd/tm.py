@@ -137,15 +137,29 @@ def _check(status: int):
 _NP_TO_TM = {np.dtype(np.int8): TM_I8, np.dtype(np.float32): TM_F32, np.dtype(np.float16): TM_F16}
 
 
+_TORCH = None
+_TORCH_TO_TM = None
+
+
+def _torch():
+    """torch, imported once (None where it is not installed)."""
+    global _TORCH, _TORCH_TO_TM
+    if _TORCH is None:
+        try:
+            import torch
+        except ImportError:
+            return None
+        _TORCH_TO_TM = {torch.int8: TM_I8, torch.float32: TM_F32, torch.bfloat16: TM_BF16,
+                        torch.float16: TM_F16}
+        _TORCH = torch
+    return _TORCH
+
+
 def tm_dtype_of(arr) -> int:
     """tm_dtype of a numpy array or torch tensor."""
-    try:
-        import torch
-        if isinstance(arr, torch.Tensor):
-            return {torch.int8: TM_I8, torch.float32: TM_F32, torch.bfloat16: TM_BF16,
-                    torch.float16: TM_F16}[arr.dtype]
-    except ImportError:
-        pass
+    torch = _torch()
+    if torch is not None and isinstance(arr, torch.Tensor):
+        return _TORCH_TO_TM[arr.dtype]
     return _NP_TO_TM[np.dtype(arr.dtype)]
 
 
@@ -170,9 +184,8 @@ def plan_params(n, k, m1=0, m2=0, fold_mult=1, x_dtype=TM_I8, t_dtype=TM_I8, fol
 
 
 def _stream_handle(stream) -> int:
-    import torch
     if stream is None:
-        stream = torch.cuda.current_stream()
+        stream = _torch().cuda.current_stream()
     return int(stream.cuda_stream)
 
 
@@ -230,6 +243,8 @@ class Plan:
                                     _stream_handle(stream) if _torch_cuda() else None,
                                     ctypes.byref(handle)))
         self.handle = handle
+        self._n = int(self.desc.n)              # plain ints for the per-call checks
+        self._x_dtype = int(self.desc.x_dtype)
         info = PlanInfo()
         _check(lib().tm_plan_get_info(self.handle, ctypes.byref(info)))
         self.info = _info_dict(info)
@@ -276,12 +291,12 @@ def _torch_cuda() -> bool:
 
 
 def _check_signal(plan: Plan, x):
-    import torch
+    torch = _torch()
     if not isinstance(x, torch.Tensor) or not x.is_cuda:
         raise TypeError("x must be a CUDA (HIP) torch tensor")
-    if x.numel() != plan.n or not x.is_contiguous():
+    if x.numel() != plan._n or not x.is_contiguous():
         raise ValueError("x must be a contiguous tensor of N elements")
-    if tm_dtype_of(x) != plan.desc.x_dtype:
+    if _TORCH_TO_TM.get(x.dtype) != plan._x_dtype:
         raise TypeError("x dtype does not match the plan")
 
 
@@ -297,8 +312,10 @@ def match_into(plan: Plan, x, out, index: int = 0, stream=None):
     """One match writing a device result: `out` is a CUDA uint8 tensor of
     48*count bytes; nothing waits."""
     _check_signal(plan, x)
-    _check(lib().tm_match(plan.handle, x.data_ptr(), out.data_ptr() + 48 * index,
-                          _stream_handle(stream)))
+    st = (_LIB or lib()).tm_match(plan.handle, x.data_ptr(), out.data_ptr() + 48 * index,
+                                  _stream_handle(stream))
+    if st != TM_OK:
+        _check(st)
 
 
 def results_from_device(out) -> List[MatchResult]:
