@@ -171,7 +171,9 @@ tm_status tm_plan_params(const tm_plan_desc* desc, tm_plan_info* info);
  * template spectrum conj(FFT_P([t 0])) / P the correlation uses.
  * The plan owns its device memory, is immutable after creation and may be used
  * from several streams at once.  Work is enqueued on `stream` and the call
- * waits for it before returning.
+ * waits for it before returning.  Besides t and the spectrum (or the shifted
+ * template copies of the int8 product), the plan holds room for 8 device
+ * copies of its per-stream instance record (see tm_match).
  */
 tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_device,
                          void* stream, tm_plan* out);
@@ -191,6 +193,12 @@ tm_status tm_plan_get_info(tm_plan plan, tm_plan_info* info);
  *    waits for the stream; with device memory it only enqueues work and `out`
  *    is valid once the stream reaches this point.
  * The caller keeps x (and a device `out`) alive until then.
+ * The first match of a plan on a stream copies the plan's instance record
+ * (about 400 bytes: sizes, workspace addresses) to device memory, ordered on
+ * the stream; later matches on that stream reuse it and pass the kernels
+ * only its address, x and out.  A plan used on more than 8 streams allocates
+ * one more small device and pinned host block per further stream, kept until
+ * tm_plan_destroy.
  */
 tm_status tm_match(tm_plan plan, const void* x, tm_result* out, void* stream);
 
