@@ -69,10 +69,12 @@ struct alignas(16) Inst {
   int32_t c_ks;           // 64-deep steps over the template band: ceil((K + 63) / 64) rounded up to 4
   int32_t c_rta, c_rtb;   // GEMM workgroups (16 rows of 64 shifts) of fold A and fold B
   int32_t c_lt;           // bytes per shifted template copy in tsh
-  int32_t c_pad0;
+  int32_t c_split;        // workgroups sharing each row tile's band (1: one; above 1, the shares
+                          // are added into `cacc` and the final kernel takes the argmax)
   int8_t* ylimb;          // [2 folds][c_nlcap][c_lp] balanced base-128 digits of the folds
   void* cpart;            // [2 folds][max(c_rta, c_rtb) * 4] best (value, shift) per wave
   int* cmax;              // [2] largest |y| per fold (in the zeroed bucket zone)
+  long long* cacc;        // split band: r of fold A [ma], then B [mb]; zero between launches
   const int8_t* tsh;      // 16 copies of the zero-padded template, copy c shifted by c bytes
   double* rtop;           // top-T on the GEMM and four-step routes: r of fold A [ma], then B [mb]
   int64_t inv_a_mod_b;    // ma^{-1} mod mb

@@ -2181,7 +2181,9 @@ __global__ void __launch_bounds__(kCgPrepThreads) k_cgemm_prep(InstTable tab, co
 
 // The W parts of a workgroup's 16 x 64 tile summed in LDS (int64; with 8
 // waves, waves 4..7 first hand their parts to waves 0..3 through the same
-// 32 KiB), the intermediates, and wave nt's best shift of column tile nt.
+// 32 KiB), then the intermediates and wave nt's best shift of column tile nt;
+// or, when several workgroups share the band, the sum added into the fold's
+// accumulators for the final kernel.
 template <int NL, int W>
 __device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int M, const v4i_t (&acc)[NL][4],
                                                long long* red) {
@@ -2222,6 +2224,19 @@ __device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int
   if (w >= 4) return;
   // wave w owns column tile nt = w: lane holds rows 4 g + jj, column c
   const int nt = w;
+  if (d.c_split > 1) {   // this workgroup's share of the band, added into r (exact int64)
+    long long* ca = d.cacc + (f ? d.va.m : 0);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      long long r = 0;
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) r += red[((ww * 4 + nt) * 4 + jj) * 64 + lane];
+      const int k = 64 * (kCgRows * rt + 4 * g + jj) + 16 * nt + c;
+      if (k < M && r != 0)
+        __hip_atomic_fetch_add(G(ca + k), r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
   double* dr = (f != d.swapped) ? d.dbg_r2 : d.dbg_r1;
   VI best{-INFINITY, 0x7fffffff};
 #pragma unroll
@@ -2255,14 +2270,17 @@ __device__ __forceinline__ void cg_finish_rows(const Inst& d, int f, int rt, int
 // of column tile nt.  8 waves halve each wave's chain of dependent steps for
 // launches of few instances.
 template <int NL, int W>
-__device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, long long* red) {
+__device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, int part, long long* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int M = f ? d.vb.m : d.va.m;
   const int lp = d.c_lp, KS = d.c_ks;
-  const int qw = (KS + W - 1) / W;
-  const int st0 = min(w * qw, KS);
-  const int q = min(qw, KS - st0);           // this wave's steps (may be 0)
+  // this workgroup's share [lo, hi) of the band's steps, then the wave's
+  const int split = max(d.c_split, 1);
+  const int lo = (int)((int64_t)KS * part / split), hi = (int)((int64_t)KS * (part + 1) / split);
+  const int qw = (hi - lo + W - 1) / W;
+  const int st0 = lo + min(w * qw, hi - lo);
+  const int q = max(0, min(qw, hi - st0));   // this wave's steps (may be 0)
   const GAS int8_t* arow = G(d.ylimb) + (int64_t)f * d.c_nlcap * lp + 64 * (kCgRows * rt + c) + 16 * g;
   const GAS int8_t* tsh = G(d.tsh);
   // copies interleaved by 16-byte chunk: chunk m of copy sh at (16 m + sh) * 16,
@@ -2310,16 +2328,19 @@ __device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, long 
 // more waves per SIMD)
 template <int MAXNL, int W>
 __device__ __forceinline__ void cg_gemm_dispatch(const Inst& d, int task, long long* red) {
-  if (task >= d.c_rta + d.c_rtb) return;
+  const int ntask = d.c_rta + d.c_rtb;
+  if (task >= ntask * max(d.c_split, 1)) return;
+  const int part = task / ntask;
+  task -= part * ntask;
   const int f = task >= d.c_rta ? 1 : 0;
   const int rt = task - f * d.c_rta;
   const int nl = min(min(cg_limbs(G(d.cmax)[f]), d.c_nlcap), MAXNL);
   switch (nl) {
-    case 1: cg_gemm_rows<1, W>(d, f, rt, red); break;
-    case 2: cg_gemm_rows<2, W>(d, f, rt, red); break;
-    case 3: cg_gemm_rows<3, W>(d, f, rt, red); break;
-    case 4: if constexpr (MAXNL >= 4) cg_gemm_rows<4, W>(d, f, rt, red); break;
-    default: if constexpr (MAXNL >= 5) cg_gemm_rows<5, W>(d, f, rt, red); break;
+    case 1: cg_gemm_rows<1, W>(d, f, rt, part, red); break;
+    case 2: cg_gemm_rows<2, W>(d, f, rt, part, red); break;
+    case 3: cg_gemm_rows<3, W>(d, f, rt, part, red); break;
+    case 4: if constexpr (MAXNL >= 4) cg_gemm_rows<4, W>(d, f, rt, part, red); break;
+    default: if constexpr (MAXNL >= 5) cg_gemm_rows<5, W>(d, f, rt, part, red); break;
   }
 }
 
@@ -2335,8 +2356,51 @@ template <typename Tin>
 __device__ __forceinline__ void cg_final(const Inst& d) {
   __shared__ __align__(16) unsigned char scratch[16 * 16];
   __shared__ VI fin[2];
+  __shared__ VI wbest[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wave < 2) {
+  if (d.c_split > 1) {
+    // split band: r of each fold from the accumulators (cleared as read)
+    for (int f = 0; f < 2; ++f) {
+      const int M = f ? d.vb.m : d.va.m;
+      long long* ca = d.cacc + (f ? d.va.m : 0);
+      double* dr = (f != d.swapped) ? d.dbg_r2 : d.dbg_r1;
+      VI best{-INFINITY, 0x7fffffff};
+      // 16 loads per thread in flight before any is used
+      constexpr int kB = 16;
+      for (int base = 0; base < M; base += kB * (int)blockDim.x) {
+        long long v[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+          const int k = base + b * (int)blockDim.x + (int)threadIdx.x;
+          v[b] = k < M ? G(ca)[k] : 0;
+        }
+#pragma unroll
+        for (int b = 0; b < kB; ++b) {
+          const int k = base + b * (int)blockDim.x + (int)threadIdx.x;
+          if (k < M) {
+            G(ca)[k] = 0;
+            if (dr) G(dr)[k] = (double)v[b];
+            if (d.rtop) G(d.rtop)[(f ? d.va.m : 0) + k] = (double)v[b];
+            if (vi_better(VI{(double)v[b], k}, best)) best = VI{(double)v[b], k};
+          }
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
+        if (vi_better(other, best)) best = other;
+      }
+      if (lane == 0) wbest[wave] = best;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        VI b = wbest[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+          if (vi_better(wbest[i], b)) b = wbest[i];
+        fin[f] = b;
+      }
+      __syncthreads();
+    }
+  } else if (wave < 2) {
     const int f = wave;
     const int n = (f ? d.c_rtb : d.c_rta) * 4;
     const int rtm = max(d.c_rta, d.c_rtb);

@@ -637,6 +637,7 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->c_rta = c.c_rta;
   in->c_rtb = c.c_rtb;
   in->c_lt = c.c_lt;
+  in->c_split = 1;
   in->tsh = p->tsh;
 }
 
@@ -954,6 +955,17 @@ static tm_status resident_inst(tm_plan p, StreamPool& pool, const Inst& host, hi
   return TM_OK;
 }
 
+// Workgroups sharing each row tile's band in a single match's product kernel
+// (TM_CGEMM_SPLIT, default 1).  With a split, the shares are added into int64
+// accumulators and the final kernel takes the argmax from them.  Measured on
+// a 16 MiB fp32 instance (M = 4096, K = 4096): the product kernel falls from
+// about 11 to 5 us at a split of 14, but the final kernel's pass over the
+// accumulators raises it from about 7 to 22 us, so the split stays off.
+static int cgemm_split(const Core& c) {
+  const int64_t env = env_int("TM_CGEMM_SPLIT", 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(env, std::max(1, c.c_ks)));
+}
+
 static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1, double* y2,
                            double* r1, double* r2, void* stream) {
   tm_status st = check_plan_for_match(p);
@@ -971,12 +983,18 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   StreamPool& pool = g_pools[{p->device, s}];
   st = ensure_device(pool, p->core.ws_bytes, s);
   if (st != TM_OK) return st;
-  st = ensure_acc(pool, p->core.acc_bytes, s);
+  const int split = p->core.cgemm ? cgemm_split(p->core) : 1;
+  const size_t cacc_bytes = split > 1 ? align256((size_t)(p->core.ma + p->core.mb) * sizeof(long long)) : 0;
+  st = ensure_acc(pool, p->core.acc_bytes + cacc_bytes, s);
   if (st != TM_OK) return st;
   Inst one;
   fill_inst(p, x, &one);
   char* base = static_cast<char*>(pool.dev);
   place_workspace(p->core, base, static_cast<char*>(pool.acc), &one);
+  if (split > 1) {
+    one.c_split = split;
+    one.cacc = reinterpret_cast<long long*>(static_cast<char*>(pool.acc) + p->core.acc_bytes);
+  }
   one.tile_base = 0;
   one.seg_base = 0;
   one.band_base = 0;
@@ -1008,7 +1026,7 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   if (p->core.cgemm) {
     const CgLaunch cl = cgemm_launch(2 * (int64_t)p->core.c_lp, 2 * (int64_t)p->core.c_lp, 1);
     TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
-    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, p->core.c_rta + p->core.c_rtb,
+    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, (p->core.c_rta + p->core.c_rtb) * split,
                                                         p->core.c_nlcap, s); }));
     TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
   }

@@ -124,3 +124,28 @@ def test_repeat_determinism_and_bucket_reset():
         assert tm.match(plan, xd) == first
     ref = O.ftm(inst.x, inst.t, plan.m1, plan.m2, correlation="fft")
     assert (first.shift, first.m1_tilde, first.m2_tilde) == (ref.shift, ref.m1_tilde, ref.m2_tilde)
+
+
+@pytest.mark.parametrize("split", ["1", "3", "7", "1000"])
+@pytest.mark.parametrize("top_t", [1, 3])
+def test_band_split_over_workgroups(split, top_t, monkeypatch):
+    # a single match's band may be shared by several workgroups whose shares
+    # are summed into r (exact int64): every split, including more parts than
+    # steps, gives the oracle's correlations and result
+    monkeypatch.setenv("TM_CGEMM_SPLIT", split)
+    rng = np.random.default_rng(int(split) + 10 * top_t)
+    n, k = 90001, 1500
+    x = rng.integers(-128, 128, n).astype(np.int8)
+    t = rng.integers(-3, 4, k).astype(np.int8)
+    x[4321:4321 + k] = t
+    _case("split", split, "top_t", top_t)
+    plan = tm.Plan(t, n=n, top_t=top_t)
+    assert plan.info["corr_gemm"] == 1
+    res, y1, y2, r1, r2 = tm.match_intermediates(plan, to_device(x))
+    ref = O.ftm(x, t, plan.m1, plan.m2, top_t=top_t)
+    assert np.array_equal(r1, ref.r1.astype(np.float64))
+    assert np.array_equal(r2, ref.r2.astype(np.float64))
+    assert res.shift == ref.shift and res.n_candidates == ref.n_candidates
+    assert (res.m1_tilde, res.m2_tilde) == (ref.m1_tilde, ref.m2_tilde)
+    plain = tm.match(plan, to_device(x))
+    assert plain == res
