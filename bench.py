@@ -39,7 +39,7 @@ FP32_PEAK_TFLOPS = 157.3
 # plain copy's readings (profiles/hbm_traffic_config2_config3.txt): the fold
 # kernel (key = workload) and the int8 correlation kernel (workload + "_corr"),
 # valid for the kernels as those counters saw them
-TRAFFIC_BYTES = {"config2": 1.828e7, "config3": 1.561e9, "config2_corr": 8.212e5, "config3_corr": 7.521e8}
+TRAFFIC_BYTES = {"config2": 1.828e7, "config3": 1.561e9, "config2_corr": 8.602e5, "config3_corr": 7.52e8}
 
 
 def corr_roofline(plans, corr_ms, corr_n, traffic=None):
