@@ -286,15 +286,20 @@ tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8, bool pair_of_t
   // int8 signals with both moduli in [kSegMinM, kSegMaxM]: streaming fold over
   // segments of x.  A segment holds at most kSegMaxRows rows of the shorter
   // modulus (16-bit lane sums; a row straddling the end adds one) and, by
-  // default, about N/512 bytes but at least 64 KiB, so a batch of many
-  // instances gets long segments and one large instance still spreads over
-  // many workgroups.
+  // default, about N/512 bytes but at least 64 KiB (4 KiB for signals below
+  // 1 MiB), so a batch of many instances gets long segments (the launch
+  // lengthens them further) and one instance still spreads over many
+  // workgroups.
   const int64_t mmin = std::min(c->ma, c->mb), mmax = std::max(c->ma, c->mb);
   if (d->x_dtype == TM_I8 && mmin >= kSegMinM && mmax <= kSegMaxM && ceil_div(d->n, mmin) < (1 << 23) &&
       env_int("TM_FOLD_STREAM", 1) != 0) {
     const int64_t cap = std::max<int64_t>(1, kSegMaxRows * mmin / 16 - 1);
     int64_t sc = env_int("TM_SEG_BYTES", 0) / 16;
-    if (sc <= 0) sc = std::max<int64_t>(ceil_div(d->n, 512 * 16), 4096);
+    // about N/512 bytes, at least 64 KiB, except that a small signal still
+    // spreads over 16 segments (of at least 4 KiB) when it is matched alone
+    if (sc <= 0)
+      sc = std::max<int64_t>(ceil_div(d->n, 512 * 16),
+                             std::min<int64_t>(4096, std::max<int64_t>(256, ceil_div(d->n, 16 * 16))));
     sc = std::max<int64_t>(1, std::min(sc, cap));
     c->sfold = 1;
     c->seg_chunks = (int32_t)sc;
