@@ -953,7 +953,11 @@ static tm_status resident_inst(tm_plan p, StreamPool& pool, const Inst& host, hi
   std::memcpy(r->staging, &key, sizeof(Inst));
   std::memset(&r->shadow, 0, sizeof(Inst));     // no match until the upload is enqueued
   TM_HIP(hipMemcpyAsync(r->dev, r->staging, sizeof(Inst), hipMemcpyHostToDevice, s));
-  TM_HIP(hipEventRecord(r->copied, s));
+  const hipError_t er = hipEventRecord(r->copied, s);
+  if (er != hipSuccess) {
+    (void)hipStreamSynchronize(s);   // the staging copy must not change under the upload
+    TM_HIP(er);
+  }
   r->pending = true;
   std::memcpy(&r->shadow, &key, sizeof(Inst));
   *dev = r->dev;
