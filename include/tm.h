@@ -172,8 +172,8 @@ tm_status tm_plan_params(const tm_plan_desc* desc, tm_plan_info* info);
  * The plan owns its device memory, is immutable after creation and may be used
  * from several streams at once.  Work is enqueued on `stream` and the call
  * waits for it before returning.  Besides t and the spectrum (or the shifted
- * template copies of the int8 product), the plan holds room for 8 device
- * copies of its per-stream instance record (see tm_match).
+ * template copies of the int8 product), the plan's first single match adds
+ * room for 8 device copies of its per-stream instance record (see tm_match).
  */
 tm_status tm_plan_create(const tm_plan_desc* desc, const void* t, int t_is_device,
                          void* stream, tm_plan* out);

@@ -572,8 +572,9 @@ struct tm_plan_s {
   double tnorm1 = 0.0;
   tm_plan_s* pair2 = nullptr;   // three moduli: the plan of the pair (M3, M1) (owned)
   // single matches: the instance in device memory, one copy per stream pool
-  // (the first kResidentSlots in slabs made with the plan), each with a pinned
-  // staging copy and the host's image of it (signal and result slot null)
+  // (the first kResidentSlots in slabs made at the plan's first single
+  // match), each with a pinned staging copy and the host's image of it
+  // (signal and result slot null)
   struct Resident {
     const StreamPool* pool = nullptr;
     Inst* dev = nullptr;
@@ -833,8 +834,6 @@ static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t
     }                                                                                  \
   } while (0)
   TM_HIP_PLAN(hipMalloc(&p->t_dev, std::max<size_t>(tb, 16)));
-  TM_HIP_PLAN(hipMalloc(reinterpret_cast<void**>(&p->res_dev), kResidentSlots * sizeof(Inst)));
-  TM_HIP_PLAN(hipHostMalloc(reinterpret_cast<void**>(&p->res_host), kResidentSlots * sizeof(Inst), hipHostMallocDefault));
   TM_HIP_PLAN(hipMemcpyAsync(p->t_dev, th.data(), tb, hipMemcpyHostToDevice, s));
   if (c.cgemm) {
     // the GEMM path needs no spectrum: 16 copies of [0 (pad + sh), t, 0 ...],
@@ -928,6 +927,18 @@ static tm_status resident_inst(tm_plan p, StreamPool& pool, const Inst& host, hi
     return TM_OK;
   }
   if (!r) {
+    if (!p->res_dev) {   // the plan's first single match: its slabs
+      void* dv = nullptr;
+      void* hs = nullptr;
+      TM_HIP(hipMalloc(&dv, kResidentSlots * sizeof(Inst)));
+      const hipError_t he = hipHostMalloc(&hs, kResidentSlots * sizeof(Inst), hipHostMallocDefault);
+      if (he != hipSuccess) {
+        (void)hipFree(dv);
+        TM_HIP(he);
+      }
+      p->res_dev = static_cast<Inst*>(dv);
+      p->res_host = static_cast<Inst*>(hs);
+    }
     tm_plan_s::Resident e;
     e.pool = &pool;
     const size_t i = p->resident.size();
