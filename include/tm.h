@@ -203,7 +203,8 @@ tm_status tm_plan_get_info(tm_plan plan, tm_plan_info* info);
 tm_status tm_match(tm_plan plan, const void* x, tm_result* out, void* stream);
 
 /*
- * tm_match_batch -- `count` independent matches in one launch sequence
+ * tm_match_batch -- Algorithm 1 steps 3 and 5-9 applied per instance to
+ * `count` independent matches in one launch sequence
  * (uneven N and K allowed; plans may repeat).  plans[i] with xs[i] gives
  * out[i].  `out` points to count results in host or device memory (same rule
  * as tm_match).  The arrays plans and xs are host arrays read during the call.

@@ -300,6 +300,18 @@ def _check_signal(plan: Plan, x):
         raise TypeError("x dtype does not match the plan")
 
 
+def _check_out(out, count: int):
+    """`out` must be a contiguous CUDA uint8 tensor with room for `count`
+    48-byte results: the kernels write there without further checks."""
+    torch = _torch()
+    if not isinstance(out, torch.Tensor) or not out.is_cuda:
+        raise TypeError("out must be a CUDA (HIP) torch tensor")
+    if out.dtype != torch.uint8 or not out.is_contiguous():
+        raise TypeError("out must be a contiguous uint8 tensor")
+    if out.numel() < 48 * count:
+        raise ValueError("out holds %d bytes; %d results need %d" % (out.numel(), count, 48 * count))
+
+
 def match(plan: Plan, x, stream=None) -> MatchResult:
     """One match with a host result (waits for the stream)."""
     _check_signal(plan, x)
@@ -312,6 +324,9 @@ def match_into(plan: Plan, x, out, index: int = 0, stream=None):
     """One match writing a device result: `out` is a CUDA uint8 tensor of
     48*count bytes; nothing waits."""
     _check_signal(plan, x)
+    if index < 0:
+        raise ValueError("index must be >= 0")
+    _check_out(out, index + 1)
     st = (_LIB or lib()).tm_match(plan.handle, x.data_ptr(), out.data_ptr() + 48 * index,
                                   _stream_handle(stream))
     if st != TM_OK:
@@ -334,6 +349,7 @@ def match_batch(plans: Sequence[Plan], xs: Sequence, stream=None, out=None) -> O
     parr = (ctypes.c_void_p * count)(*[p.handle.value for p in plans])
     xarr = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
     if out is not None:
+        _check_out(out, count)
         _check(lib().tm_match_batch(count, parr, xarr, out.data_ptr(), _stream_handle(stream)))
         return None
     host = np.zeros(count, dtype=RESULT_DTYPE)
@@ -357,6 +373,7 @@ class Batch:
 
     def run(self, out, stream=None):
         """out: CUDA uint8 tensor of 48*count bytes (device results, no wait)."""
+        _check_out(out, self.count)
         _check(lib().tm_match_batch(self.count, self._p, self._x, out.data_ptr(),
                                     _stream_handle(stream)))
 
@@ -481,6 +498,7 @@ class Many:
 
     def run(self, out, stream=None):
         """out: CUDA uint8 tensor of 48*count bytes (device results, no wait)."""
+        _check_out(out, self.count)
         _check(lib().tm_match_many(self.plan.handle, self.count, self._x, out.data_ptr(),
                                    _stream_handle(stream)))
 

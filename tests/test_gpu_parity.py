@@ -233,3 +233,25 @@ def test_invalid_calls_leave_no_side_effects():
     assert st == tm.TM_ERR_INVALID
     st = tm.lib().tm_match(None, None, tm.ctypes.addressof(res), None)
     assert st == tm.TM_ERR_INVALID
+
+
+def test_result_buffer_is_checked_before_launch():
+    inst = G.config1(1)
+    plan = tm.Plan(inst.t, n=inst.n)
+    x = to_device(inst.x)
+    small = torch.zeros(48 * 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        tm.match_into(plan, x, small, 2)                 # slot past the end
+    with pytest.raises(ValueError):
+        tm.match_into(plan, x, small, -1)
+    with pytest.raises(TypeError):
+        tm.match_into(plan, x, torch.zeros(96, dtype=torch.int32, device="cuda"), 0)
+    with pytest.raises(TypeError):
+        tm.match_into(plan, x, torch.zeros(96, dtype=torch.uint8), 0)   # host tensor
+    with pytest.raises(ValueError):
+        tm.match_batch([plan] * 3, [x] * 3, out=small)
+    with pytest.raises(ValueError):
+        tm.Batch([plan] * 3, [x] * 3).run(small)
+    assert torch.count_nonzero(small).item() == 0        # nothing was written
+    tm.match_into(plan, x, small, 1)
+    assert tm.results_from_device(small)[1] == tm.match(plan, x)
