@@ -203,6 +203,26 @@ tm_status tm_plan_get_info(tm_plan plan, tm_plan_info* info);
 tm_status tm_match(tm_plan plan, const void* x, tm_result* out, void* stream);
 
 /*
+ * tm_match_noalloc -- tm_match for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops and harnesses that forbid
+ * allocation): the same kernels and the same result, bit for bit, with every
+ * intermediate in a device array of 16 MiB that the library holds on each
+ * GPU from the moment it is loaded until the process ends.  The call
+ * allocates nothing: no hipMalloc, no hipFree, no pool growth, no per-stream
+ * instance copy.
+ * plan: created beforehand on the current device (plan creation allocates);
+ *    its workspace (tm_plan_info.workspace_bytes) plus about 1 KiB must fit in
+ *    16 MiB, else TM_ERR_UNSUPPORTED.  Three-moduli plans: TM_ERR_UNSUPPORTED.
+ * x: as tm_match.  out: one tm_result in DEVICE memory (TM_ERR_INVALID for
+ *    host memory); valid once `stream` reaches this point.  Nothing waits.
+ * Every call on a GPU uses that GPU's one array, which keeps the previous
+ * call's contents (each call clears what must start at zero): calls that
+ * overlap on one GPU (on different streams or threads) race and give
+ * undefined results; calls in one stream's order do not.
+ */
+tm_status tm_match_noalloc(tm_plan plan, const void* x, tm_result* out, void* stream);
+
+/*
  * tm_match_batch -- Algorithm 1 steps 3 and 5-9 applied per instance to
  * `count` independent matches in one launch sequence
  * (uneven N and K allowed; plans may repeat).  plans[i] with xs[i] gives

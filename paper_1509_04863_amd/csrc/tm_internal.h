@@ -258,4 +258,13 @@ hipError_t launch_combine3(const Inst* tab, const Combine3* cmb, const tm_result
                            hipStream_t s);
 hipError_t launch_gfft(const Inst& host, const Inst* dev, hipStream_t s);   // literal folds .. result, one instance
 
+// Allocation-free single match: a device array of kScratchBytes per device
+// (tm_kernels.hip), its address on device `dev` (looked up by
+// configure_kernels), and the kernel that stores an instance record into it
+// and clears `nzero` ints of its bucket zone.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+void* scratch_device_ptr(int dev);
+hipError_t launch_noalloc_setup(const Inst& rec, Inst* dst, int* zero, int64_t nzero, hipStream_t s);
+
 }  // namespace tmi

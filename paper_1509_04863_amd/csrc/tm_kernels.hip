@@ -2640,6 +2640,35 @@ __global__ void __launch_bounds__(1024) k_spectrum(const void* t, int t_dtype, i
 }
 
 // --------------------------------------------------------------------------
+// device scratch of the allocation-free single match
+// --------------------------------------------------------------------------
+//
+// One array per device, allocated when the code object loads and kept until
+// the process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a stand-in, not a device address): the address that
+// hipGetSymbolAddress returns for the current device is kept per device when
+// the kernels are configured and handed to the kernels as an argument.
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// the instance record into scratch (one thread) and the bucket zone cleared
+// (a fill kernel rather than a memset, so a captured sequence holds no memset)
+__global__ void __launch_bounds__(256) k_noalloc_setup(Inst rec, Inst* dst, int* zero, int64_t nzero) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = rec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nzero; i += (int64_t)gridDim.x * blockDim.x)
+    G(zero)[i] = 0;
+}
+
+void* scratch_device_ptr(int dev) { return dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr; }
+
+hipError_t launch_noalloc_setup(const Inst& rec, Inst* dst, int* zero, int64_t nzero, hipStream_t s) {
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nzero + 255) / 256));
+  TM_LAUNCH(k_noalloc_setup, dim3(grid), dim3(256), 0, s, rec, dst, zero, nzero);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
 
@@ -2661,6 +2690,12 @@ hipError_t configure_kernels() {
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
       (void)hipGetLastError();
   }
+  // this device's copy of the scratch array (the device is current here)
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = ptr;
   return hipSuccess;
 }
 

@@ -1070,6 +1070,65 @@ tm_status tm_match_intermediates(tm_plan p, const void* x, tm_result* out, doubl
   return match_one(p, x, out, y1, y2, r1, r2, stream);
 }
 
+// tm_match without the per-stream pool: the instance record, the bucket zone
+// and the workspace live in the device's scratch array (layout: record, then
+// buckets, then workspace, each 256-byte aligned).  Host code uses only the
+// address configure_kernels looked up for the plan's device.
+tm_status tm_match_noalloc(tm_plan p, const void* x, tm_result* out, void* stream) {
+  tm_status st = check_plan_for_match(p);
+  if (st != TM_OK) return st;
+  if (p->core.three) return fail(TM_ERR_UNSUPPORTED, "tm_match_noalloc: three-moduli plans are not supported");
+  st = check_x(p, x);
+  if (st != TM_OK) return st;
+  if (!out) return fail(TM_ERR_INVALID, "null result pointer");
+  if (!is_device_pointer(out)) return fail(TM_ERR_INVALID, "tm_match_noalloc: out must be device memory");
+  int cur = -1;
+  TM_HIP(hipGetDevice(&cur));
+  if (cur != p->device) return fail(TM_ERR_INVALID, "tm_match_noalloc: the plan's device is not current");
+  char* scr = static_cast<char*>(scratch_device_ptr(p->device));
+  if (!scr) return fail(TM_ERR_DEVICE, "tm_match_noalloc: no scratch address for this device");
+  const Core& c = p->core;
+  const size_t off_acc = align256(sizeof(Inst));
+  const size_t off_ws = off_acc + align256(c.acc_bytes);
+  if (off_ws + c.ws_bytes > kScratchBytes)
+    return fail(TM_ERR_UNSUPPORTED, "tm_match_noalloc: the plan needs " + std::to_string(off_ws + c.ws_bytes) +
+                                        " bytes of scratch, above the " + std::to_string(kScratchBytes) +
+                                        "-byte maximum");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Inst one;
+  fill_inst(p, x, &one);
+  place_workspace(c, scr + off_ws, scr + off_acc, &one);
+  one.out = out;
+  Inst* dev_one = reinterpret_cast<Inst*>(scr);
+  // record and zeroed buckets (the previous call's contents are not trusted)
+  TM_HIP(launch_noalloc_setup(one, dev_one, reinterpret_cast<int*>(scr + off_acc), (int64_t)(c.acc_bytes / 4), s));
+  InstTable tab{};
+  tab.table = nullptr;
+  tab.count = 1;
+  tab.one = dev_one;
+  tab.x = one.x;
+  tab.out = one.out;
+  FoldWork fw;
+  fw.tiles = c.ntiles;
+  fw.lds = c.fold_lds;
+  fw.segs = c.nseg;
+  fw.bands = c.nband;
+  if (fw.tiles + fw.segs + fw.bands <= 0) return fail(TM_ERR_INVALID, "plan without fold work");
+  TM_HIP(folds(tab, fw, s));
+  TM_HIP(launch_reduce(tab, c.nred, s));
+  if (c.cgemm) {
+    const CgLaunch cl = cgemm_launch(2 * (int64_t)c.c_lp, 2 * (int64_t)c.c_lp, 1);
+    TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
+    TM_HIP(launch_cgemm_gemm(tab, nullptr, 1, c.c_rta + c.c_rtb, c.c_nlcap, s));
+    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
+  } else if (c.gfft) {
+    TM_HIP(launch_gfft(one, dev_one, s));
+  } else {
+    TM_HIP(launch_finish(tab, nullptr, 1, c.mode, c.p_log2, c.finish_lds, s));
+  }
+  return TM_OK;
+}
+
 // One launch sequence for `count` instances.  Without `cmb` the results go
 // to out[0..count); with it the instances are the expanded list of a batch
 // with three-moduli plans: their results stay in device scratch and one

@@ -27,7 +27,7 @@ EXPORTS = ["tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_i
            "tm_match_batch", "tm_match_intermediates", "tm_status_string", "tm_last_error",
            "tm_version", "tm_profile_enable", "tm_profile_read", "tm_server_create", "tm_server_submit",
            "tm_server_poll", "tm_server_wait", "tm_server_get_stats", "tm_server_destroy",
-           "tm_admit_batches", "tm_match_many", "tm_profile_read_corr"]
+           "tm_admit_batches", "tm_match_many", "tm_profile_read_corr", "tm_match_noalloc"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -120,6 +120,8 @@ def lib():
         L.tm_admit_batches.argtypes = [i32, i64p, ctypes.c_int64, i32, ctypes.POINTER(i32)]
         L.tm_match_many.argtypes = [vp, i32, ctypes.POINTER(vp), vp, vp]
         L.tm_match_many.restype = ctypes.c_int
+        L.tm_match_noalloc.argtypes = [vp, vp, vp, vp]
+        L.tm_match_noalloc.restype = ctypes.c_int
         for fn in ("tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_wait",
                    "tm_server_get_stats", "tm_server_destroy", "tm_admit_batches"):
             getattr(L, fn).restype = ctypes.c_int
@@ -331,6 +333,18 @@ def match_into(plan: Plan, x, out, index: int = 0, stream=None):
                                   _stream_handle(stream))
     if st != TM_OK:
         _check(st)
+
+
+def match_noalloc(plan: Plan, x, out, index: int = 0, stream=None):
+    """tm_match_noalloc: one match that allocates no device memory, writing
+    its result into slot `index` of `out` (a CUDA uint8 tensor); nothing
+    waits.  Calls that overlap on one GPU race (one scratch array per GPU)."""
+    _check_signal(plan, x)
+    if index < 0:
+        raise ValueError("index must be >= 0")
+    _check_out(out, index + 1)
+    _check(lib().tm_match_noalloc(plan.handle, x.data_ptr(), out.data_ptr() + 48 * index,
+                                  _stream_handle(stream)))
 
 
 def results_from_device(out) -> List[MatchResult]:
