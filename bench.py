@@ -1,26 +1,29 @@
 """Benchmark of the MI355X template matcher.
 
-Default workload (config2): one large instance per step (N = 2^22 +-1 values
-stored as fp32, K = 4096, 10% template sign flips, M1 = 4096, M2 = 4097), one
-match per launch sequence, sequences issued round-robin over a few streams,
-inputs resident in HBM and rotated over >= 1 GiB of distinct signals so the
-256 MB memory-side cache does not serve them.  Other workloads: config1
-(N = 2^16 int8), config3 (4096 uneven int8 instances per launch), config4
-(request server: open-loop p50/p99 and saturation vs plain launch), config5b
-(1024 signals sharing one template: int8 MFMA GEMM vs the FFT path).
+Default workload (config3): 4096 independent int8 +-1 instances of uneven
+size (N = 2^U(16,20), K = 2^U(9,12), flips U[5%, 15%]), one tm_match_batch
+per step, 1.45 GB of signals resident in HBM (every step reads all of them,
+more than the 256 MB memory-side cache holds).  Other workloads: config1
+(N = 2^16 int8, one match per launch), config2 (N = 2^22 +-1 stored fp32, one
+match per launch), config4 (request server: open-loop p50/p99 at the offered
+rate and saturation vs plain launch), config5a (N = 2^24 fp32, K = 2^14 at
+-3 dB with FP32/BF16/FP16 fold storage, error against FP64), config5b (1024
+signals sharing one template: int8 MFMA GEMM vs the FFT path).
 
-Prints one JSON line: whole-job matches/s; the roofline of the dominant
-kernel, the fold (HBM bytes against 8 TB/s) or the correlation (int8 matrix
-product: 2 K (M1 + M2) operations per match against 5 POP/s; FFT finish: its
-FFT flops against the FP64 or FP32 vector peak), both timed by HIP events
-carried on the kernels' own dispatches in a separate single-stream run, the
-other one reported beside it; and the CPU oracle timed on a bounded sample of
-the same workload.  Single-match warmup runs every rotated signal's plan once
-on each stream the timed region uses it on: a plan's first match on a stream
-uploads its device copy of the instance.
+Prints one JSON line: whole-job matches/s over the timed steps; per-step
+times (HIP events on the launch stream); `roofline` for the dominant kernel
+and `roofline_other` for the next one, each from HIP events carried on the
+kernels' own dispatches during the timed region: the fold against 8 TB/s with
+its algorithmic bytes (x read once), the correlation with the method's FFT
+flops (10 P log2 P + 6 P per instance) against the FP32 vector peak whatever
+route computed it (the int8 product's own executed operations are reported
+beside); `serving` (default run: a short request-server sample of the serving
+workload); and `cpu_baseline`, the oracle's FP64 FFT path timed on host cores
+on a bounded sample of the same workload, compared with the GPU's results.
 """
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -34,36 +37,63 @@ HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0      # dense int8 MFMA
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+METRIC = "template matches/sec + fold GB/s vs HBM peak; served p50/p99 vs plain launch"
+KERNELS_SRC = os.path.join(ROOT, "paper_1509_04863_amd", "csrc", "tm_kernels.hip")
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a
-# plain copy's readings (profiles/hbm_traffic_config2_config3.txt): the fold
-# kernel (key = workload) and the int8 correlation kernel (workload + "_corr"),
-# valid for the kernels as those counters saw them
-TRAFFIC_BYTES = {"config2": 1.828e7, "config3": 1.561e9, "config2_corr": 8.602e5, "config3_corr": 7.52e8}
+# HBM bytes per launch (FETCH_SIZE + WRITE_SIZE from rocprofv3 --pmc, each
+# scaled by a plain copy's reading; summaries under profiles/), valid only for
+# the kernel source they were taken on: `traffic` is null for any other.
+TRAFFIC_SRC_SHA = ""
+TRAFFIC_BYTES = {}
 
 
-def corr_roofline(plans, corr_ms, corr_n, traffic=None):
-    """The correlation kernel's roofline from its average launch time: the
-    int8 matrix product against the int8 MFMA peak (algorithmic operations
-    2 K (M1 + M2) per match), or the FFT finish against the vector peak of its
-    precision (2 transforms of 5 P log2 P flops plus 6 P per match)."""
-    avg_s = corr_ms / corr_n / 1e3
-    info = plans[0].info
-    if info["corr_gemm"]:
-        ops = sum(2.0 * p.k * (p.m1 + p.m2) for p in plans)
-        achieved = ops / avg_s / 1e12
-        return {"kernel": "k_cgemm", "bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                "unit": "TOP/s", "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic,
-                "avg_kernel_us": avg_s * 1e6, "algorithmic_ops_per_launch": ops}
-    flops = 0.0
+def kernels_sha() -> str:
+    with open(KERNELS_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(key):
+    if not TRAFFIC_SRC_SHA or kernels_sha() != TRAFFIC_SRC_SHA:
+        return None
+    return TRAFFIC_BYTES.get(key)
+
+
+def fft_flops(plans):
+    """The method's correlation work (steps 4-6): one complex transform of
+    length P each way per instance, 10 P log2 P + 6 P flops."""
+    total = 0.0
     for p in plans:
         P = 1 << p.info["fft_log2"]
-        flops += 10.0 * P * math.log2(P) + 6.0 * P
-    peak = FP64_PEAK_TFLOPS if info["exact"] else FP32_PEAK_TFLOPS
+        total += 10.0 * P * math.log2(P) + 6.0 * P
+    return total
+
+
+def corr_roofline(plans, corr_ms, corr_n, traffic=None, name=None):
+    """The correlation kernel against the method's FFT work: the FFT flops of
+    the instances of one launch over its average duration, against the FP32
+    vector peak (the precision the method's transform needs for real data).
+    For the int8 product route the executed MFMA operations (2 K (M1 + M2)
+    per instance and digit) are reported beside it."""
+    avg_s = corr_ms / corr_n / 1e3
+    info = plans[0].info
+    flops = fft_flops(plans)
     achieved = flops / avg_s / 1e12
-    return {"kernel": "k_finish", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic, "avg_kernel_us": avg_s * 1e6,
-            "algorithmic_flops_per_launch": flops}
+    out = {"kernel": name or ("k_cgemm" if info["corr_gemm"] else "k_finish"), "bound": "alu",
+           "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+           "traffic": traffic, "avg_kernel_us": avg_s * 1e6, "algorithmic_flops_per_launch": flops}
+    if info["corr_gemm"]:
+        ops = sum(2.0 * p.k * (p.m1 + p.m2) for p in plans)
+        out["mfma_int8_ops_per_launch_one_digit"] = ops
+        out["mfma_int8_tops_one_digit"] = ops / avg_s / 1e12
+    return out
+
+
+def fold_roofline(kernel, fold_ms, fold_n, x_bytes, traffic=None):
+    avg_s = fold_ms / fold_n / 1e3
+    achieved = x_bytes / avg_s / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_kernel_us": avg_s * 1e6,
+            "algorithmic_bytes_per_launch": x_bytes}
 
 
 def pick_roofline(line, fold_roof, corr_roof):
@@ -81,23 +111,27 @@ def pick_roofline(line, fold_roof, corr_roof):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config5b", "copy"])
-    ap.add_argument("--pool", type=int, default=96, help="device signals in the config4 pool")
-    ap.add_argument("--templates", type=int, default=384, help="distinct config4 requests (plans)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 batches for config3, 2000 matches for config1/2)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="config3",
+                    choices=["config1", "config2", "config3", "config4", "config5a", "config5b", "copy"])
+    ap.add_argument("--pool", type=int, default=1024, help="device signals in the config4 pool")
+    ap.add_argument("--templates", type=int, default=2048, help="distinct config4 requests (plans)")
     ap.add_argument("--rate", type=float, default=20000.0, help="config4 offered load, requests/s")
-    ap.add_argument("--duration", type=float, default=2.0, help="config4 open-loop seconds")
+    ap.add_argument("--duration", type=float, default=10.0, help="config4 open-loop seconds")
     ap.add_argument("--batch", type=int, default=4096, help="instances per step for config3")
     ap.add_argument("--rotate-mib", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0: the host cores, at most 16)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="skip the fold-kernel event timing")
+    ap.add_argument("--no-serving", action="store_true", help="config3: skip the serving sample")
+    ap.add_argument("--no-profile", action="store_true", help="no kernel timing events")
     ap.add_argument("--streams", type=int, default=4, help="streams for single-match launch sequences")
-    ap.add_argument("--traffic-bytes", type=float, default=None,
-                    help="HBM bytes per fold launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 2000 if args.config in ("config1", "config2") else 20
+    return args
 
 
 def workload(name):
@@ -110,9 +144,17 @@ def workload(name):
                 desc="N=65536 +-1 int8, K=1024, 5% flips, M1=K")
 
 
-def run_batched(args):
-    """config3: every step is one tm_match_batch over the whole uneven batch."""
+def _step_stats(ms):
     import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    return {"windows": int(a.size), "median_ms": float(np.median(a)), "min_ms": float(a.min()),
+            "max_ms": float(a.max())}
+
+
+def run_batched(args):
+    """config3: every step is one tm_match_batch over the whole uneven batch;
+    the fold and correlation kernels carry timing events during the timed
+    steps themselves."""
     import torch
 
     from paper_1509_04863_amd import datagen as G
@@ -124,64 +166,75 @@ def run_batched(args):
     batch = tm.Batch(plans, xs)
     out = torch.zeros(48 * len(insts), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    profile = not args.no_profile
+    # warmup with the timing events on as well, for as many steps as are
+    # timed: every event the timed steps use is created here and reused
+    tm.profile_enable(profile)
+    for _ in range(max(1, args.warmup, args.steps if profile else 0)):
         batch.run(out, stream)
     torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(args.steps):
-        batch.run(out, stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    fold_ms, fold_n, corr_ms, corr_n = 0.0, 0, 0.0, 0
-    if not args.no_profile:
+    tm.profile_enable(False)
+    if profile:
         tm.profile_read(reset=True)
         tm.profile_read_corr(reset=True)
         tm.profile_enable(True)
-        for _ in range(args.steps):
-            batch.run(out, stream)
-        torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    for i in range(args.steps):
+        batch.run(out, stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    if profile:
         tm.profile_enable(False)
-        fold_ms, fold_n = tm.profile_read(reset=True)
-        corr_ms, corr_n = tm.profile_read_corr(reset=True)
+    total_ms = ev[0].elapsed_time(ev[-1])
+    steps_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    fold_ms, fold_n = tm.profile_read(reset=True) if profile else (0.0, 0)
+    corr_ms, corr_n = tm.profile_read_corr(reset=True) if profile else (0.0, 0)
     results = tm.results_from_device(out)
     x_bytes = sum(s.x.nbytes for s in insts)
+    t_bytes = sum(s.t.nbytes for s in insts)
     ms_per_step = total_ms / args.steps
+    exact_gemm = all(p.info["corr_gemm"] for p in plans)
     line = {
-        "metric": "template matches/sec + fold GB/s vs HBM peak; served p50/p99 vs plain launch",
+        "metric": METRIC,
         "value": len(insts) * args.steps / (total_ms / 1e3), "unit": "matches/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "i32 fold, i8 MFMA correlation (exact)" if all(p.info["corr_gemm"] for p in plans)
-        else "i32 fold, f64 fft", "data": "synthetic",
+        "dtype": "i8 in, i32 fold, i8 MFMA correlation (i32/i64 sums)" if exact_gemm else "i8 in, i32 fold, f64 fft",
+        "data": "synthetic",
         "config": {"workload": "config3: %d uneven int8 +-1 instances, N=2^U(16,20), K=2^U(9,12), "
-                               "flips U[5%%,15%%], one batch per step" % len(insts),
-                   "instances": len(insts), "batch_x_bytes": x_bytes},
+                               "flips U[5%%,15%%], one tm_match_batch per step" % len(insts),
+                   "instances": len(insts), "batch_x_bytes": x_bytes, "batch_t_bytes": t_bytes,
+                   "timed_bytes": args.steps * x_bytes, "kernel_timing": "events on the timed steps' dispatches"},
+        "step_times": _step_stats(steps_ms),
+        "path_roofline": {"bound": "hbm", "achieved": (x_bytes + t_bytes) / (ms_per_step / 1e3) / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": (x_bytes + t_bytes) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+                          "algorithmic_bytes_per_step": x_bytes + t_bytes},
         "planted_recovered": "%d/%d" % (sum(int(r.shift == s.shift) for r, s in zip(results, insts)),
                                         len(insts)),
     }
     fold_roof = corr_roof = None
     if fold_n:
-        avg_s = fold_ms / fold_n / 1e3
-        achieved = x_bytes / avg_s / 1e9
-        fold_roof = {"kernel": "k_fold_s8", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": args.traffic_bytes if args.traffic_bytes is not None
-                     else TRAFFIC_BYTES.get("config3"),
-                     "avg_kernel_us": avg_s * 1e6, "algorithmic_bytes_per_launch": x_bytes}
+        fold_roof = fold_roofline("k_fold_s8", fold_ms, fold_n, x_bytes, traffic_for("k_fold_s8/config3"))
     if corr_n:
-        corr_roof = corr_roofline(plans, corr_ms, corr_n, TRAFFIC_BYTES.get("config3_corr"))
+        corr_roof = corr_roofline(plans, corr_ms, corr_n, traffic_for("corr/config3"))
     pick_roofline(line, fold_roof, corr_roof)
+    del batch, xs
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        line["serving"] = serving_sample(pool_size=160, templates=320, rate=args.rate, duration=2.0)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(lambda i: insts[i], args.cpu_seconds, results)
+        line["cpu_baseline"] = cpu_baseline_pool("config3", args.cpu_seconds, results, args.cpu_workers)
     print(json.dumps(line), flush=True)
 
 
-def run_serving(args):
-    """config4: open-loop Poisson arrivals into the request server (p50/p99
-    latency), then closed-loop saturation throughput of the server and of the
-    plain path (one synchronous tm_match per request)."""
+def serving_sample(pool_size, templates, rate, duration, plain_rounds=3):
+    """The serving workload through the request server: open-loop Poisson
+    arrivals at `rate` for `duration` seconds (p50/p99 latency from
+    submission to result), then closed-loop saturation throughput of the
+    server and of the plain path (one synchronous tm_match per request), and
+    whether every served result equals the plain one."""
     import threading
 
     import numpy as np
@@ -190,18 +243,16 @@ def run_serving(args):
     from paper_1509_04863_amd import datagen as G
     from paper_1509_04863_amd import tm
 
-    pool = G.config4_pool(args.pool)
+    pool = G.config4_pool(pool_size)
     xs = [torch.from_numpy(s.x).cuda() for s in pool]
-    reqs = G.config4_requests(pool, args.templates, rate_hz=args.rate)
+    reqs = G.config4_requests(pool, templates, rate_hz=rate)
     plans = [tm.Plan(r.t, n=pool[r.pool_id].n, x_dtype=tm.tm_dtype_of(pool[r.pool_id].x)) for r in reqs]
     req_x = [xs[r.pool_id] for r in reqs]
     torch.cuda.synchronize()
     nreq = len(reqs)
-
-    # open loop at the offered rate
     rng = np.random.default_rng(7)
-    count = max(1, int(args.rate * args.duration))
-    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=count))
+    count = max(1, int(rate * duration))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
     lat = np.zeros(count)
     with tm.Server(budget_bytes=2 << 30, max_batch=512, max_inflight=3) as srv:
         for i in range(min(64, nreq)):                      # warm-up
@@ -226,45 +277,133 @@ def run_serving(args):
         th.join()
         open_s = time.perf_counter() - t0
         open_stats = srv.stats()
-
         # closed loop: the whole request set queued at once, several rounds
-        rounds = 20
+        rounds = 10
         t0 = time.perf_counter()
         ts = [srv.submit(plans[i % nreq], req_x[i % nreq]) for i in range(rounds * nreq)]
         served = [srv.wait(t)[0] for t in ts]
         served_s = time.perf_counter() - t0
-    # plain path on the same requests
+        held = srv.stats()
     for i in range(min(16, nreq)):
         tm.match(plans[i], req_x[i])
     t0 = time.perf_counter()
     plain = [tm.match(plans[i], req_x[i]) for i in range(nreq)]
-    for _ in range(2):
+    for _ in range(plain_rounds - 1):
         for i in range(nreq):
             tm.match(plans[i], req_x[i])
-    plain_s = (time.perf_counter() - t0) / 3
+    plain_s = (time.perf_counter() - t0) / plain_rounds
     same = sum(int(a == b) for a, b in zip(served[:nreq], plain))
-    recovered = sum(int(r.shift == q.shift) for r, q in zip(plain, reqs))
     served_rate = rounds * nreq / served_s
     plain_rate = nreq / plain_s
     lat_ms = lat / 1e6
+    return {"workload": "config4: Poisson %.0f req/s for %.1f s over %d distinct requests on a pool of %d "
+                        "signals (N=2^U(14,24), 70%% int8 +-1 / 30%% fp32 N(0,1)), K=2^U(8,13), templates at 0 dB"
+                        % (rate, duration, nreq, len(pool)),
+            "pool_bytes": int(sum(s.x.nbytes for s in pool)),
+            "offered_rate": rate, "open_loop_requests": count, "open_loop_s": open_s,
+            "achieved_open_rate": count / open_s,
+            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "mean_batch": open_stats["completed"] / max(1, open_stats["batches"]),
+            "served_matches_per_s": served_rate, "plain_matches_per_s": plain_rate,
+            "served_vs_plain": served_rate / plain_rate,
+            "served_equals_plain": "%d/%d" % (same, nreq),
+            "server_peak_inflight_bytes": held["peak_inflight_bytes"],
+            "planted_recovered": "%d/%d" % (sum(int(r.shift == q.shift) for r, q in zip(plain, reqs)), nreq)}
+
+
+def run_serving(args):
+    """config4 at its stated shape: the request server under open-loop
+    Poisson arrivals, then saturation against the plain path."""
+    sv = serving_sample(pool_size=args.pool, templates=args.templates, rate=args.rate, duration=args.duration)
     line = {
-        "metric": "template matches/sec + fold GB/s vs HBM peak; served p50/p99 vs plain launch",
-        "value": served_rate, "unit": "matches/s", "n_gpus": 1, "steps": rounds, "warmup": 1,
-        "ms_per_step": served_s / rounds * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "i32 fold + f32 fft (real templates)", "data": "synthetic",
-        "config": {"workload": "config4: serving, %d distinct requests over a pool of %d signals "
-                               "(N=2^U(14,24), 70%% int8 +-1 / 30%% fp32 N(0,1)), K=2^U(8,13), "
-                               "templates at 0 dB" % (nreq, len(pool)),
-                   "pool_bytes": int(sum(s.x.nbytes for s in pool))},
-        "serving": {"offered_rate": args.rate, "open_loop_requests": count, "open_loop_s": open_s,
-                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-                    "mean_batch": open_stats["completed"] / max(1, open_stats["batches"]),
-                    "served_matches_per_s": served_rate, "plain_matches_per_s": plain_rate,
-                    "served_vs_plain": served_rate / plain_rate,
-                    "served_equals_plain": "%d/%d" % (same, nreq)},
-        "planted_recovered": "%d/%d" % (recovered, nreq),
+        "metric": METRIC, "value": sv["served_matches_per_s"], "unit": "matches/s", "n_gpus": 1,
+        "steps": 10, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32 fold (int8 signals), f32 fold (fp32 signals), f32 fft", "data": "synthetic",
+        "config": {"workload": sv["workload"], "pool_bytes": sv["pool_bytes"]},
+        "serving": sv,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_precision(args):
+    """config5a: one N = 2^24 fp32 N(0,1) signal per match, K = 2^14 at -3 dB,
+    for each fold storage (FP32, BF16, FP16): matches/s over signals rotated
+    beyond 1 GiB, the fold kernel's HBM rate, and against the oracle's FP64
+    correlation the normwise error of r and the argmax agreement."""
+    import numpy as np
+    import torch
+
+    from paper_1509_04863_amd import datagen as G
+    from paper_1509_04863_amd import tm
+
+    rot = max(1, min(32, math.ceil(args.rotate_mib * 2 ** 20 / (4 << 24))))
+    insts = [G.config5a(i) for i in range(rot)]
+    xs = [torch.from_numpy(s.x).cuda() for s in insts]
+    x_bytes = insts[0].x.nbytes
+    stream = torch.cuda.current_stream()
+    stores = {"f32": tm.TM_F32, "bf16": tm.TM_BF16, "f16": tm.TM_F16}
+    per = {}
+    for name, st in stores.items():
+        plans = [tm.Plan(s.t, n=s.n, fold_store=st) for s in insts]
+        out = torch.zeros(48 * rot, dtype=torch.uint8, device="cuda")
+        for i in range(max(args.warmup, rot)):
+            tm.match_into(plans[i % rot], xs[i % rot], out, i % rot, stream)
+        torch.cuda.synchronize()
+        tm.profile_read(reset=True)
+        tm.profile_read_corr(reset=True)
+        tm.profile_enable(not args.no_profile)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for i in range(args.steps):
+            tm.match_into(plans[i % rot], xs[i % rot], out, i % rot, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        tm.profile_enable(False)
+        ms = a.elapsed_time(b)
+        fold_ms, fold_n = tm.profile_read(reset=True)
+        entry = {"matches_per_s": args.steps / (ms / 1e3), "ms_per_match": ms / args.steps,
+                 "timed_signals": min(args.steps, rot), "timed_bytes": min(args.steps, rot) * x_bytes}
+        if fold_n:
+            entry["fold"] = fold_roofline("k_fold_band", fold_ms, fold_n, x_bytes)
+        if not args.no_cpu:
+            entry.update(cpu_precision_leg(plans, xs, insts, 2))
+        per[name] = entry
+        del plans
+    f32 = per["f32"]
+    line = {
+        "metric": METRIC, "value": f32["matches_per_s"], "unit": "matches/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": f32["ms_per_match"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (fold storage f32; bf16 and f16 beside)",
+        "data": "synthetic",
+        "config": {"workload": "config5a: N=2^24 fp32 N(0,1), K=2^14, template at -3 dB, one match per launch",
+                   "signals_rotated": rot, "rotated_bytes": rot * x_bytes},
+        "storage": per,
+    }
+    if "fold" in f32:
+        line["roofline"] = f32["fold"]
+    print(json.dumps(line), flush=True)
+
+
+def cpu_precision_leg(plans, xs, insts, count):
+    """The oracle's FP64 path on the first `count` signals of the precision
+    workload (timed at one core), against the GPU's intermediates through the
+    C ABI: normwise error of r and agreement of the argmaxes and the shift."""
+    import numpy as np
+
+    from oracle import ftm as O
+    from paper_1509_04863_amd import tm
+    errs, agree, busy = [], 0, 0.0
+    for i in range(min(count, len(plans))):
+        res, y1, y2, r1, r2 = tm.match_intermediates(plans[i], xs[i])
+        t0 = time.perf_counter()
+        ref = O.ftm(insts[i].x.astype(np.float64), insts[i].t.astype(np.float64), plans[i].m1, plans[i].m2,
+                    correlation="fft")
+        busy += time.perf_counter() - t0
+        errs.append(max(float(np.max(np.abs(r1 - ref.r1)) / np.max(np.abs(ref.r1))),
+                        float(np.max(np.abs(r2 - ref.r2)) / np.max(np.abs(ref.r2)))))
+        agree += int((res.m1_tilde, res.m2_tilde, res.shift) == (ref.m1_tilde, ref.m2_tilde, ref.shift))
+    return {"normwise_r_error_vs_fp64": errs, "argmax_and_shift_agree_with_fp64": "%d/%d" % (agree, len(errs)),
+            "oracle_matches_per_s_one_core": len(errs) / busy if busy > 0 else None}
 
 
 def run_shared(args):
@@ -326,28 +465,69 @@ def run_shared(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(make, budget_s, gpu_results):
-    """The oracle as it stands, on instances of the same workload, for about
-    budget_s seconds of single-threaded CPU work."""
+def _oracle_make(name):
+    from paper_1509_04863_amd import datagen as G
+    return {"config1": lambda i: G.config1(i, 1), "config2": G.config2, "config3": G.config3}[name]
+
+
+def _oracle_worker(job):
+    """One oracle process: instances wid, wid + stride, ... of the named
+    workload through the oracle's FP64 FFT path (steps 2-9) until `budget_s`
+    seconds of oracle time or `limit`; generating an instance is not timed."""
+    name, wid, stride, budget_s, limit = job
     from oracle import ftm as O
-    done, t0, agree = 0, time.perf_counter(), 0
-    elapsed = 0.0
-    while elapsed < budget_s or done == 0:
-        inst = make(done)
+    make = _oracle_make(name)
+    busy, done, i = 0.0, [], wid
+    while i < limit and (busy < budget_s or not done):
+        inst = make(i)
         m1, m2 = O.choose_moduli(inst.n, inst.k)
-        s = time.perf_counter()
-        ref = O.ftm(inst.x, inst.t, m1, m2)
-        elapsed += time.perf_counter() - s
-        if done < len(gpu_results):
-            g = gpu_results[done]
-            agree += int(g.shift == ref.shift and g.m1_tilde == ref.m1_tilde and g.m2_tilde == ref.m2_tilde)
-        done += 1
-        if time.perf_counter() - t0 > 4 * budget_s + 60:
-            break
-    return {"value": done / elapsed, "unit": "matches/s", "cores": 1, "kind": "oracle",
-            "sample": "%d instances of the same workload (fresh seeds 0..%d), oracle steps 2-9 with "
-                      "direct O(MK) correlation, %.1f s" % (done, done - 1, elapsed),
-            "gpu_agrees_on": "%d/%d" % (agree, min(done, len(gpu_results)))}
+        t0 = time.perf_counter()
+        ref = O.ftm(inst.x, inst.t, m1, m2, correlation="fft")
+        busy += time.perf_counter() - t0
+        done.append((i, int(ref.shift), int(ref.m1_tilde), int(ref.m2_tilde)))
+        i += stride
+    return busy, done
+
+
+def _agreement(done, gpu_results):
+    agree = checked = 0
+    for i, shift, m1t, m2t in done:
+        if i < len(gpu_results):
+            g = gpu_results[i]
+            checked += 1
+            agree += int((g.shift, g.m1_tilde, g.m2_tilde) == (shift, m1t, m2t))
+    return "%d/%d" % (agree, checked)
+
+
+def cpu_baseline_pool(name, budget_s, gpu_results, workers=0):
+    """The oracle's vectorised path (fold, FP64 numpy FFT correlation, argmax,
+    resolve) on the batch's own instances, spread over the host cores in
+    separate processes; the rate is the sum of the processes' rates."""
+    import concurrent.futures
+    import multiprocessing
+    cores = workers or min(16, len(os.sched_getaffinity(0)))
+    ctx = multiprocessing.get_context("spawn")      # fresh interpreters: nothing of the GPU process
+    jobs = [(name, w, cores, budget_s, len(gpu_results)) for w in range(cores)]
+    t0 = time.perf_counter()
+    with concurrent.futures.ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
+        parts = list(ex.map(_oracle_worker, jobs))
+    wall = time.perf_counter() - t0
+    done = [d for _, ds in parts for d in ds]
+    rate = sum(len(ds) / b for b, ds in parts if b > 0)
+    return {"value": rate, "unit": "matches/s", "cores": cores, "kind": "oracle",
+            "sample": "%d instances of the timed batch (indices strided over %d processes), oracle steps 2-9 "
+                      "with the FP64 numpy FFT correlation, %.1f s of oracle time per process at most "
+                      "(%.1f s wall); instance generation not timed" % (len(done), cores, budget_s, wall),
+            "gpu_agrees_on": _agreement(done, gpu_results)}
+
+
+def cpu_baseline_single(name, budget_s, gpu_results):
+    """Single-instance workloads: the oracle's FFT path at one core."""
+    busy, done = _oracle_worker((name, 0, 1, budget_s, 1 << 30))
+    return {"value": len(done) / busy, "unit": "matches/s", "cores": 1, "kind": "oracle",
+            "sample": "%d instances of the same workload (seeds 0..%d), oracle steps 2-9 with the FP64 numpy "
+                      "FFT correlation, %.1f s" % (len(done), len(done) - 1, busy),
+            "gpu_agrees_on": _agreement(done, gpu_results)}
 
 
 def main():
@@ -383,6 +563,9 @@ def main():
         return
     if args.config == "config4":
         run_serving(args)
+        return
+    if args.config == "config5a":
+        run_precision(args)
         return
     if args.config == "config5b":
         run_shared(args)
@@ -453,8 +636,9 @@ def main():
     value = args.steps / (total_ms / 1e3)
     info = plans[0].info
     p_len = 1 << info["fft_log2"]
+    timed_signals = min(args.steps, rot)
     line = {
-        "metric": "template matches/sec + fold GB/s vs HBM peak; served p50/p99 vs plain launch",
+        "metric": METRIC,
         "value": value, "unit": "matches/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
@@ -464,26 +648,23 @@ def main():
         "config": {"workload": args.config + ": " + wl["desc"], "n": first.n, "k": first.k,
                    "m1": info["m1"], "m2": info["m2"], "fft_len": p_len,
                    "x_dtype": str(first.x.dtype), "signals_rotated": rot,
-                   "rotated_bytes": rot * x_bytes, "streams": len(streams), "warmup_matches": warm_matches,
+                   "timed_signals": timed_signals, "timed_distinct_bytes": timed_signals * x_bytes,
+                   "streams": len(streams), "warmup_matches": warm_matches,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "fold_kernel": "k_fold_band" if info["fold_bands"] else
-                                  ("k_fold_s8" if info["fold_segments"] else "k_fold")},
+                                  ("k_fold_s8" if info["fold_segments"] else "k_fold"),
+                   "kernel_timing": "events on the dispatches of a single-stream pass after the timed region"},
         "planted_recovered": "%d/%d" % (planted_ok, rot),
     }
     fold_roof = corr_roof = None
     if fold_n:
-        avg_s = fold_ms / fold_n / 1e3
-        achieved = x_bytes / avg_s / 1e9
-        fold_roof = {"kernel": line["config"]["fold_kernel"], "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": args.traffic_bytes if args.traffic_bytes is not None
-                     else TRAFFIC_BYTES.get(args.config), "avg_kernel_us": avg_s * 1e6,
-                     "algorithmic_bytes_per_launch": x_bytes}
+        fold_roof = fold_roofline(line["config"]["fold_kernel"], fold_ms, fold_n, x_bytes,
+                                  traffic_for(line["config"]["fold_kernel"] + "/" + args.config))
     if corr_n:
-        corr_roof = corr_roofline([plans[0]], corr_ms, corr_n, TRAFFIC_BYTES.get(args.config + "_corr"))
+        corr_roof = corr_roofline([plans[0]], corr_ms, corr_n, traffic_for("corr/" + args.config))
     pick_roofline(line, fold_roof, corr_roof)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wl["make"], args.cpu_seconds, results)
+        line["cpu_baseline"] = cpu_baseline_single(args.config, args.cpu_seconds, results)
     print(json.dumps(line), flush=True)
 
 

@@ -276,8 +276,12 @@ tm_status tm_profile_read_corr(double* ms_total, int64_t* launches, int reset);
  * max_batch requests; up to max_inflight batches run on the device at once,
  * each on its own stream, so requests that arrive while others run are
  * launched as soon as a slot is free.  A request is admitted while the device
- * workspace (tm_plan_info.workspace_bytes + 48 bytes) of all batches in flight
- * stays within budget_bytes; a single request above the budget runs alone.
+ * workspace (tm_plan_info.workspace_bytes plus about 0.5 KiB of result slot and
+ * instance record) of all batches in flight stays within budget_bytes, and a
+ * batch is launched only while the device memory all the server's streams
+ * hold (each grows to exactly what its batches need; idle ones give theirs
+ * back first) stays within it too; a single request above the budget runs
+ * alone.  tm_server_destroy frees all of it.
  * Every result equals the one tm_match returns for the same plan and signal.
  * Plans (templates, spectra and twiddles) stay on the device; the caller keeps
  * each plan and signal valid until its result has been taken.
@@ -293,6 +297,8 @@ typedef struct {
 typedef struct {
   int64_t submitted, completed, failed, batches;
   int64_t peak_inflight_bytes;   /* largest admitted workspace in flight */
+  int64_t peak_held_bytes;       /* largest device memory the server's streams held at a
+                                    launch: at most max(budget_bytes, the largest request) */
 } tm_server_stats;
 
 /* Creates the streams, pinned result buffers and worker thread on the current

@@ -258,6 +258,14 @@ hipError_t launch_combine3(const Inst* tab, const Combine3* cmb, const tm_result
                            hipStream_t s);
 hipError_t launch_gfft(const Inst& host, const Inst* dev, hipStream_t s);   // literal folds .. result, one instance
 
+// Per-stream workspace pools (tm_runtime.cpp), for the request server's own
+// streams: grow to exactly what a launch needs, report the device bytes a
+// stream's pool holds, and free them (after the stream drains; keep_entry
+// keeps the stream's settings for later launches).
+void stream_pool_set_exact(int dev, hipStream_t s);
+size_t stream_pool_device_bytes(int dev, hipStream_t s);
+hipError_t stream_pool_release(int dev, hipStream_t s, bool keep_entry);
+
 // Allocation-free single match: a device array of kScratchBytes per device
 // (tm_kernels.hip), its address on device `dev` (looked up by
 // configure_kernels), and the kernel that stores an instance record into it

@@ -393,6 +393,7 @@ struct StreamPool {
   void* acc = nullptr;           // integer bucket zone: all zero between launches
   size_t acc_cap = 0;
   bool acc_dirty = false;        // a launch sequence broke off after its fold
+  bool exact_growth = false;     // grow to exactly what a launch needs (request server streams)
   // two pinned staging buffers for descriptor tables, used in turn: the host
   // fills one while the copy out of the other may still be in flight
   void* host[2] = {nullptr, nullptr};
@@ -496,7 +497,7 @@ tm_status ensure_device(StreamPool& p, size_t need, hipStream_t s) {
     p.dev = nullptr;
     p.cap = 0;
   }
-  const size_t cap = align256(need + need / 4);
+  const size_t cap = align256(p.exact_growth ? need : need + need / 4);
   TM_HIP(hipMalloc(&p.dev, cap));
   p.cap = cap;
   return TM_OK;
@@ -510,7 +511,7 @@ tm_status ensure_acc(StreamPool& p, size_t need, hipStream_t s) {
       p.acc = nullptr;
       p.acc_cap = 0;
     }
-    const size_t cap = align256(std::max<size_t>(need + need / 4, 4096));
+    const size_t cap = align256(std::max<size_t>(p.exact_growth ? need : need + need / 4, 4096));
     TM_HIP(hipMalloc(&p.acc, cap));
     p.acc_cap = cap;
     p.acc_dirty = true;
@@ -553,6 +554,47 @@ bool is_device_pointer(const void* ptr) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- pool control (request server)
+
+namespace tmi {
+
+void stream_pool_set_exact(int dev, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_pools[{dev, s}].exact_growth = true;
+}
+
+size_t stream_pool_device_bytes(int dev, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_pools.find({dev, s});
+  return it == g_pools.end() ? 0 : it->second.cap + it->second.acc_cap;
+}
+
+hipError_t stream_pool_release(int dev, hipStream_t s, bool keep_entry) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_pools.find({dev, s});
+  if (it == g_pools.end()) return hipSuccess;
+  StreamPool& p = it->second;
+  hipError_t err = hipStreamSynchronize(s);     // nothing on the stream may still use the pool
+  auto note = [&](hipError_t e) { if (err == hipSuccess) err = e; };
+  if (p.dev) note(hipFree(p.dev));
+  if (p.acc) note(hipFree(p.acc));
+  p.dev = p.acc = nullptr;
+  p.cap = p.acc_cap = 0;
+  p.acc_dirty = false;
+  for (int i = 0; i < 2; ++i) {
+    if (p.host[i]) note(hipHostFree(p.host[i]));
+    if (p.staged[i]) note(hipEventDestroy(p.staged[i]));
+    p.host[i] = nullptr;
+    p.hcap[i] = 0;
+    p.staged[i] = nullptr;
+    p.staged_pending[i] = false;
+  }
+  if (!keep_entry) g_pools.erase(it);
+  return err;
+}
+
+}  // namespace tmi
 
 // ---------------------------------------------------------------- plan
 

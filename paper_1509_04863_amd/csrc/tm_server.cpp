@@ -5,7 +5,12 @@
 // first out while the device workspace of the batches in flight stays within
 // the budget.  Results come back through pinned host memory; each request's
 // latency is measured from submission to the moment the worker sees its batch
-// complete.
+// complete.  The worker sleeps until a request arrives or a batch finishes
+// (a host function enqueued after each batch's result copy wakes it).  The
+// device memory the server's streams hold stays within the budget: a slot's
+// workspace pool grows to exactly what its batches need, and a batch is
+// launched only while the pools of all slots fit the budget (idle slots
+// release theirs first); one request larger than the budget runs alone.
 
 #include <algorithm>
 #include <chrono>
@@ -22,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include "tm.h"
+#include "tm_internal.h"
 
 namespace {
 
@@ -70,6 +76,8 @@ struct tm_server_s {
   uint64_t next_ticket = 1;
   int64_t inflight_bytes = 0;
   bool stop = false;
+  bool kick = false;               // a request arrived or a batch finished
+  bool poll_mode = false;          // a wake-up host function could not be enqueued
   tm_server_stats stats{};
   std::thread worker;
 };
@@ -111,6 +119,45 @@ void finish_slot(tm_server_s* s, Slot& sl, tm_status st) {
   s->cv_done.notify_all();
 }
 
+void wake(tm_server_s* s) {
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->kick = true;
+  }
+  s->cv_work.notify_one();
+}
+
+void batch_done_cb(void* user) { wake(static_cast<tm_server_s*>(user)); }
+
+// Device bytes the slots' pools hold, and the admission test on them: a
+// batch of `fp` bytes may run in slot `mine` while every slot's pool, that
+// slot's grown to the batch, fits the budget (or the batch is alone and
+// larger than the budget).  Idle slots give their pools back first.
+int64_t held_bytes(tm_server_s* s) {
+  int64_t h = 0;
+  for (Slot& sl : s->slots) h += (int64_t)tmi::stream_pool_device_bytes(s->device, sl.stream);
+  return h;
+}
+
+bool make_room(tm_server_s* s, Slot& mine, int64_t fp) {
+  const int64_t budget = std::max(s->desc.budget_bytes, fp);
+  auto fits = [&] {
+    int64_t h = 0;
+    for (Slot& sl : s->slots) {
+      const int64_t b = (int64_t)tmi::stream_pool_device_bytes(s->device, sl.stream);
+      h += &sl == &mine ? std::max(b, fp) : b;
+    }
+    return h <= budget;
+  };
+  if (fits()) return true;
+  for (Slot& sl : s->slots) {
+    if (sl.busy && &sl != &mine) continue;
+    (void)tmi::stream_pool_release(s->device, sl.stream, true);
+    if (fits()) return true;
+  }
+  return false;
+}
+
 void worker_loop(tm_server_s* s) {
   (void)hipSetDevice(s->device);
   std::vector<tm_plan> plans;
@@ -130,7 +177,7 @@ void worker_loop(tm_server_s* s) {
     for (Slot& sl : s->slots) {
       if (sl.busy) continue;
       {
-        std::lock_guard<std::mutex> lock(s->mu);
+        std::unique_lock<std::mutex> lock(s->mu);
         if (s->pending.empty()) break;
         fps.clear();
         const size_t look = std::min<size_t>(s->pending.size(), (size_t)s->desc.max_batch);
@@ -138,6 +185,14 @@ void worker_loop(tm_server_s* s) {
         const int32_t n = admit_prefix((int32_t)fps.size(), fps.data(), s->inflight_bytes, s->desc.budget_bytes,
                                        s->desc.max_batch);
         if (n == 0) break;   // budget full until a batch completes
+        int64_t fp = 0;
+        for (int32_t i = 0; i < n; ++i) fp += fps[(size_t)i];
+        lock.unlock();       // pools are released outside the request lock
+        const bool room = make_room(s, sl, fp);
+        lock.lock();
+        if (!room) break;    // the pools in flight hold the budget until a batch completes
+        const int64_t held = held_bytes(s);
+        s->stats.peak_held_bytes = std::max(s->stats.peak_held_bytes, held);
         sl.reqs.assign(s->pending.begin(), s->pending.begin() + n);
         s->pending.erase(s->pending.begin(), s->pending.begin() + n);
         for (const Req& r : sl.reqs) sl.footprint += r.footprint;
@@ -158,18 +213,21 @@ void worker_loop(tm_server_s* s) {
                          sl.stream) != hipSuccess)
         st = TM_ERR_DEVICE;
       if (st == TM_OK && hipEventRecord(sl.event, sl.stream) != hipSuccess) st = TM_ERR_DEVICE;
+      if (st == TM_OK && !s->poll_mode && hipLaunchHostFunc(sl.stream, batch_done_cb, s) != hipSuccess) {
+        (void)hipGetLastError();
+        s->poll_mode = true;   // no wake-up from the device: poll the events instead
+      }
       if (st != TM_OK) finish_slot(s, sl, st);
       else any_busy = true;
     }
-    // 3. wait for work
+    // 3. sleep until a request arrives or a batch finishes
     std::unique_lock<std::mutex> lock(s->mu);
     if (s->stop && s->pending.empty() && !any_busy) return;
-    if (!any_busy && s->pending.empty()) {
-      s->cv_work.wait(lock, [&] { return s->stop || !s->pending.empty(); });
-    } else if (any_busy) {
-      lock.unlock();
-      std::this_thread::yield();
-    }
+    if (any_busy && s->poll_mode)
+      s->cv_work.wait_for(lock, std::chrono::microseconds(50), [&] { return s->kick; });
+    else
+      s->cv_work.wait(lock, [&] { return s->kick; });
+    s->kick = false;
   }
 }
 
@@ -212,6 +270,7 @@ tm_status tm_server_create(const tm_server_desc* desc, tm_server* out) {
   bool ok = true;
   for (Slot& sl : s->slots) {
     ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
+    if (ok) tmi::stream_pool_set_exact(s->device, sl.stream);
     ok = ok && hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipMalloc(&sl.dev_out, sizeof(tm_result) * (size_t)d.max_batch) == hipSuccess;
     ok = ok && hipHostMalloc(&sl.host_out, sizeof(tm_result) * (size_t)d.max_batch, hipHostMallocDefault) ==
@@ -221,6 +280,7 @@ tm_status tm_server_create(const tm_server_desc* desc, tm_server* out) {
   if (!ok) {
     for (Slot& sl : s->slots) {
       if (sl.event) (void)hipEventDestroy(sl.event);
+      if (sl.stream) (void)tmi::stream_pool_release(s->device, sl.stream, false);
       if (sl.stream) (void)hipStreamDestroy(sl.stream);
       if (sl.dev_out) (void)hipFree(sl.dev_out);
       if (sl.host_out) (void)hipHostFree(sl.host_out);
@@ -242,7 +302,9 @@ tm_status tm_server_submit(tm_server s, tm_plan plan, const void* x, uint64_t* t
   Req r;
   r.plan = plan;
   r.x = x;
-  r.footprint = info.workspace_bytes + (int64_t)sizeof(tm_result);
+  // workspace, result slot, and the request's entry in the batch's instance
+  // table and launch list
+  r.footprint = info.workspace_bytes + (int64_t)sizeof(tm_result) + (int64_t)sizeof(tmi::Inst) + 16;
   r.t_submit = now_ns();
   {
     std::lock_guard<std::mutex> lock(s->mu);
@@ -251,6 +313,7 @@ tm_status tm_server_submit(tm_server s, tm_plan plan, const void* x, uint64_t* t
     s->outstanding.insert(r.ticket);
     s->pending.push_back(r);
     s->stats.submitted += 1;
+    s->kick = true;
   }
   s->cv_work.notify_one();
   *ticket = r.ticket;
@@ -299,11 +362,14 @@ tm_status tm_server_destroy(tm_server s) {
   {
     std::lock_guard<std::mutex> lock(s->mu);
     s->stop = true;
+    s->kick = true;
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   tm_status st = TM_OK;
   for (Slot& sl : s->slots) {
+    // the stream drains (wake-up host functions included), then its pool goes
+    if (tmi::stream_pool_release(s->device, sl.stream, false) != hipSuccess) st = TM_ERR_DEVICE;
     if (hipStreamSynchronize(sl.stream) != hipSuccess) st = TM_ERR_DEVICE;
     (void)hipEventDestroy(sl.event);
     (void)hipStreamDestroy(sl.stream);

@@ -61,7 +61,8 @@ class ServerDesc(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
-                ("batches", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64)]
+                ("batches", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64),
+                ("peak_held_bytes", ctypes.c_int64)]
 
 
 assert ctypes.sizeof(Result) == 48 and ctypes.sizeof(PlanDesc) == 48

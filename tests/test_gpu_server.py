@@ -69,7 +69,7 @@ def test_budget_bounds_workspace_in_flight():
     insts = _mix(40, 2)
     plans = [tm.Plan(s.t, n=s.n, x_dtype=tm.tm_dtype_of(s.x)) for s in insts]
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
-    fps = [p.info["workspace_bytes"] + 48 for p in plans]
+    fps = [p.info["workspace_bytes"] + 48 + 512 for p in plans]   # + result slot and instance record
     budget = 3 * int(np.median(fps))
     print("case: server budget", budget, flush=True)
     with tm.Server(budget_bytes=budget, max_batch=64, max_inflight=4) as srv:
@@ -77,6 +77,9 @@ def test_budget_bounds_workspace_in_flight():
         got = [srv.wait(t)[0] for t in tickets]
         st = srv.stats()
     assert st["peak_inflight_bytes"] <= max(budget, max(fps))
+    # the device memory the server's streams held at any launch: the budget
+    # (plus the alignment of a few pool blocks), or one oversized request
+    assert 0 < st["peak_held_bytes"] <= max(budget, max(fps)) + 4 * 4 * 4096
     assert st["batches"] >= sum(fps) // max(budget, max(fps))
     alone = [tm.match(p, x) for p, x in zip(plans, xs)]
     assert got == alone
@@ -101,3 +104,34 @@ def test_poll_and_drain_on_close():
     srv.close()                               # drains the queued requests
     assert len(later) == len(plans)
     assert [done[t] for t in tickets] == [tm.match(p, x) for p, x in zip(plans, xs)]
+
+
+def test_create_destroy_frees_device_memory():
+    # every slot's workspace pool, pinned staging and events go with the
+    # server: device memory in use returns to its level after each cycle
+    insts = _mix(18, 4)
+    plans = [tm.Plan(s.t, n=s.n, x_dtype=tm.tm_dtype_of(s.x)) for s in insts]
+    xs = [torch.from_numpy(s.x).cuda() for s in insts]
+    alone = [tm.match(p, x) for p, x in zip(plans, xs)]
+    torch.cuda.synchronize()
+    print("case: server create/destroy", flush=True)
+
+    def used():
+        free, total = torch.cuda.mem_get_info()
+        return total - free
+
+    def cycle():
+        with tm.Server(budget_bytes=64 << 20, max_batch=8, max_inflight=3) as srv:
+            got = [srv.wait(srv.submit(p, x))[0] for p, x in zip(plans, xs)]
+            held = srv.stats()["peak_held_bytes"]
+        assert got == alone
+        return held
+
+    cycle()                                   # the runtime's own first-use allocations
+    torch.cuda.synchronize()
+    base = used()
+    for _ in range(3):
+        held = cycle()
+        torch.cuda.synchronize()
+        assert held > 0
+        assert used() <= base + (2 << 20), "a server left device memory behind"
