@@ -164,7 +164,7 @@ def run_batched(args):
     plans = [tm.Plan(s.t, n=s.n) for s in insts]
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
     batch = tm.Batch(plans, xs)
-    out = torch.zeros(48 * len(insts), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * len(insts), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     profile = not args.no_profile
     # warmup with the timing events on as well, for as many steps as are
@@ -180,9 +180,11 @@ def run_batched(args):
         tm.profile_enable(True)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     ev[0].record(stream)
+    h0 = time.perf_counter()
     for i in range(args.steps):
         batch.run(out, stream)
         ev[i + 1].record(stream)
+    host_ms = (time.perf_counter() - h0) * 1e3 / args.steps
     torch.cuda.synchronize()
     if profile:
         tm.profile_enable(False)
@@ -207,6 +209,7 @@ def run_batched(args):
                    "instances": len(insts), "batch_x_bytes": x_bytes, "batch_t_bytes": t_bytes,
                    "timed_bytes": args.steps * x_bytes, "kernel_timing": "events on the timed steps' dispatches"},
         "step_times": _step_stats(steps_ms),
+        "host_enqueue_ms_per_step": host_ms,
         "path_roofline": {"bound": "hbm", "achieved": (x_bytes + t_bytes) / (ms_per_step / 1e3) / 1e9,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": (x_bytes + t_bytes) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
@@ -220,6 +223,8 @@ def run_batched(args):
     if corr_n:
         corr_roof = corr_roofline(plans, corr_ms, corr_n, traffic_for("corr/config3"))
     pick_roofline(line, fold_roof, corr_roof)
+    line["graph_replay"] = graph_replay(plans, xs, out, results, args.steps, stream)
+    line["fft_route"] = fft_route(insts, xs, results, max(3, args.steps // 4), stream)
     del batch, xs
     torch.cuda.empty_cache()
     if not args.no_serving:
@@ -227,6 +232,56 @@ def run_batched(args):
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_pool("config3", args.cpu_seconds, results, args.cpu_workers)
     print(json.dumps(line), flush=True)
+
+
+def graph_replay(plans, xs, out, results, steps, stream):
+    """The same batch through a reusable batch (tm_batch_*: its launch
+    sequence captured once in a HIP graph, one graph launch per step)."""
+    import torch
+
+    from paper_1509_04863_amd import tm
+    g_out = torch.zeros_like(out)
+    g = tm.BatchGraph(plans, xs, g_out, stream)
+    for _ in range(2):
+        g.run(stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    h0 = time.perf_counter()
+    for _ in range(steps):
+        g.run(stream)
+    host_ms = (time.perf_counter() - h0) * 1e3 / steps
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    same = tm.results_from_device(g_out) == results
+    g.close()
+    return {"ms_per_step": ms, "matches_per_s": len(plans) / (ms / 1e3), "host_enqueue_ms_per_step": host_ms,
+            "results_equal_eager": bool(same)}
+
+
+def fft_route(insts, xs, results, steps, stream):
+    """The same instances with the correlation by the exact FFT of steps 4-6
+    (TM_F_FFT plans: FP64 transform in one workgroup's LDS) instead of the
+    int8 product, for comparison."""
+    import torch
+
+    from paper_1509_04863_amd import tm
+    plans = [tm.Plan(s.t, n=s.n, flags=tm.TM_F_FFT) for s in insts]
+    out = torch.zeros(tm.RESULT_BYTES * len(plans), dtype=torch.uint8, device="cuda")
+    batch = tm.Batch(plans, xs)
+    batch.run(out, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        batch.run(out, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    same = sum(int(x == y) for x, y in zip(tm.results_from_device(out), results))
+    return {"ms_per_step": ms, "matches_per_s": len(plans) / (ms / 1e3), "steps": steps,
+            "same_results": "%d/%d" % (same, len(plans))}
 
 
 def serving_sample(pool_size, templates, rate, duration, plain_rounds=3):
@@ -345,7 +400,7 @@ def run_precision(args):
     per = {}
     for name, st in stores.items():
         plans = [tm.Plan(s.t, n=s.n, fold_store=st) for s in insts]
-        out = torch.zeros(48 * rot, dtype=torch.uint8, device="cuda")
+        out = torch.zeros(tm.RESULT_BYTES * rot, dtype=torch.uint8, device="cuda")
         for i in range(max(args.warmup, rot)):
             tm.match_into(plans[i % rot], xs[i % rot], out, i % rot, stream)
         torch.cuda.synchronize()
@@ -421,7 +476,7 @@ def run_shared(args):
     plan = tm.Plan(insts[0].t, n=insts[0].n)
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
     many = tm.Many(plan, xs)
-    out = torch.zeros(48 * len(xs), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * len(xs), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
 
     def timed(steps):
@@ -577,7 +632,7 @@ def main():
     insts = [first] + [wl["make"](i) for i in range(1, rot)]
     plans = [tm.Plan(s.t, n=s.n, fold_mult=wl["fold_mult"], flags=wl["flags"]) for s in insts]
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
-    out = torch.zeros(48 * rot, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * rot, dtype=torch.uint8, device="cuda")
     main_stream = torch.cuda.current_stream()
     # independent single-match launch sequences, round-robin over the streams:
     # one match's one-workgroup finish overlaps the next match's fold

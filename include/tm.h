@@ -235,6 +235,27 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
                          tm_result* out, void* stream);
 
 /*
+ * Reusable batches -- Algorithm 1 steps 3 and 5-9 per instance, as
+ * tm_match_batch, for a fixed list of plans and signals matched again and
+ * again (the signals' contents may change between launches, their addresses
+ * may not).  tm_batch_create builds the instance table once in device memory
+ * of its own (workspace, buckets, table) and captures the batch's whole
+ * kernel sequence in a HIP graph; tm_batch_launch replays it on `stream`
+ * with one graph launch, so the host builds and uploads nothing per launch.
+ * out: `count` results in DEVICE memory (TM_ERR_INVALID otherwise), written
+ * by every launch.  plans, xs: host arrays read during the call; the plans
+ * and signals must stay valid until tm_batch_destroy.  Launches of one batch
+ * on several streams at once race (they share its workspace).  Three-moduli
+ * plans: TM_ERR_UNSUPPORTED.  The creating call waits for `stream`.
+ */
+typedef struct tm_batch_s* tm_batch;
+tm_status tm_batch_create(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
+                          void* stream, tm_batch* batch);
+tm_status tm_batch_launch(tm_batch batch, void* stream);
+/* Waits for the device, then frees the batch's memory and graph.  NULL is allowed. */
+tm_status tm_batch_destroy(tm_batch batch);
+
+/*
  * tm_match_many -- one template, `count` signals of the plan's N (Algorithm 1
  * per signal).  xs is a host array of count device pointers; out holds count
  * results (host or device, as tm_match).  For exact int8 plans (K <= 2^14,

@@ -172,6 +172,9 @@ constexpr int kCgMaxLimbs = 5;                      // balanced base-128 digits 
 constexpr int kCgMaxK = 1 << 17;                    // int32 limb sums stay exact below this K
 constexpr int kCgPrepThreads = 256;
 constexpr int kTopTMax = 4;                         // runners-up per fold for top-T re-scoring
+constexpr int kCg2Waves = 4;                        // waves of the per-instance product kernel (batches)
+constexpr size_t kCg2MaxLds = 156 * 1024;           // its largest LDS footprint (template copies, digit rows)
+constexpr int kCgClasses = 5;                       // LDS classes of its launches
 
 // One user instance of a batch that holds three-moduli plans: the indices of
 // its results in the expanded instance list (i2 < 0: a two-moduli plan whose
@@ -251,6 +254,12 @@ hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int coun
 hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
                              hipStream_t s);
 hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s);
+// batches: the correlation stage with one workgroup per instance (literal
+// folds, product with its operands in LDS, argmaxes, resolve; no prep or
+// final kernel); `lds` bytes: the largest cgemm_inst_lds_bytes of the listed
+// instances (tasks = c_rta + c_rtb, rtm = max(c_rta, c_rtb))
+size_t cgemm_inst_lds_bytes(int c_lt, int c_lp, int nlcap, int tasks, int rtm);
+hipError_t launch_cgemm_inst(const InstTable& tab, const int32_t* list, int count, size_t lds, hipStream_t s);
 int cgemm_limbs_for(int64_t maxabs);                   // limbs that hold |y| <= maxabs
 // Theorem 4 with three moduli: per user instance, S1 cap S2 cap S3 from the two
 // pairs' argmaxes, re-scored by (Tx)_c (one workgroup each)

@@ -474,11 +474,8 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
   const int64_t B0 = g.c_begin * 16, B1 = g.c_end * 16;
   int64_t k = B0 > g.delta ? (B0 - g.delta + M - 1) / M : 0;
   int64_t rb = k * M + g.delta;                 // first byte of row k
-  // top slot: bytes of buckets >= M are cleared
-  const int utop = u0 + kSegHalf * (NSL - 1);
-  const int nval = (int)max((int64_t)0, min((int64_t)4, M - 4 * (int64_t)utop));
-  const uint32_t topm = nval >= 4 ? 0xFFFFFFFFu : (1u << (8 * nval)) - 1u;
-  const uint32_t top_even = topm & 0x00FF00FFu, top_odd = (topm >> 8) & 0x00FF00FFu;
+  // the top slot also sums bytes past the row's end into lanes of buckets >= M:
+  // those lanes stay below 2^16 like the others and are never flushed
 
   uint32_t lo[NSL], hi[NSL];
 #pragma unroll
@@ -500,39 +497,43 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
     const int64_t Bp = B0 + (int64_t)j * kSegPiece;
     const int64_t Bend = min(Bp + kSegPiece, B1);
     const int ring = (j & 1) * kSegPiece;              // LDS offset of byte b: ring + (b - Bp)
-    // rows starting in this piece (first byte in [Bp, Bend), row < L): counted
-    // once, then folded G at a time with 32-bit offsets, all reads of a group
-    // in flight together; rows past the count read offset 0 with an all-zero
-    // byte selector
-    constexpr int GR = NSL <= 2 ? 4 : (NSL <= 4 ? 2 : 1);
+    // rows starting in this piece (first byte in [Bp, Bend), row < L), counted
+    // once.  Row i starts at LDS offset rel + i M; its misalignment
+    // (rel + i M) mod 4 has period 4 in i, so four byte selectors and four
+    // word-aligned bases, computed once per piece, serve every group of four
+    // rows (no per-row scalar work beyond the group's offset)
     int nr = 0;
     if (k < L && rb < Bend) nr = (int)min(L - k, (Bend - rb + M - 1) / M);
     const int M32 = (int)M;
-    int rel = ring + (int)(rb - Bp);             // LDS offset of the next row's first byte
-    for (int r = 0; r < nr; r += GR) {
-      uint32_t w0[GR][NSL], w1[GR][NSL], sel[GR];
+    const int rel = ring + (int)(rb - Bp);
+    uint32_t se[4], so[4];
+    int base[4];
 #pragma unroll
-      for (int q = 0; q < GR; ++q) {
-        const bool ok = r + q < nr;
-        const int off = ok ? rel + q * M32 : 0;
-        sel[q] = ok ? 0x0C020C00u + ((uint32_t)off & 3u) * 0x00010001u : 0x0C0C0C0Cu;
-        seg_read_row<NSL>(lds, off & ~3, u0, w0[q], w1[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < GR; ++q) {
-        const uint32_t se = sel[q];                                                  // bytes c, c + 2
-        const uint32_t so = se == 0x0C0C0C0Cu ? se : se + 0x00010001u;               // bytes c + 1, c + 3
-#pragma unroll
-        for (int s = 0; s < NSL; ++s) {
-          uint32_t e = __builtin_amdgcn_perm(w1[q][s], w0[q][s], se);
-          uint32_t o = __builtin_amdgcn_perm(w1[q][s], w0[q][s], so);
-          if (s == NSL - 1) { e &= top_even; o &= top_odd; }
-          lo[s] += e;
-          hi[s] += o;
-        }
-      }
-      rel += GR * M32;
+    for (int q = 0; q < 4; ++q) {
+      const int off = rel + q * M32;
+      const uint32_t a = (uint32_t)off & 3u;
+      se[q] = 0x0C020C00u + a * 0x00010001u;      // bytes c, c + 2 of the row's four
+      so[q] = se[q] + 0x00010001u;                // bytes c + 1, c + 3
+      base[q] = off - (int)a;
     }
+    auto row = [&](int q, int r) {                // row r + q, r a multiple of 4
+      uint32_t w0[NSL], w1[NSL];
+      seg_read_row<NSL>(lds, base[q] + r * M32, u0, w0, w1);
+#pragma unroll
+      for (int s = 0; s < NSL; ++s) {
+        lo[s] += __builtin_amdgcn_perm(w1[s], w0[s], se[q]);
+        hi[s] += __builtin_amdgcn_perm(w1[s], w0[s], so[q]);
+      }
+    };
+    const int full = nr & ~3;
+    for (int r = 0; r < full; r += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) row(q, r);
+    }
+    const int rest = nr - full;
+    if (rest > 0) row(0, full);
+    if (rest > 1) row(1, full);
+    if (rest > 2) row(2, full);
     k += nr;
     rb += (int64_t)nr * M;
     __syncthreads();
@@ -2119,31 +2120,42 @@ __device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
   GAS int* cmax = G(d.cmax);
   int mx[2] = {0, 0};
   const int e1 = min(e0 + chunk, 2 * lp);
-  for (int e = e0 + (int)threadIdx.x; e < e1; e += kCgPrepThreads) {
-    const int f = e >= lp ? 1 : 0;
-    const int u = e - f * lp;
+  // four consecutive entries per thread (a fold's 4-aligned entries never
+  // straddle the folds: lp is a multiple of 256), one 4-byte store per digit
+  for (int e4 = e0 + 4 * (int)threadIdx.x; e4 < e1; e4 += 4 * kCgPrepThreads) {
+    const int f = e4 >= lp ? 1 : 0;
     const int M = f ? mb : ma;
     const int rho = f ? rhoB : rhoA;
-    int val = 0;
-    if (u < M + K - 1) {
-      const int s = u < M ? u : u - M;
-      val = yp[(f ? ma : 0) + s];
-      if (sfold) val -= (f ? biasB : biasA) + (s < rho ? 128 : 0);
-      if (!zpad) {
-        if (s >= rho) val += ld_int<Tin>(x, mod_small((int64_t)(s - rho), N, general));
-        if (u >= M) val += ld_int<Tin>(x, mod_small((int64_t)s + M - rho, N, general)) - ld_int<Tin>(x, s);
+    double* dy = f ? dyB : dyA;
+    int val[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int u = e4 + i - f * lp;
+      int v = 0;
+      if (u < M + K - 1) {
+        const int s = u < M ? u : u - M;
+        v = yp[(f ? ma : 0) + s];
+        if (sfold) v -= (f ? biasB : biasA) + (s < rho ? 128 : 0);
+        if (!zpad) {
+          if (s >= rho) v += ld_int<Tin>(x, mod_small((int64_t)(s - rho), N, general));
+          if (u >= M) v += ld_int<Tin>(x, mod_small((int64_t)s + M - rho, N, general)) - ld_int<Tin>(x, s);
+        }
+        if (dy) G(dy)[u] = (double)v;
       }
-      double* dy = f ? dyB : dyA;
-      if (dy) G(dy)[u] = (double)val;
+      val[i] = v;
+      mx[f] = max(mx[f], v < 0 ? -v : v);
     }
-    int rest = val;
-    GAS int8_t* dst = limb + (int64_t)f * nlc * lp + u;
+    GAS uint32_t* dst = reinterpret_cast<GAS uint32_t*>(limb + (int64_t)f * nlc * lp + (e4 - f * lp));
     for (int l = 0; l < nlc; ++l) {
-      const int digit = ((rest + 64) & 127) - 64;
-      rest = (rest - digit) >> 7;
-      dst[(int64_t)l * lp] = (int8_t)digit;
+      uint32_t w = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int digit = ((val[i] + 64) & 127) - 64;
+        val[i] = (val[i] - digit) >> 7;
+        w |= (uint32_t)(uint8_t)(int8_t)digit << (8 * i);
+      }
+      dst[(int64_t)l * (lp >> 2)] = w;
     }
-    mx[f] = max(mx[f], val < 0 ? -val : val);
   }
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
@@ -2440,6 +2452,293 @@ __global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_
   else cg_final_dispatch(tab.resident());
 }
 
+// --------------------------------------------------------------------------
+// the same product for batches: one workgroup per instance, operands in LDS
+// --------------------------------------------------------------------------
+//
+// A workgroup of kCg2Waves waves owns one instance: it stages the 16 shifted
+// template copies (the interleaved layout above) and the digit rows the prep
+// kernel wrote in LDS once, then every wave computes whole 16 x 64 row tiles
+// (all four column tiles, every digit, the whole band) from LDS, so the
+// template is read from memory once per instance rather than once per row
+// tile and the B operand of each step serves all digits of its row tile; the
+// same workgroup then takes both argmaxes and resolves (no final kernel, no
+// partials in memory).  When an
+// instance has fewer row tiles than waves, the band's steps are split over
+// P = kCg2Waves / tiles waves per tile and their digit sums meet in an LDS
+// int32 buffer (each digit's full sum fits int32: |d| <= 64, |t| <= 128,
+// K <= 2^17).  The digit rows sit in LDS with 16 pad bytes after every 256,
+// so the 16 rows of an A operand (64 bytes apart) fall in distinct banks.
+// Each (fold, row tile) keeps the best (value, lowest shift) of each column
+// tile in LDS.
+
+__host__ __device__ __forceinline__ int cg2_pad(int b) { return b + ((b >> 8) << 4); }   // padded LDS offset
+
+// digit sums of a finished tile (registers, or the split band's LDS
+// accumulators) to r (int64), the intermediates, and the best of each column
+// tile into cpart (lane layout of the MFMA result: rows 4 g + jj, column c)
+template <int NL>
+__device__ __forceinline__ void cg2_report(const Inst& d, int f, int rt, const int* red,
+                                           const v4i_t (&acc)[NL][4], VI* tbest) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15, g = lane >> 4;
+  const int M = f ? d.vb.m : d.va.m;
+  double* dr = (f != d.swapped) ? d.dbg_r2 : d.dbg_r1;
+  const int rtm = max(d.c_rta, d.c_rtb);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    VI best{-INFINITY, 0x7fffffff};
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      long long r = 0, wt = 1;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const int v = red ? red[((l * 4 + nt) * 4 + jj) * 64 + lane] : acc[l][nt][jj];
+        r += wt * (long long)v;
+        wt *= 128;
+      }
+      const int k = 64 * (kCgRows * rt + 4 * g + jj) + 16 * nt + c;
+      if (k < M) {
+        if (dr) G(dr)[k] = (double)r;
+        if (d.rtop) G(d.rtop)[(f ? d.va.m : 0) + k] = (double)r;
+        if (vi_better(VI{(double)r, k}, best)) best = VI{(double)r, k};
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
+      if (vi_better(other, best)) best = other;
+    }
+    if (lane == 0) tbest[(f * rtm + rt) * 4 + nt] = best;
+  }
+}
+
+// One wave: row tile rt of fold f over the band's steps [s0, s1), every
+// digit and column tile, operands from LDS (`lb`: template copies; `la`: the
+// padded digit rows, this fold's digit l at row row0 + l).  With `red` (the
+// tile's own block of accumulators, 1024 ints per digit) the sums go there,
+// else straight to the report.
+template <int NL>
+__device__ __forceinline__ void cg2_tile(const Inst& d, const unsigned char* lb, const unsigned char* la, int row0,
+                                         int f, int rt, int s0, int s1, int* red, VI* tbest) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15, g = lane >> 4;
+  const int M = f ? d.vb.m : d.va.m;
+  // column tiles that hold a shift below M (the last row tile of a fold may need fewer)
+  const int ntc = min(4, (M - 1024 * rt + 15) >> 4);
+  const int lp = d.c_lp;
+  const int abase = row0 * lp + 64 * (kCgRows * rt + c) + 16 * g;   // this lane's A bytes at step 0, digit 0
+  v4i_t acc[NL][4];
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
+  auto ld_b = [&](int st, int nt) {
+    const int j = 64 * st + 16 * g - (16 * nt + c) + kCgPad;
+    const int sh = (-j) & 15;
+    return *reinterpret_cast<const v4i_t*>(lb + (((j + sh) >> 4) * 16 + sh) * 16);
+  };
+  auto ld_a = [&](int st, int l) {
+    return *reinterpret_cast<const v4i_t*>(la + cg2_pad(abase + l * lp + 64 * st));
+  };
+  if (s1 > s0) {
+    v4i_t bc[4], ac[NL];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bc[nt] = ld_b(s0, nt);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) ac[l] = ld_a(s0, l);
+    for (int st = s0; st < s1; ++st) {
+      // the next step's operands are read while this step's products run
+      v4i_t bn[4], an[NL];
+      const int sn = min(st + 1, s1 - 1);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) bn[nt] = ld_b(sn, nt);
+#pragma unroll
+      for (int l = 0; l < NL; ++l) an[l] = ld_a(sn, l);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        if (nt < ntc) {                       // uniform over the wave
+#pragma unroll
+          for (int l = 0; l < NL; ++l)
+            acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ac[l], bc[nt], acc[l][nt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) bc[nt] = bn[nt];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) ac[l] = an[l];
+    }
+  }
+  if (red) {   // a share of the band: digit sums into the tile's LDS accumulators
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          atomicAdd(red + ((l * 4 + nt) * 4 + jj) * 64 + lane, acc[l][nt][jj]);
+  } else {
+    cg2_report<NL>(d, f, rt, nullptr, acc, tbest);
+  }
+}
+
+__device__ __forceinline__ void cg2_dispatch_task(int nl, const Inst& d, const unsigned char* lb,
+                                                  const unsigned char* la, int row0, int f, int rt, int s0, int s1,
+                                                  int* red, VI* tbest) {
+  switch (nl) {
+    case 1: cg2_tile<1>(d, lb, la, row0, f, rt, s0, s1, red, tbest); break;
+    case 2: cg2_tile<2>(d, lb, la, row0, f, rt, s0, s1, red, tbest); break;
+    case 3: cg2_tile<3>(d, lb, la, row0, f, rt, s0, s1, red, tbest); break;
+    case 4: cg2_tile<4>(d, lb, la, row0, f, rt, s0, s1, red, tbest); break;
+    default: cg2_tile<5>(d, lb, la, row0, f, rt, s0, s1, red, tbest); break;
+  }
+}
+
+__device__ __forceinline__ void cg2_dispatch_report(int nl, const Inst& d, int f, int rt, const int* red, VI* tbest) {
+  switch (nl) {
+    case 1: { v4i_t a[1][4]; cg2_report<1>(d, f, rt, red, a, tbest); break; }
+    case 2: { v4i_t a[2][4]; cg2_report<2>(d, f, rt, red, a, tbest); break; }
+    case 3: { v4i_t a[3][4]; cg2_report<3>(d, f, rt, red, a, tbest); break; }
+    case 4: { v4i_t a[4][4]; cg2_report<4>(d, f, rt, red, a, tbest); break; }
+    default: { v4i_t a[5][4]; cg2_report<5>(d, f, rt, red, a, tbest); break; }
+  }
+}
+
+// LDS of one instance: template copies, both folds' padded digit rows (nlcap
+// each), the split-band accumulators, and the best entry of every column tile
+__host__ __device__ inline size_t cg2_lds_bytes(int c_lt, int c_lp, int nlcap, int tasks, int rtm) {
+  const size_t b = (size_t)16 * c_lt;
+  const size_t a = ((size_t)cg2_pad(2 * nlcap * c_lp) + 15) & ~(size_t)15;
+  const size_t red = kCg2Waves / tasks > 1 ? (size_t)tasks * nlcap * 4 * 4 * 64 * 4 : 0;
+  return b + a + red + (size_t)2 * rtm * 4 * sizeof(VI);
+}
+
+// Global -> LDS copy of `n` 16-byte chunks, eight loads in flight per thread
+// before their stores (the workgroup's copies overlap their latencies)
+template <typename Dst>
+__device__ __forceinline__ void cg2_stage(uintptr_t src, int n, Dst dst_of) {
+  constexpr int U = 8;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  for (int base = 0; base < n; base += U * NT) {
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * NT + tid;
+      if (i < n) v[u] = gload16(src + (uintptr_t)i * 16);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * NT + tid;
+      if (i < n) *reinterpret_cast<uint4*>(dst_of(i)) = v[u];
+    }
+  }
+}
+
+// One workgroup does the product, both argmaxes and the resolve of one
+// instance (Algorithm 1 steps 4-9) from the digit rows the prep kernel wrote:
+// template copies and digit rows into LDS, the row tiles, the argmaxes from
+// the per-column-tile bests in LDS, the buckets and fold maxima back to zero,
+// and the resolve with its re-score.
+template <typename Tin>
+__device__ __forceinline__ void cg2_instance(const Inst& d, unsigned char* lds) {
+  __shared__ VI fin[2];
+  __shared__ __align__(16) unsigned char scratch[16 * 16];
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lt = d.c_lt, lp = d.c_lp, nlcap = d.c_nlcap;
+  const int ma = d.va.m, mb = d.vb.m;
+  const int rtm = max(d.c_rta, d.c_rtb);
+  const int ntask = d.c_rta + d.c_rtb;
+  const int parts = ntask < kCg2Waves ? kCg2Waves / ntask : 1;
+  unsigned char* lb = lds;
+  unsigned char* la = lds + (size_t)16 * lt;
+  const size_t a_bytes = ((size_t)cg2_pad(2 * nlcap * lp) + 15) & ~(size_t)15;
+  int* red = parts > 1 ? reinterpret_cast<int*>(la + a_bytes) : nullptr;
+  VI* tbest = reinterpret_cast<VI*>(la + a_bytes + (parts > 1 ? (size_t)ntask * nlcap * 4 * 4 * 64 * 4 : 0));
+  int nl[2];
+  nl[0] = min(cg_limbs(G(d.cmax)[0]), nlcap);
+  nl[1] = min(cg_limbs(G(d.cmax)[1]), nlcap);
+  // the 16 template copies (contiguous), then the digit rows in use: fold f's
+  // digit l at padded LDS row f nlcap + l
+  cg2_stage(reinterpret_cast<uintptr_t>(d.tsh), lt, [&](int i) { return lb + (size_t)i * 16; });
+  const int cpr = lp >> 4;
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const uintptr_t src = reinterpret_cast<uintptr_t>(d.ylimb + (int64_t)f * nlcap * lp);
+    cg2_stage(src, nl[f] * cpr, [&](int i) {
+      const int l = i / cpr, q = i - l * cpr;
+      return la + cg2_pad((f * nlcap + l) * lp + 16 * q);
+    });
+  }
+  if (red) {
+    const int nred = ntask * nlcap * 4 * 4 * 64;
+    for (int i = tid; i < nred; i += NT) red[i] = 0;
+  }
+  __syncthreads();
+  // the buckets and fold maxima have been consumed (the fold maxima by every
+  // thread above): back to zero for the next launch
+  for (int i = tid; i < ma + mb; i += NT) G(d.yp)[i] = 0;
+  if (tid < 2) G(d.cmax)[tid] = 0;
+  const int KS = d.c_ks;
+  for (int w = wave; w < ntask * parts; w += kCg2Waves) {
+    const int task = w % ntask, part = w / ntask;
+    const int f = task >= d.c_rta ? 1 : 0;
+    const int rt = task - f * d.c_rta;
+    const int s0 = (int)((int64_t)KS * part / parts), s1 = (int)((int64_t)KS * (part + 1) / parts);
+    cg2_dispatch_task(nl[f], d, lb, la, f * nlcap, f, rt, s0, s1, red ? red + task * nlcap * 1024 : nullptr, tbest);
+  }
+  if (red) {
+    __syncthreads();
+    for (int task = wave; task < ntask; task += kCg2Waves) {
+      const int f = task >= d.c_rta ? 1 : 0;
+      cg2_dispatch_report(nl[f], d, f, task - f * d.c_rta, red + task * nlcap * 1024, tbest);
+    }
+  }
+  // the correlations (global memory, read by top-T) and the per-column-tile
+  // bests of every tile are written: the two argmaxes, lowest shift first
+  __threadfence_block();
+  __syncthreads();
+  if (wave < 2) {
+    const int f = wave;
+    const int n = (f ? d.c_rtb : d.c_rta) * 4;
+    VI best{-INFINITY, 0x7fffffff};
+    for (int i = lane; i < n; i += 64) {
+      const VI v = tbest[f * rtm * 4 + i];
+      if (vi_better(v, best)) best = v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
+      if (vi_better(other, best)) best = other;
+    }
+    if (lane == 0) fin[f] = best;
+  }
+  __syncthreads();
+  if (d.top_t > 1) resolve_top_t<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+  else resolve_and_report<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+}
+
+__global__ void __launch_bounds__(64 * kCg2Waves) k_cgemm_inst(InstTable tab, const int32_t* list) {
+  extern __shared__ __align__(16) unsigned char lds2[];
+  const Inst& d = list ? tab.table[list[blockIdx.x]] : tab.resident();
+  switch (d.x_dtype) {
+    case TM_I8: cg2_instance<int8_t>(d, lds2); break;
+    case TM_F32: cg2_instance<float>(d, lds2); break;
+    case TM_BF16: cg2_instance<bf16_t>(d, lds2); break;
+    default: cg2_instance<f16_t>(d, lds2); break;
+  }
+}
+
+size_t cgemm_inst_lds_bytes(int c_lt, int c_lp, int nlcap, int tasks, int rtm) {
+  return cg2_lds_bytes(c_lt, c_lp, nlcap, tasks, rtm);
+}
+
+hipError_t launch_cgemm_inst(const InstTable& tab, const int32_t* list, int count, size_t lds, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  TM_LAUNCH(k_cgemm_inst, dim3(count), dim3(64 * kCg2Waves), lds, s, tab, list);
+  return hipGetLastError();
+}
+
 hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int count, int chunk, int prep_y,
                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
@@ -2685,7 +2984,7 @@ hipError_t configure_kernels() {
                        reinterpret_cast<const void*>(k_gfft_cols<double>), reinterpret_cast<const void*>(k_gfft_cols<float>),
                        reinterpret_cast<const void*>(k_gfft_rows<double>), reinterpret_cast<const void*>(k_gfft_rows<float>),
                        reinterpret_cast<const void*>(k_gfft_icols<double>),
-                       reinterpret_cast<const void*>(k_gfft_icols<float>)};
+                       reinterpret_cast<const void*>(k_gfft_icols<float>), reinterpret_cast<const void*>(k_cgemm_inst)};
   for (const void* f : fns) {
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
       (void)hipGetLastError();

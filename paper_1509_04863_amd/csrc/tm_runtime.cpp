@@ -154,13 +154,13 @@ int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
 }
 
 // Literal-fold entries per prep workgroup: about 4096 workgroups over the
-// launch's entries, at least 256 and at most one instance's pair of folds;
-// grid rows = chunks of the largest instance.
+// launch's entries, at least 1024 (four per thread) and at most one
+// instance's pair of folds; grid rows = chunks of the largest instance.
 struct CgLaunch { int chunk; int prep_y; };
 CgLaunch cgemm_launch(int64_t total_entries, int64_t max_entries, int64_t count) {
   (void)count;
-  int64_t chunk = std::max<int64_t>(256, align_up(ceil_div(total_entries, 4096), 256));
-  chunk = std::min(chunk, align_up(max_entries, 256));
+  int64_t chunk = std::max<int64_t>(1024, align_up(ceil_div(total_entries, 4096), 1024));
+  chunk = std::min(chunk, align_up(max_entries, 1024));
   return CgLaunch{(int)chunk, (int)ceil_div(max_entries, chunk)};
 }
 
@@ -1028,6 +1028,26 @@ static int cgemm_split(const Core& c) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(env, std::max(1, c.c_ks)));
 }
 
+// Product kernel choice (TM_CGEMM_KIND): 0 and 1 per row tile (the
+// default), 2 per instance wherever its LDS holds the operands (single
+// matches included).  Measured on 4096 uneven int8 instances (N up to 2^20,
+// K up to 4096), the per-instance kernel's correlation stage took about
+// 600 us per batch against 390 us for prep, row-tile product and final
+// kernel: with up to 133 KB of LDS per instance a compute unit holds one or
+// two of its workgroups, and their staging loads leave the matrix cores idle
+// (3% busy).
+static int cgemm_kind() { return (int)env_int("TM_CGEMM_KIND", 0); }
+
+// LDS classes of the per-instance product kernel: footprints that let 8, 5,
+// 3, 2 and 1 workgroups share a compute unit; kCgClasses: too large for it
+static int cg_class(const Core& c) {
+  static const size_t lim[kCgClasses] = {20u << 10, 32u << 10, 53u << 10, 80u << 10, kCg2MaxLds};
+  const size_t b = cgemm_inst_lds_bytes(c.c_lt, c.c_lp, c.c_nlcap, c.c_rta + c.c_rtb, std::max(c.c_rta, c.c_rtb));
+  for (int i = 0; i < kCgClasses; ++i)
+    if (b <= lim[i]) return i;
+  return kCgClasses;
+}
+
 static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1, double* y2,
                            double* r1, double* r2, void* stream) {
   tm_status st = check_plan_for_match(p);
@@ -1085,11 +1105,21 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   TM_HIP(timed_fold(tab, fw, s));
   pool.acc_dirty = true;                 // until the finish kernel is enqueued
   TM_HIP(launch_reduce(tab, p->core.nred, s));
-  if (p->core.cgemm) {
-    const CgLaunch cl = cgemm_launch(2 * (int64_t)p->core.c_lp, 2 * (int64_t)p->core.c_lp, 1);
+  const Core& cc = p->core;
+  if (cc.cgemm && split == 1 && cgemm_kind() == 2 && cg_class(cc) < kCgClasses) {
+    // digit rows, then product .. resolve in one workgroup
+    const CgLaunch cl = cgemm_launch(2 * (int64_t)cc.c_lp, 2 * (int64_t)cc.c_lp, 1);
     TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
-    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, (p->core.c_rta + p->core.c_rtb) * split,
-                                                        p->core.c_nlcap, s); }));
+    TM_HIP(timed_corr(s, [&] {
+      return launch_cgemm_inst(tab, nullptr, 1,
+                               cgemm_inst_lds_bytes(cc.c_lt, cc.c_lp, cc.c_nlcap, cc.c_rta + cc.c_rtb,
+                                                    std::max(cc.c_rta, cc.c_rtb)), s);
+    }));
+  } else if (cc.cgemm) {
+    const CgLaunch cl = cgemm_launch(2 * (int64_t)cc.c_lp, 2 * (int64_t)cc.c_lp, 1);
+    TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
+    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, (cc.c_rta + cc.c_rtb) * split,
+                                                        cc.c_nlcap, s); }));
     TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
   }
   else if (p->core.gfft) TM_HIP(launch_gfft(one, dev_one, s));
@@ -1175,148 +1205,348 @@ tm_status tm_match_noalloc(tm_plan p, const void* x, tm_result* out, void* strea
 // to out[0..count); with it the instances are the expanded list of a batch
 // with three-moduli plans: their results stay in device scratch and one
 // combine kernel writes out[0..cmb->size()).
-static tm_status run_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
-                           void* stream, const std::vector<Combine3>* cmb) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool dev_out = is_device_pointer(out);
-  const bool scratch_res = !dev_out || cmb;           // instance results in the pool
-  const int32_t n_user = cmb ? (int32_t)cmb->size() : count;
+// Host-side layout and launch parameters of one batch.
+struct BatchPlan {
+  int32_t count = 0, n_user = 0;
+  bool dev_out = false, scratch_res = false, use_inst = false;
+  std::vector<size_t> ws_off, acc_off;
+  std::vector<int32_t> seg_chunks, nseg, order;
+  size_t ws = 0, accb = 0, fold_lds = 0;
+  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, cps = 0, cp_max = 0, cgs = 0, cg_limbs_max = 0;
+  int32_t ncg_inst = 0;
+  // device layout: [instance workspaces][results][user results][table][lists][combine records]
+  size_t off_res = 0, off_ures = 0, off_tab = 0, tab_bytes = 0, off_lists = 0, list_bytes = 0, cmb_bytes = 0,
+         total = 0;
+};
 
-  // layout: [instance workspaces][results if host out][table][lists]
-  std::vector<size_t> ws_off(count), acc_off(count);
-  std::vector<int32_t> seg_chunks(count), nseg(count);
-  size_t ws = 0, accb = 0;
-  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, launch_bytes = 0, cps = 0, cp_max = 0, cgs = 0, cg_limbs_max = 0;
-  size_t fold_lds = 0;
+static tm_status plan_batch(int32_t count, const tm_plan* plans, bool dev_out, const std::vector<Combine3>* cmb,
+                            BatchPlan& b) {
+  b.count = count;
+  b.dev_out = dev_out;
+  b.scratch_res = !dev_out || cmb;           // instance results in the workspace
+  b.n_user = cmb ? (int32_t)cmb->size() : count;
+  b.ws_off.resize(count);
+  b.acc_off.resize(count);
+  b.seg_chunks.resize(count);
+  b.nseg.resize(count);
+  int64_t launch_bytes = 0;
   for (int32_t i = 0; i < count; ++i) launch_bytes += plans[i]->core.n * dtype_bytes(plans[i]->core.x_dtype);
   for (int32_t i = 0; i < count; ++i) {
     const Core& c = plans[i]->core;
-    ws_off[i] = ws;
-    ws += c.ws_bytes;
-    acc_off[i] = accb;
-    accb += c.acc_bytes;
-    tiles += c.ntiles;
-    seg_chunks[i] = c.seg_chunks;
-    nseg[i] = c.nseg;
+    b.ws_off[i] = b.ws;
+    b.ws += c.ws_bytes;
+    b.acc_off[i] = b.accb;
+    b.accb += c.acc_bytes;
+    b.tiles += c.ntiles;
+    b.seg_chunks[i] = c.seg_chunks;
+    b.nseg[i] = c.nseg;
     if (c.sfold) {
-      seg_chunks[i] = (int32_t)launch_seg_chunks(c, launch_bytes);
-      nseg[i] = segments_of(c.n, seg_chunks[i]);
+      b.seg_chunks[i] = (int32_t)launch_seg_chunks(c, launch_bytes);
+      b.nseg[i] = segments_of(c.n, b.seg_chunks[i]);
     }
-    segs += nseg[i];
-    bands += c.nband;
-    chunks += c.nred;
+    b.segs += b.nseg[i];
+    b.bands += c.nband;
+    b.chunks += c.nred;
     if (c.cgemm) {
-      cps += 2 * (int64_t)c.c_lp;
-      cp_max = std::max<int64_t>(cp_max, 2 * (int64_t)c.c_lp);
-      cgs = std::max<int64_t>(cgs, c.c_rta + c.c_rtb);
-      cg_limbs_max = std::max<int64_t>(cg_limbs_max, c.c_nlcap);
+      b.cps += 2 * (int64_t)c.c_lp;
+      b.cp_max = std::max<int64_t>(b.cp_max, 2 * (int64_t)c.c_lp);
+      b.cgs = std::max<int64_t>(b.cgs, c.c_rta + c.c_rtb);
+      b.cg_limbs_max = std::max<int64_t>(b.cg_limbs_max, c.c_nlcap);
     }
-    fold_lds = std::max(fold_lds, c.fold_lds);
+    b.fold_lds = std::max(b.fold_lds, c.fold_lds);
   }
-  if (tiles > 0x7fffffff || chunks > 0x7fffffff || segs > 0x7fffffff || bands > 0x7fffffff ||
-      cps > 0x7fffffff || cgs > 0x7fffffff)
+  if (b.tiles > 0x7fffffff || b.chunks > 0x7fffffff || b.segs > 0x7fffffff || b.bands > 0x7fffffff ||
+      b.cps > 0x7fffffff || b.cgs > 0x7fffffff)
     return fail(TM_ERR_UNSUPPORTED, "batch too large");
-  // the GEMM-correlation instances first (one launch sequence for all of
-  // them), then the finish launches grouped by (mode, FFT length) so each gets
-  // its own LDS size
-  std::vector<int32_t> order(count);
-  for (int32_t i = 0; i < count; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    const Core& ca = plans[a]->core;
-    const Core& cb = plans[b]->core;
+  // product kernel of the GEMM-correlation instances: per row tile, or per
+  // instance with its operands in LDS when asked for
+  int64_t cg_tasks = 0;
+  for (int32_t i = 0; i < count; ++i)
+    if (plans[i]->core.cgemm) cg_tasks += plans[i]->core.c_rta + plans[i]->core.c_rtb;
+  b.use_inst = cgemm_kind() == 2 && cg_tasks > 0;
+  // the GEMM-correlation instances first: by product-kernel LDS class, the
+  // largest first within a class (they start first); then the finish
+  // launches grouped by (mode, FFT length) so each gets its own LDS size
+  b.order.resize(count);
+  for (int32_t i = 0; i < count; ++i) b.order[i] = i;
+  const bool use_inst = b.use_inst;
+  std::stable_sort(b.order.begin(), b.order.end(), [&](int32_t x, int32_t y) {
+    const Core& ca = plans[x]->core;
+    const Core& cb = plans[y]->core;
     if (ca.cgemm != cb.cgemm) return ca.cgemm > cb.cgemm;
+    if (ca.cgemm && use_inst) {
+      const int ka = cg_class(ca), kb = cg_class(cb);
+      if (ka != kb) return ka < kb;
+      return (int64_t)ca.k * (ca.ma + ca.mb) > (int64_t)cb.k * (cb.ma + cb.mb);
+    }
     return ca.mode != cb.mode ? ca.mode < cb.mode : ca.p_log2 < cb.p_log2;
   });
-  const size_t off_res = align256(ws);
+  while (b.ncg_inst < count && plans[b.order[b.ncg_inst]]->core.cgemm) ++b.ncg_inst;
+  b.off_res = align256(b.ws);
   // combined user results staged on the device when out is host memory
-  const size_t off_ures = align256(off_res + (scratch_res ? sizeof(tm_result) * (size_t)count : 0));
-  const size_t off_tab = align256(off_ures + (cmb && !dev_out ? sizeof(tm_result) * (size_t)n_user : 0));
-  const size_t tab_bytes = sizeof(Inst) * (size_t)count;
-  const size_t off_lists = off_tab + tab_bytes;   // sizeof(Inst) keeps the list 16-byte aligned
-  const size_t list_bytes = align_up(sizeof(int32_t) * (size_t)count, 16);
-  const size_t cmb_bytes = cmb ? sizeof(Combine3) * cmb->size() : 0;
-  const size_t total = off_lists + list_bytes + cmb_bytes;
+  b.off_ures = align256(b.off_res + (b.scratch_res ? sizeof(tm_result) * (size_t)count : 0));
+  b.off_tab = align256(b.off_ures + (cmb && !dev_out ? sizeof(tm_result) * (size_t)b.n_user : 0));
+  b.tab_bytes = sizeof(Inst) * (size_t)count;
+  b.off_lists = b.off_tab + b.tab_bytes;   // sizeof(Inst) keeps the list 16-byte aligned
+  b.list_bytes = align_up(sizeof(int32_t) * (size_t)count, 16);
+  b.cmb_bytes = cmb ? sizeof(Combine3) * cmb->size() : 0;
+  b.total = b.off_lists + b.list_bytes + b.cmb_bytes;
+  return TM_OK;
+}
 
-  std::lock_guard<std::mutex> lock(g_mu);
-  StreamPool& pool = g_pools[{plans[0]->device, s}];
-  tm_status st = ensure_device(pool, total, s);
-  if (st != TM_OK) return st;
-  st = ensure_acc(pool, accb, s);
-  if (st != TM_OK) return st;
-  int slot = 0;
-  st = ensure_host(pool, tab_bytes + list_bytes + cmb_bytes, &slot);
-  if (st != TM_OK) return st;
-  char* base = static_cast<char*>(pool.dev);
-  Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
-  int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + tab_bytes);
-  if (cmb) std::memcpy(static_cast<char*>(pool.host[slot]) + tab_bytes + list_bytes, cmb->data(), cmb_bytes);
+// The instance table (host image) and the launch list for workspace `base`
+// and bucket zone `acc`.
+static void fill_batch(const BatchPlan& b, const tm_plan* plans, const void* const* xs, tm_result* out, char* base,
+                       char* acc, Inst* host_tab, int32_t* host_list) {
   int32_t tile_base = 0, red_base = 0, seg_base = 0, band_base = 0;
-  for (int32_t i = 0; i < count; ++i) {
+  for (int32_t i = 0; i < b.count; ++i) {
     const tm_plan_s* p = plans[i];
     Inst& in = host_tab[i];
     fill_inst(p, xs[i], &in);
-    place_workspace(p->core, base + ws_off[i], static_cast<char*>(pool.acc) + acc_off[i], &in);
+    place_workspace(p->core, base + b.ws_off[i], acc + b.acc_off[i], &in);
     in.tile_base = tile_base;
     in.red_base = red_base;
     in.seg_base = seg_base;
-    in.seg_chunks = seg_chunks[i];
-    in.nseg = nseg[i];
+    in.seg_chunks = b.seg_chunks[i];
+    in.nseg = b.nseg[i];
     in.band_base = band_base;
     tile_base += p->core.ntiles;
-    seg_base += nseg[i];
+    seg_base += b.nseg[i];
     band_base += p->core.nband;
     red_base += p->core.nred;
-    in.out = scratch_res ? reinterpret_cast<tm_result*>(base + off_res) + i : out + i;
-    host_list[i] = order[i];
+    in.out = b.scratch_res ? reinterpret_cast<tm_result*>(base + b.off_res) + i : out + i;
+    host_list[i] = b.order[i];
   }
-  TM_HIP(hipMemcpyAsync(base + off_tab, pool.host[slot], tab_bytes + list_bytes + cmb_bytes, hipMemcpyHostToDevice,
-                        s));
-  TM_HIP(hipEventRecord(pool.staged[slot], s));
-  pool.staged_pending[slot] = true;
+}
 
+// The kernels of one batch, in stream order, on the device table at
+// base + off_tab (host image host_tab): folds, the real path's reduction,
+// the correlation stage of the GEMM-correlation instances, the finish
+// launches, and the three-moduli combine.  `timed`: the fold and correlation
+// kernels carry the profiling events.
+static hipError_t launch_batch(const BatchPlan& b, const tm_plan* plans, const Inst* host_tab, char* base,
+                               tm_result* out, const std::vector<Combine3>* cmb, hipStream_t s, bool timed) {
   InstTable tab{};
-  tab.table = reinterpret_cast<const Inst*>(base + off_tab);
-  tab.count = count;
-  const int32_t* dlist = reinterpret_cast<const int32_t*>(base + off_lists);
+  tab.table = reinterpret_cast<const Inst*>(base + b.off_tab);
+  tab.count = b.count;
+  const int32_t* dlist = reinterpret_cast<const int32_t*>(base + b.off_lists);
+  const std::vector<int32_t>& order = b.order;
+  const int32_t ncg_inst = b.ncg_inst;
+  auto corr = [&](auto&& launch) { return timed ? timed_corr(s, launch) : launch(); };
   FoldWork fw;
-  fw.tiles = (int)tiles;
-  fw.lds = fold_lds;
-  fw.segs = (int)segs;
-  fw.bands = (int)bands;
-  TM_HIP(timed_fold(tab, fw, s));
-  pool.acc_dirty = true;                 // until every finish kernel is enqueued
-  TM_HIP(launch_reduce(tab, (int)chunks, s));
-  int32_t ncg_inst = 0;
-  while (ncg_inst < count && plans[order[ncg_inst]]->core.cgemm) ++ncg_inst;
-  if (ncg_inst > 0) {
-    const CgLaunch cl = cgemm_launch(cps, cp_max, ncg_inst);
-    TM_HIP(launch_cgemm_prep(tab, dlist, ncg_inst, cl.chunk, cl.prep_y, s));
-    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, dlist, ncg_inst, (int)cgs, (int)cg_limbs_max, s); }));
-    TM_HIP(launch_cgemm_final(tab, dlist, ncg_inst, s));
+  fw.tiles = (int)b.tiles;
+  fw.lds = b.fold_lds;
+  fw.segs = (int)b.segs;
+  fw.bands = (int)b.bands;
+  hipError_t e = timed ? timed_fold(tab, fw, s) : folds(tab, fw, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch_reduce(tab, (int)b.chunks, s)) != hipSuccess) return e;
+  if (ncg_inst > 0 && b.use_inst) {
+    // the digit rows of every instance, then per LDS class one launch of the
+    // per-instance kernel (product .. resolve, each launch with its class's
+    // largest footprint); the instances too large for its LDS, last in the
+    // order, by row tile with the final kernel
+    const CgLaunch cl = cgemm_launch(b.cps, b.cp_max, ncg_inst);
+    if ((e = launch_cgemm_prep(tab, dlist, ncg_inst, cl.chunk, cl.prep_y, s)) != hipSuccess) return e;
+    int32_t g0 = 0;
+    std::vector<std::pair<int32_t, int32_t>> groups;
+    while (g0 < ncg_inst && cg_class(plans[order[g0]]->core) < kCgClasses) {
+      const int k0 = cg_class(plans[order[g0]]->core);
+      int32_t g1 = g0;
+      while (g1 < ncg_inst && cg_class(plans[order[g1]]->core) == k0) ++g1;
+      groups.emplace_back(g0, g1);
+      g0 = g1;
+    }
+    const int32_t n_inst = g0;
+    e = corr([&] {
+      for (const auto& gr : groups) {
+        size_t lds = 0;
+        for (int32_t g = gr.first; g < gr.second; ++g) {
+          const Core& c = plans[order[g]]->core;
+          lds = std::max(lds, cgemm_inst_lds_bytes(c.c_lt, c.c_lp, c.c_nlcap, c.c_rta + c.c_rtb,
+                                                   std::max(c.c_rta, c.c_rtb)));
+        }
+        const hipError_t el = launch_cgemm_inst(tab, dlist + gr.first, gr.second - gr.first, lds, s);
+        if (el != hipSuccess) return el;
+      }
+      return hipSuccess;
+    });
+    if (e != hipSuccess) return e;
+    if (n_inst < ncg_inst) {
+      int64_t gy = 0, nl = 0;
+      for (int32_t g = n_inst; g < ncg_inst; ++g) {
+        const Core& c = plans[order[g]]->core;
+        gy = std::max<int64_t>(gy, c.c_rta + c.c_rtb);
+        nl = std::max<int64_t>(nl, c.c_nlcap);
+      }
+      const int32_t n_rest = ncg_inst - n_inst;
+      if ((e = launch_cgemm_gemm(tab, dlist + n_inst, n_rest, (int)gy, (int)nl, s)) != hipSuccess) return e;
+      if ((e = launch_cgemm_final(tab, dlist + n_inst, n_rest, s)) != hipSuccess) return e;
+    }
+  } else if (ncg_inst > 0) {
+    const CgLaunch cl = cgemm_launch(b.cps, b.cp_max, ncg_inst);
+    if ((e = launch_cgemm_prep(tab, dlist, ncg_inst, cl.chunk, cl.prep_y, s)) != hipSuccess) return e;
+    e = corr([&] { return launch_cgemm_gemm(tab, dlist, ncg_inst, (int)b.cgs, (int)b.cg_limbs_max, s); });
+    if (e != hipSuccess) return e;
+    if ((e = launch_cgemm_final(tab, dlist, ncg_inst, s)) != hipSuccess) return e;
   }
-  for (int32_t g0 = ncg_inst; g0 < count;) {
+  for (int32_t g0 = ncg_inst; g0 < b.count;) {
     const Core& c0 = plans[order[g0]]->core;
     int32_t g1 = g0 + 1;
-    while (g1 < count && plans[order[g1]]->core.mode == c0.mode && plans[order[g1]]->core.p_log2 == c0.p_log2) ++g1;
+    while (g1 < b.count && plans[order[g1]]->core.mode == c0.mode && plans[order[g1]]->core.p_log2 == c0.p_log2)
+      ++g1;
     if (c0.gfft) {   // one launch sequence per instance
-      for (int32_t g = g0; g < g1; ++g) TM_HIP(launch_gfft(host_tab[order[g]], tab.table + order[g], s));
+      for (int32_t g = g0; g < g1; ++g)
+        if ((e = launch_gfft(host_tab[order[g]], tab.table + order[g], s)) != hipSuccess) return e;
     } else {
-      TM_HIP(launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.p_log2, c0.finish_lds, s));
+      e = launch_finish(tab, dlist + g0, g1 - g0, c0.mode, c0.p_log2, c0.finish_lds, s);
+      if (e != hipSuccess) return e;
     }
     g0 = g1;
   }
-  pool.acc_dirty = false;
-  tm_result* user_dev = reinterpret_cast<tm_result*>(base + off_res);
   if (cmb) {
-    user_dev = dev_out ? out : reinterpret_cast<tm_result*>(base + off_ures);
-    TM_HIP(launch_combine3(reinterpret_cast<const Inst*>(base + off_tab),
-                           reinterpret_cast<const Combine3*>(base + off_lists + list_bytes),
-                           reinterpret_cast<const tm_result*>(base + off_res), user_dev, n_user, s));
+    tm_result* user_dev = b.dev_out ? out : reinterpret_cast<tm_result*>(base + b.off_ures);
+    e = launch_combine3(reinterpret_cast<const Inst*>(base + b.off_tab),
+                        reinterpret_cast<const Combine3*>(base + b.off_lists + b.list_bytes),
+                        reinterpret_cast<const tm_result*>(base + b.off_res), user_dev, b.n_user, s);
+    if (e != hipSuccess) return e;
   }
-  if (!dev_out) {
-    TM_HIP(hipMemcpyAsync(out, user_dev, sizeof(tm_result) * (size_t)n_user, hipMemcpyDeviceToHost, s));
+  return hipSuccess;
+}
+
+static tm_status run_batch(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out,
+                           void* stream, const std::vector<Combine3>* cmb) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BatchPlan b;
+  tm_status st = plan_batch(count, plans, is_device_pointer(out), cmb, b);
+  if (st != TM_OK) return st;
+  std::lock_guard<std::mutex> lock(g_mu);
+  StreamPool& pool = g_pools[{plans[0]->device, s}];
+  st = ensure_device(pool, b.total, s);
+  if (st != TM_OK) return st;
+  st = ensure_acc(pool, b.accb, s);
+  if (st != TM_OK) return st;
+  int slot = 0;
+  st = ensure_host(pool, b.tab_bytes + b.list_bytes + b.cmb_bytes, &slot);
+  if (st != TM_OK) return st;
+  char* base = static_cast<char*>(pool.dev);
+  Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
+  int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + b.tab_bytes);
+  if (cmb) std::memcpy(static_cast<char*>(pool.host[slot]) + b.tab_bytes + b.list_bytes, cmb->data(), b.cmb_bytes);
+  fill_batch(b, plans, xs, out, base, static_cast<char*>(pool.acc), host_tab, host_list);
+  TM_HIP(hipMemcpyAsync(base + b.off_tab, pool.host[slot], b.tab_bytes + b.list_bytes + b.cmb_bytes,
+                        hipMemcpyHostToDevice, s));
+  TM_HIP(hipEventRecord(pool.staged[slot], s));
+  pool.staged_pending[slot] = true;
+  pool.acc_dirty = true;                 // until every kernel that restores the buckets is enqueued
+  TM_HIP(launch_batch(b, plans, host_tab, base, out, cmb, s, true));
+  pool.acc_dirty = false;
+  if (!b.dev_out) {
+    tm_result* user_dev = reinterpret_cast<tm_result*>(base + (cmb ? b.off_ures : b.off_res));
+    TM_HIP(hipMemcpyAsync(out, user_dev, sizeof(tm_result) * (size_t)b.n_user, hipMemcpyDeviceToHost, s));
     TM_HIP(hipStreamSynchronize(s));
   }
+  return TM_OK;
+}
+
+// ---------------------------------------------------------------- reusable batches
+
+struct tm_batch_s {
+  int device = 0;
+  BatchPlan plan;
+  void* dev = nullptr;           // workspace, results, table and list
+  void* acc = nullptr;           // bucket zone (zero between launches)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(tm_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->dev) (void)hipFree(b->dev);
+  if (b->acc) (void)hipFree(b->acc);
+  delete b;
+}
+
+tm_status tm_batch_create(int32_t count, const tm_plan* plans, const void* const* xs, tm_result* out, void* stream,
+                          tm_batch* res) {
+  if (!res) return fail(TM_ERR_INVALID, "null batch output");
+  *res = nullptr;
+  if (count < 1) return fail(TM_ERR_INVALID, "count must be >= 1");
+  if (!plans || !xs || !out) return fail(TM_ERR_INVALID, "null argument");
+  for (int32_t i = 0; i < count; ++i) {
+    tm_status st = check_plan_for_match(plans[i]);
+    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+    st = check_x(plans[i], xs[i]);
+    if (st != TM_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+    if (plans[i]->core.three) return fail(TM_ERR_UNSUPPORTED, "tm_batch_create: three-moduli plans are not supported");
+    if (plans[i]->device != plans[0]->device) return fail(TM_ERR_INVALID, "plans on different devices");
+  }
+  if (!is_device_pointer(out)) return fail(TM_ERR_INVALID, "tm_batch_create: out must be device memory");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tm_batch_s* b = new tm_batch_s();
+  b->device = plans[0]->device;
+  tm_status st = plan_batch(count, plans, true, nullptr, b->plan);
+  if (st != TM_OK) { delete b; return st; }
+  const BatchPlan& bp = b->plan;
+  std::vector<Inst> tab((size_t)count);
+  std::vector<int32_t> list((size_t)count);
+  hipStream_t cs = nullptr;
+  auto bail = [&](tm_status code, const std::string& msg) {
+    if (cs) {
+      hipGraph_t g = nullptr;
+      hipStreamCaptureStatus cst;
+      if (hipStreamIsCapturing(cs, &cst) == hipSuccess && cst == hipStreamCaptureStatusActive)
+        (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+    }
+    batch_free(b);
+    return fail(code, msg);
+  };
+#define TM_HIP_B(expr)                                                                  \
+  do {                                                                                  \
+    const hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) return bail(TM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  TM_HIP_B(hipMalloc(&b->dev, std::max<size_t>(bp.total, 256)));
+  TM_HIP_B(hipMalloc(&b->acc, std::max<size_t>(bp.accb, 256)));
+  fill_batch(bp, plans, xs, out, static_cast<char*>(b->dev), static_cast<char*>(b->acc), tab.data(), list.data());
+  char* base = static_cast<char*>(b->dev);
+  TM_HIP_B(hipMemcpyAsync(base + bp.off_tab, tab.data(), bp.tab_bytes, hipMemcpyHostToDevice, s));
+  TM_HIP_B(hipMemcpyAsync(base + bp.off_lists, list.data(), sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, s));
+  // the buckets start at zero; every replay leaves them at zero again (no
+  // memset inside the graph)
+  TM_HIP_B(hipMemsetAsync(b->acc, 0, std::max<size_t>(bp.accb, 256), s));
+  TM_HIP_B(hipStreamSynchronize(s));
+  // capture the kernels on a private stream, untimed
+  TM_HIP_B(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  TM_HIP_B(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  TM_HIP_B(launch_batch(bp, plans, tab.data(), base, out, nullptr, cs, false));
+  {
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess) return bail(TM_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    b->graph = g;
+  }
+  TM_HIP_B(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  (void)hipStreamDestroy(cs);
+  cs = nullptr;
+#undef TM_HIP_B
+  *res = b;
+  return TM_OK;
+}
+
+tm_status tm_batch_launch(tm_batch b, void* stream) {
+  if (!b || !b->exec) return fail(TM_ERR_INVALID, "null batch");
+  TM_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+  return TM_OK;
+}
+
+tm_status tm_batch_destroy(tm_batch b) {
+  if (!b) return TM_OK;
+  TM_HIP(hipDeviceSynchronize());
+  batch_free(b);
   return TM_OK;
 }
 

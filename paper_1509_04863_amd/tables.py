@@ -98,23 +98,31 @@ def table1(trials: int, log2ns=(23, 24, 25, 26, 27), progress=True, top_t=1):
     return rows
 
 
-def table2(trials: int, snrs=(20, 10, 6, 1, -2, -6), log2n=26, log2k=16, progress=True, top_t=1):
+def table2_trial(snr: float, trial: int, n: int, k: int):
+    """One trial of the noise experiment on the device: a +-1 signal x, a
+    uniform shift m, the template t cut from the clean x at m, and the observed
+    signal x_e = x + e with e ~ N(0, sigma^2), sigma = 10^(-SNR/20) for the unit
+    power of x.  Returns (x_e, t, m) with x_e and t as fp32 device tensors."""
     import torch
+    sigma = 10.0 ** (-snr / 20.0)
+    g = _gen(2, int(snr) + 100, trial)
+    x = _rademacher(n, g)
+    m = int(torch.randint(0, n, (1,), generator=g, device="cuda").item())
+    t = _window(x, m, k).to(torch.float32)
+    xe = x.to(torch.float32) + sigma * torch.randn(n, generator=g, device="cuda", dtype=torch.float32)
+    return xe, t, m
 
+
+def table2(trials: int, snrs=(20, 10, 6, 1, -2, -6), log2n=26, log2k=16, progress=True, top_t=1):
     from paper_1509_04863_amd import tm
     n, k = 1 << log2n, 1 << log2k
     m1, m2 = k, k + 1
     rows = []
     for snr in snrs:
-        sigma = 10.0 ** (-snr / 20.0)
         hits = 0
         t0 = time.perf_counter()
         for trial in range(trials):
-            g = _gen(2, snr + 100, trial)
-            x = _rademacher(n, g)
-            m = int(torch.randint(0, n, (1,), generator=g, device="cuda").item())
-            t = _window(x, m, k).to(torch.float32)
-            xe = x.to(torch.float32) + sigma * torch.randn(n, generator=g, device="cuda", dtype=torch.float32)
+            xe, t, m = table2_trial(snr, trial, n, k)
             plan = tm.Plan(t, n=n, m1=m1, m2=m2, top_t=top_t)
             r = tm.match(plan, xe)
             hits += int(r.shift == m)

@@ -27,7 +27,8 @@ EXPORTS = ["tm_plan_params", "tm_plan_create", "tm_plan_destroy", "tm_plan_get_i
            "tm_match_batch", "tm_match_intermediates", "tm_status_string", "tm_last_error",
            "tm_version", "tm_profile_enable", "tm_profile_read", "tm_server_create", "tm_server_submit",
            "tm_server_poll", "tm_server_wait", "tm_server_get_stats", "tm_server_destroy",
-           "tm_admit_batches", "tm_match_many", "tm_profile_read_corr", "tm_match_noalloc"]
+           "tm_admit_batches", "tm_match_many", "tm_profile_read_corr", "tm_match_noalloc",
+           "tm_batch_create", "tm_batch_launch", "tm_batch_destroy"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -66,6 +67,7 @@ class ServerStats(ctypes.Structure):
 
 
 assert ctypes.sizeof(Result) == 48 and ctypes.sizeof(PlanDesc) == 48
+RESULT_BYTES = ctypes.sizeof(Result)
 
 RESULT_DTYPE = np.dtype([("shift", "<i8"), ("m1_tilde", "<i4"), ("m2_tilde", "<i4"),
                          ("n_candidates", "<i4"), ("flags", "<u4"), ("peak1", "<f8"),
@@ -123,6 +125,11 @@ def lib():
         L.tm_match_many.restype = ctypes.c_int
         L.tm_match_noalloc.argtypes = [vp, vp, vp, vp]
         L.tm_match_noalloc.restype = ctypes.c_int
+        L.tm_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, ctypes.POINTER(vp)]
+        L.tm_batch_launch.argtypes = [vp, vp]
+        L.tm_batch_destroy.argtypes = [vp]
+        for fn in ("tm_batch_create", "tm_batch_launch", "tm_batch_destroy"):
+            getattr(L, fn).restype = ctypes.c_int
         for fn in ("tm_server_create", "tm_server_submit", "tm_server_poll", "tm_server_wait",
                    "tm_server_get_stats", "tm_server_destroy", "tm_admit_batches"):
             getattr(L, fn).restype = ctypes.c_int
@@ -391,6 +398,40 @@ class Batch:
         _check_out(out, self.count)
         _check(lib().tm_match_batch(self.count, self._p, self._x, out.data_ptr(),
                                     _stream_handle(stream)))
+
+
+class BatchGraph:
+    """tm_batch_*: a fixed list of (plan, signal) pairs whose launch sequence
+    is captured once in a HIP graph; run() replays it, writing the results
+    into the device buffer `out` given at creation."""
+
+    def __init__(self, plans: Sequence[Plan], xs: Sequence, out, stream=None):
+        if len(plans) != len(xs):
+            raise ValueError("plans and xs differ in length")
+        for p, x in zip(plans, xs):
+            _check_signal(p, x)
+        self.count = len(plans)
+        _check_out(out, self.count)
+        self.plans, self.xs, self.out = list(plans), list(xs), out     # kept alive with the graph
+        parr = (ctypes.c_void_p * self.count)(*[p.handle.value for p in plans])
+        xarr = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in xs])
+        self.handle = ctypes.c_void_p()
+        _check(lib().tm_batch_create(self.count, parr, xarr, out.data_ptr(), _stream_handle(stream),
+                                     ctypes.byref(self.handle)))
+
+    def run(self, stream=None):
+        _check(lib().tm_batch_launch(self.handle, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _check(lib().tm_batch_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def match_intermediates(plan: Plan, x, stream=None):

@@ -1,11 +1,12 @@
 """Parity on the launch shapes the headline workloads run.
 
-* The product kernel's 4-wave variant, which launches of 512 or more product
-  workgroups select (a batch of uneven int8 instances, N up to 2^20 and K up
-  to 2^12): forced with TM_CGEMM_WAVES=4 on single matches of every digit
-  count, swapped and explicit moduli and top-T, and reached naturally by a
-  batch of 160 uneven instances.  Every result field against the oracle
-  (Algorithm 1 steps 2-9), and y / r bit for bit on a sample.
+* The product kernels that launches of 512 or more product workgroups run (a
+  batch of uneven int8 instances, N up to 2^20 and K up to 2^12): the
+  per-instance kernel with its operands in LDS and the per-row-tile kernel's
+  4-wave variant, each forced onto single matches of every digit count,
+  swapped and explicit moduli and top-T, and reached by a batch of 160 uneven
+  instances.  Every result field against the oracle (Algorithm 1 steps 2-9),
+  and y / r bit for bit on a sample.
 * The precision workload at its stated size: N = 2^24 fp32 N(0,1), K = 2^14,
   template at -3 dB, the fold stored as FP32, BF16 or FP16; r normwise against
   the oracle's FP64 correlation of the same stored fold values, and the argmax
@@ -34,13 +35,25 @@ def _case(*a):
 
 # ------------------------------------------------------------ 4-wave product
 
+# the product kernels a batch can run: per row tile with 4 waves (forced), and
+# per instance with its operands in LDS (forced onto single matches)
+KERNELS = {"row-tile 4 waves": ("TM_CGEMM_WAVES", "4"), "per instance": ("TM_CGEMM_KIND", "2")}
+
+
+@pytest.fixture(params=list(KERNELS))
+def product_kernel(request, monkeypatch):
+    monkeypatch.setenv(*KERNELS[request.param])
+    return request.param
+
+
 @pytest.mark.parametrize("lo,hi,n,k,label", [
     (-1, 2, 60000, 700, "1-2 digits"),
     (-128, 128, 3 << 16, 700, "3 digits (int8 extremes)"),
     (-1, 2, 1 << 20, 4096, "config-3 largest shape"),
+    (-1, 2, 70000, 512, "one row tile per fold (split band)"),
+    (-1, 2, 3000, 37, "tiny"),
 ])
-def test_four_wave_product_int8(lo, hi, n, k, label, monkeypatch):
-    monkeypatch.setenv("TM_CGEMM_WAVES", "4")
+def test_four_wave_product_int8(lo, hi, n, k, label, product_kernel):
     rng = np.random.default_rng(n + k + 1)
     x = rng.integers(lo, hi, n).astype(np.int8)
     if hi > 2:
@@ -48,35 +61,48 @@ def test_four_wave_product_int8(lo, hi, n, k, label, monkeypatch):
     x[x == 0] = 1
     t = x[1234:1234 + k].copy()
     t[rng.choice(k, k // 10, replace=False)] *= -1
-    _case("4 waves", label, n, k)
+    _case(product_kernel, label, n, k)
+    assert_exact_parity(x, t)
+
+
+@pytest.mark.parametrize("n,k", [(200000, 300), (60000, 500)])
+def test_folds_with_different_digit_counts(n, k, product_kernel):
+    # every M1-th sample is 127: one bucket of the M1 fold sums L of them
+    # (three base-128 digits) while the M2 fold spreads them over distinct
+    # buckets (two digits), so the two folds of one instance use different
+    # digit counts, with the band split over waves (one or two row tiles)
+    m1, _ = O.choose_moduli(n, k)
+    rng = np.random.default_rng(n + k)
+    x = rng.choice(np.array([-1, 1], dtype=np.int8), n)
+    x[::m1] = 127
+    t = x[777:777 + k].copy()
+    _case(product_kernel, "unequal digits", n, k, m1)
     assert_exact_parity(x, t)
 
 
 @pytest.mark.parametrize("scale,label", [(3000, "4 digits"), (1000000, "5 digits")])
-def test_four_wave_product_wide_digits(scale, label, monkeypatch):
+def test_four_wave_product_wide_digits(scale, label, product_kernel):
     # fp32 integer signals whose folds need four and five base-128 digits
-    monkeypatch.setenv("TM_CGEMM_WAVES", "4")
     rng = np.random.default_rng(scale + 7)
     n, k = 200000, 500
     x = np.full(n, scale, dtype=np.float32)
     x[rng.choice(n, n // 100, replace=False)] = -scale
     t = np.zeros(k, dtype=np.float32)
     t[rng.choice(k, 5, replace=False)] = rng.choice([-127.0, 127.0], 5)
-    _case("4 waves", label)
+    _case(product_kernel, label)
     assert_exact_parity(x, t, flags=tm.TM_F_EXACT)
 
 
-def test_four_wave_product_moduli_and_top_t(monkeypatch):
-    monkeypatch.setenv("TM_CGEMM_WAVES", "4")
+def test_four_wave_product_moduli_and_top_t(product_kernel):
     inst = G.planted_pm1(300000, 600, config_id=93, index=0, flip_frac=0.05, shift=299000)
-    _case("4 waves swapped")
+    _case(product_kernel, "swapped")
     assert_exact_parity(inst.x, inst.t, m1=701, m2=700)
-    _case("4 waves non-consecutive")
+    _case(product_kernel, "non-consecutive")
     assert_exact_parity(inst.x, inst.t, m1=1000, m2=1003)
     for top_t in (2, 4):
         plan = tm.Plan(inst.t, n=inst.n, top_t=top_t)
         assert plan.info["corr_gemm"] == 1
-        _case("4 waves top-T", top_t)
+        _case(product_kernel, "top-T", top_t)
         res, y1, y2, r1, r2 = tm.match_intermediates(plan, to_device(inst.x))
         ref = O.ftm(inst.x, inst.t, plan.m1, plan.m2, top_t=top_t)
         assert np.array_equal(r1, ref.r1.astype(np.float64))
@@ -104,14 +130,16 @@ def _row_tiles(m):
     return (rows + 15) // 16
 
 
-def test_large_batch_four_wave_route():
+@pytest.mark.parametrize("kind", ["0", "2"], ids=["row-tile kernel (default)", "per-instance kernel"])
+def test_large_batch_four_wave_route(kind, monkeypatch):
+    monkeypatch.setenv("TM_CGEMM_KIND", kind)
     insts = _uneven_batch(160, 11)
     plans = [tm.Plan(s.t, n=s.n) for s in insts]
     assert all(p.info["corr_gemm"] for p in plans)
     tasks = max(_row_tiles(p.m1) + _row_tiles(p.m2) for p in plans)
     assert len(plans) * tasks >= 512, "the launch must take the 4-wave variant"
     xs = [to_device(s.x) for s in insts]
-    _case("large batch", len(insts), "product workgroups", len(plans) * tasks)
+    _case("large batch", kind, len(insts), "product workgroups", len(plans) * tasks)
     batch = tm.match_batch(plans, xs)
     single = [tm.match(p, x) for p, x in zip(plans, xs)]
     assert batch == single
@@ -124,13 +152,12 @@ def test_large_batch_four_wave_route():
         assert b.flags & tm.TM_R_EXACT
 
 
-def test_large_batch_intermediates_sample(monkeypatch):
-    # the intermediates of a sample of the batch's shapes, bit for bit, with
-    # the 4-wave variant forced (a single match would otherwise take 8 waves)
-    monkeypatch.setenv("TM_CGEMM_WAVES", "4")
+def test_large_batch_intermediates_sample(product_kernel):
+    # the intermediates of a sample of the batch's shapes, bit for bit, on the
+    # kernels a large batch runs (a single match would otherwise take 8 waves)
     insts = _uneven_batch(160, 11)
     for inst in (insts[0], insts[17], insts[101]):
-        _case("sample", inst.index, inst.n, inst.k)
+        _case(product_kernel, "sample", inst.index, inst.n, inst.k)
         assert_exact_parity(inst.x, inst.t)
 
 
