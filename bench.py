@@ -447,9 +447,10 @@ def cpu_precision_leg(plans, xs, insts, count):
 
     from oracle import ftm as O
     from paper_1509_04863_amd import tm
-    errs, agree, busy = [], 0, 0.0
+    errs, agree, busy, bounds = [], 0, 0.0, []
     for i in range(min(count, len(plans))):
         res, y1, y2, r1, r2 = tm.match_intermediates(plans[i], xs[i])
+        bounds.append(res.err_bound)
         t0 = time.perf_counter()
         ref = O.ftm(insts[i].x.astype(np.float64), insts[i].t.astype(np.float64), plans[i].m1, plans[i].m2,
                     correlation="fft")
@@ -457,7 +458,8 @@ def cpu_precision_leg(plans, xs, insts, count):
         errs.append(max(float(np.max(np.abs(r1 - ref.r1)) / np.max(np.abs(ref.r1))),
                         float(np.max(np.abs(r2 - ref.r2)) / np.max(np.abs(ref.r2)))))
         agree += int((res.m1_tilde, res.m2_tilde, res.shift) == (ref.m1_tilde, ref.m2_tilde, ref.shift))
-    return {"normwise_r_error_vs_fp64": errs, "argmax_and_shift_agree_with_fp64": "%d/%d" % (agree, len(errs)),
+    return {"normwise_r_error_vs_fp64": errs, "result_err_bound": bounds,
+            "argmax_and_shift_agree_with_fp64": "%d/%d" % (agree, len(errs)),
             "oracle_matches_per_s_one_core": len(errs) / busy if busy > 0 else None}
 
 

@@ -130,7 +130,17 @@ typedef struct {
   double   peak2;        /* r_M2[m2_tilde] */
   double   score;        /* (Tx)_shift: exact integer on the exact path, FP64 sum
                             otherwise; 0 when shift = -1 */
-} tm_result;             /* 48 bytes */
+  double   err_bound;    /* real path: a bound on max_k |r_i[k] - r*_i[k]| over both
+                            folds, where r* is the correlation in exact arithmetic of
+                            the FP32 fold sums: the FP32 transform's rounding
+                            ((14 p + 8) 2^-24 ||FFT(t)||_inf ||z||_2 for a transform of
+                            2^p points, p + 2 on the four-step route) plus the fold's
+                            BF16/FP16 storage rounding (||t||_2 u_s ||z||_2, u_s =
+                            2^-8 or 2^-11), with z = y1 + i y2 the stored folds.  The
+                            rounding of the FP32 fold sums themselves (L terms each) is
+                            not included.  0 on the exact path. */
+  int64_t  reserved;     /* 0 */
+} tm_result;             /* 64 bytes */
 
 /* Host-side plan parameters (no GPU needed). */
 typedef struct {

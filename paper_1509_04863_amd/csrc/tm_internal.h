@@ -90,6 +90,8 @@ struct alignas(16) Inst {
   const void* spec;       // P complex values: conj(FFT_P(t)) / P at bit-reversed positions
   const void* tw;         // P/2 complex values W^e = exp(-2 pi i e / P)
   double tnorm1;          // sum |t_j|
+  double tspec_max;       // max_k |FFT_P(t)[k]| (real plans; for the results' error bound)
+  double tnorm2;          // ||t||_2
   tm_result* out;         // device result slot
   double* dbg_y1;         // optional intermediates (user order), may be null
   double* dbg_y2;
@@ -254,6 +256,10 @@ hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int coun
 hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
                              hipStream_t s);
 hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s);
+// batches: one wave per row tile over the whole band (gemm_y row tiles per
+// instance at most, four per workgroup), per-column-tile bests to cpart
+hipError_t launch_cgemm_wave(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
+                             hipStream_t s);
 // batches: the correlation stage with one workgroup per instance (literal
 // folds, product with its operands in LDS, argmaxes, resolve; no prep or
 // final kernel); `lds` bytes: the largest cgemm_inst_lds_bytes of the listed

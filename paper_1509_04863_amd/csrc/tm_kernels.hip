@@ -481,7 +481,8 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
 #pragma unroll
   for (int s = 0; s < NSL; ++s) { lo[s] = 0; hi[s] = 0; }
 
-  // prologue: the first two pieces' loads in flight together
+  // prologue: the first two pieces' loads in flight together; while piece
+  // j's rows are folded, the load of piece j + 2 is in flight
   uint4 v[kSegLoads];
   {
     uint4 v1[kSegLoads];
@@ -493,7 +494,8 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
   if (nstage > 2) seg_load(g, 2, v);
   __syncthreads();
 
-  for (int j = 0; j < nproc; ++j) {
+  // the rows that start in piece j (ring slot j & 1)
+  auto piece_rows = [&](int j) {
     const int64_t Bp = B0 + (int64_t)j * kSegPiece;
     const int64_t Bend = min(Bp + kSegPiece, B1);
     const int ring = (j & 1) * kSegPiece;              // LDS offset of byte b: ring + (b - Bp)
@@ -536,6 +538,9 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
     if (rest > 2) row(2, full);
     k += nr;
     rb += (int64_t)nr * M;
+  };
+  for (int j = 0; j < nproc; ++j) {
+    piece_rows(j);
     __syncthreads();
     if (j + 2 < nstage) {
       seg_store(g, N, j + 2, v, lds);
@@ -1262,7 +1267,7 @@ __device__ __forceinline__ FinRed block_finred(FinRed mine, FinRed* scratch) {
 // result record.
 template <typename Tin>
 __device__ __forceinline__ void resolve_lists(const Inst& d, const VI* A, int na, const VI* B, int nb, uint32_t flags,
-                              void* scratch) {
+                              void* scratch, double err_bound = 0.0) {
   const int tid = threadIdx.x;
   const int ma = d.va.m, mb = d.vb.m;
   __shared__ long long cand[3 * kTopTMax * kTopTMax];
@@ -1320,12 +1325,28 @@ __device__ __forceinline__ void resolve_lists(const Inst& d, const VI* A, int na
     r->peak1 = d.swapped ? bmax.v : amax.v;
     r->peak2 = d.swapped ? amax.v : bmax.v;
     r->score = nc ? best_score : 0.0;
+    r->err_bound = err_bound;
+    r->reserved = 0;
   }
 }
 
 template <typename Tin>
-__device__ __forceinline__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
-  resolve_lists<Tin>(d, &amax, 1, &bmax, 1, flags, scratch);
+__device__ __forceinline__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch,
+                                                   double err_bound = 0.0) {
+  resolve_lists<Tin>(d, &amax, 1, &bmax, 1, flags, scratch, err_bound);
+}
+
+// Error bound of a real plan's correlations (FP32 transform of 2^stages
+// points, the BF16/FP16 storage of the fold) given ||z||_2 of the stored
+// folds: the rounding of a radix-2^k FFT of 2^p points is at most
+// p (mu + gamma_4 (sqrt 2 + mu)) of ||FFT z||_2 with mu <= 2u the twiddles'
+// error, about 7 p u; the forward transform, the product with the stored
+// spectrum and the inverse transform give (14 p + 8) u ||FFT(t)||_inf ||z||_2
+// (u = 2^-24); stored fold values off by u_s |y| move each r[k] by at most
+// u_s sum_j |t_j| |y_{k+j}| <= u_s ||t||_2 ||z||_2 (Cauchy-Schwarz).
+__device__ __forceinline__ double real_err_bound(const Inst& d, int stages, double znorm2) {
+  const double us = d.fold_store == TM_BF16 ? 0x1p-8 : (d.fold_store == TM_F16 ? 0x1p-11 : 0.0);
+  return ((14.0 * stages + 8.0) * 0x1p-24 * d.tspec_max + d.tnorm2 * us) * sqrt(znorm2);
 }
 
 // Runners-up of one fold for top-T (reading of the option: value descending,
@@ -1359,7 +1380,8 @@ __device__ __forceinline__ int block_top_t(F value_of, int m, int T, VI (&top)[k
 // top-T re-scoring from the whole correlations in `rtop` (fold A at 0, fold B
 // at ma), given both argmaxes
 template <typename Tin>
-__device__ __forceinline__ void resolve_top_t(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch) {
+__device__ __forceinline__ void resolve_top_t(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch,
+                                              double err_bound = 0.0) {
   const int ma = d.va.m, mb = d.vb.m;
   const GAS double* r = G(d.rtop);
   VI A[kTopTMax], B[kTopTMax];
@@ -1367,7 +1389,7 @@ __device__ __forceinline__ void resolve_top_t(const Inst& d, VI amax, VI bmax, u
   B[0] = bmax;
   const int na = block_top_t([&](int n) { return r[n]; }, ma, d.top_t, A, reinterpret_cast<VI*>(scratch));
   const int nb = block_top_t([&](int n) { return r[ma + n]; }, mb, d.top_t, B, reinterpret_cast<VI*>(scratch));
-  resolve_lists<Tin>(d, A, na, B, nb, flags, scratch);
+  resolve_lists<Tin>(d, A, na, B, nb, flags, scratch, err_bound);
 }
 
 template <typename T, typename Tin>
@@ -1511,6 +1533,7 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
   VI* vs = reinterpret_cast<VI*>(scratch);
 
   uint32_t flags = 0;
+  const double err = exact ? 0.0 : real_err_bound(d, p, znorm2);
   if (!exact) {
     // near tie: second largest (excluding the argmax) within 1e-5 of the fold's peak scale
     VI sa{-INFINITY, 0x7fffffff}, sb{-INFINITY, 0x7fffffff};
@@ -1544,10 +1567,10 @@ __device__ __forceinline__ void finish_instance(const Inst& d, unsigned char* ld
       return exact ? rint((double)buf[padi(n)].x) : (double)buf[padi(n)].x; }, ma, d.top_t, A, vs);
     const int nb = block_top_t([&](int n) {
       return exact ? rint((double)buf[padi(n)].y) : (double)buf[padi(n)].y; }, mb, d.top_t, B, vs);
-    resolve_lists<Tin>(d, A, na, B, nb, flags, scratch);
+    resolve_lists<Tin>(d, A, na, B, nb, flags, scratch, err);
     return;
   }
-  resolve_and_report<Tin>(d, amax, bmax, flags, scratch);
+  resolve_and_report<Tin>(d, amax, bmax, flags, scratch, err);
 }
 
 template <typename T>
@@ -1837,8 +1860,10 @@ __global__ void __launch_bounds__(kGfftThreads) k_gfft_final(InstTable tab) {
   } else if (a.v1 - a.v2 <= 1e-5 * a.mag || b.v1 - b.v2 <= 1e-5 * b.mag) {
     flags |= TM_R_NEAR_TIE;
   }
-  if (d.top_t > 1) resolve_top_t<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch);
-  else resolve_and_report<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch);
+  // the two twiddle products of the four-step transform count as two more stages
+  const double err = d.mode == MODE_EXACT ? 0.0 : real_err_bound(d, d.p_log2 + 2, zn2);
+  if (d.top_t > 1) resolve_top_t<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch, err);
+  else resolve_and_report<Tin>(d, VI{a.v1, a.i1}, VI{b.v1, b.i1}, flags, scratch, err);
 }
 
 template <typename T, typename Tin>
@@ -2453,6 +2478,97 @@ __global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_
 }
 
 // --------------------------------------------------------------------------
+// the same product for batches: one wave per row tile
+// --------------------------------------------------------------------------
+//
+// Each wave computes one 16 x 64 row tile of one fold over the whole band
+// (all steps, every digit, the four column tiles) and writes the best of each
+// column tile to cpart, so no partial sums meet across waves; the four waves
+// of a workgroup take consecutive row tiles of one instance, which read the
+// same template copies through the compute unit's cache.  For batches, whose
+// many row tiles fill the machine without splitting a band over waves.
+
+template <int NL>
+__device__ __forceinline__ void cg2_report(const Inst& d, int f, int rt, const int* red, const v4i_t (&acc)[NL][4],
+                                           VI* tbest);
+
+template <int NL>
+__device__ __forceinline__ void cgw_tile(const Inst& d, int f, int rt) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15, g = lane >> 4;
+  const int M = f ? d.vb.m : d.va.m;
+  const int ntc = min(4, (M - 1024 * rt + 15) >> 4);
+  const int lp = d.c_lp, KS = d.c_ks;
+  const GAS int8_t* arow = G(d.ylimb) + (int64_t)f * d.c_nlcap * lp + 64 * (kCgRows * rt + c) + 16 * g;
+  const GAS int8_t* tsh = G(d.tsh);
+  auto ld_b = [&](int st, int nt) {
+    const int j = 64 * st + 16 * g - (16 * nt + c) + kCgPad;
+    const int sh = (-j) & 15;
+    return *reinterpret_cast<const GAS v4i_t*>(tsh + (((j + sh) >> 4) * 16 + sh) * 16);
+  };
+  auto ld_a = [&](int st, int l) { return *reinterpret_cast<const GAS v4i_t*>(arow + (int64_t)l * lp + 64 * st); };
+  v4i_t acc[NL][4];
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
+  v4i_t bc[4], ac[NL];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) bc[nt] = ld_b(0, nt);
+#pragma unroll
+  for (int l = 0; l < NL; ++l) ac[l] = ld_a(0, l);
+  for (int st = 0; st < KS; ++st) {
+    // the next step's operands are in flight during this step's products
+    v4i_t bn[4], an[NL];
+    const int sn = min(st + 1, KS - 1);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bn[nt] = ld_b(sn, nt);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) an[l] = ld_a(sn, l);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      if (nt < ntc) {                         // uniform over the wave
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+          acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ac[l], bc[nt], acc[l][nt], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bc[nt] = bn[nt];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) ac[l] = an[l];
+  }
+  cg2_report<NL>(d, f, rt, nullptr, acc, nullptr);
+}
+
+// grid (instances, groups of four row tiles), one row tile per wave
+template <int MAXNL>
+__global__ void __launch_bounds__(256) k_cgemm_wave(InstTable tab, const int32_t* list) {
+  const Inst& d = list ? tab.table[list[blockIdx.x]] : tab.resident();
+  const int task = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (task >= d.c_rta + d.c_rtb) return;          // no barriers in this kernel
+  const int f = task >= d.c_rta ? 1 : 0;
+  const int rt = task - f * d.c_rta;
+  const int nl = min(min(cg_limbs(G(d.cmax)[f]), d.c_nlcap), MAXNL);
+  switch (nl) {
+    case 1: cgw_tile<1>(d, f, rt); break;
+    case 2: cgw_tile<2>(d, f, rt); break;
+    case 3: cgw_tile<3>(d, f, rt); break;
+    case 4: if constexpr (MAXNL >= 4) cgw_tile<4>(d, f, rt); break;
+    default: if constexpr (MAXNL >= 5) cgw_tile<5>(d, f, rt); break;
+  }
+}
+
+hipError_t launch_cgemm_wave(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const dim3 grid(count, (gemm_y + 3) / 4);
+  if (max_limbs <= 3) TM_LAUNCH(k_cgemm_wave<3>, grid, dim3(256), 0, s, tab, list);
+  else TM_LAUNCH(k_cgemm_wave<5>, grid, dim3(256), 0, s, tab, list);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // the same product for batches: one workgroup per instance, operands in LDS
 // --------------------------------------------------------------------------
 //
@@ -2476,7 +2592,8 @@ __host__ __device__ __forceinline__ int cg2_pad(int b) { return b + ((b >> 8) <<
 
 // digit sums of a finished tile (registers, or the split band's LDS
 // accumulators) to r (int64), the intermediates, and the best of each column
-// tile into cpart (lane layout of the MFMA result: rows 4 g + jj, column c)
+// tile into `tbest` (LDS), or into cpart when tbest is null (lane layout of
+// the MFMA result: rows 4 g + jj, column c)
 template <int NL>
 __device__ __forceinline__ void cg2_report(const Inst& d, int f, int rt, const int* red,
                                            const v4i_t (&acc)[NL][4], VI* tbest) {
@@ -2509,7 +2626,15 @@ __device__ __forceinline__ void cg2_report(const Inst& d, int f, int rt, const i
       const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
       if (vi_better(other, best)) best = other;
     }
-    if (lane == 0) tbest[(f * rtm + rt) * 4 + nt] = best;
+    if (lane == 0) {
+      if (tbest) {
+        tbest[(f * rtm + rt) * 4 + nt] = best;
+      } else {
+        double* pp = reinterpret_cast<double*>(d.cpart) + ((int64_t)(f * rtm + rt) * 4 + nt) * 2;
+        G(pp)[0] = best.v;
+        G(pp)[1] = (double)best.i;
+      }
+    }
   }
 }
 
@@ -2860,6 +2985,8 @@ __device__ __forceinline__ void combine3(const Inst& d, const Combine3& cb, cons
     r.peak1 = r1.peak1;
     r.peak2 = r1.peak2;
     r.score = nc ? best_score : 0.0;
+    r.err_bound = fmax(r1.err_bound, r2.err_bound);
+    r.reserved = 0;
     *out = r;
   }
 }

@@ -45,7 +45,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 static_assert(sizeof(tm_plan_desc) == 48, "tm_plan_desc layout is part of the ABI");
-static_assert(sizeof(tm_result) == 48, "tm_result layout is part of the ABI");
+static_assert(sizeof(tm_result) == 64, "tm_result layout is part of the ABI");
 
 int64_t gcd64(int64_t a, int64_t b) {
   while (b) { const int64_t t = a % b; a = b; b = t; }
@@ -612,6 +612,8 @@ struct tm_plan_s {
   void* spec = nullptr;
   int8_t* tsh = nullptr;     // GEMM path: 16 shifted copies of the zero-padded template
   double tnorm1 = 0.0;
+  double tnorm2 = 0.0;          // ||t||_2
+  double tspec_max = 0.0;       // ||FFT_P(t)||_inf (real plans)
   tm_plan_s* pair2 = nullptr;   // three moduli: the plan of the pair (M3, M1) (owned)
   // single matches: the instance in device memory, one copy per stream pool
   // (the first kResidentSlots in slabs made at the plan's first single
@@ -678,6 +680,8 @@ void fill_inst(const tm_plan_s* p, const void* x, Inst* in) {
   in->tw_cols = p->tw_cols;
   in->tw_rows = p->tw_rows;
   in->tnorm1 = p->tnorm1;
+  in->tspec_max = p->tspec_max;
+  in->tnorm2 = p->tnorm2;
   in->cgemm = c.cgemm;
   in->c_nlcap = c.c_nlcap;
   in->c_lp = c.c_lp;
@@ -834,7 +838,7 @@ static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t
   } else {
     std::memcpy(th.data(), t, tb);
   }
-  double norm1 = 0.0;
+  double norm1 = 0.0, sumsq = 0.0;
   bool t_i8 = true;
   for (int64_t i = 0; i < c.k; ++i) {
     const double v = host_value(th.data(), c.t_dtype, i);
@@ -843,6 +847,7 @@ static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t
       return fail(TM_ERR_INVALID, "exact path needs an integer-valued template");
     t_i8 = t_i8 && v == std::nearbyint(v) && v >= -128.0 && v <= 127.0;
     norm1 += std::fabs(v);
+    sumsq += v * v;
   }
   st = compute_core(desc, &c, t_i8, pair_of_three);
   if (st != TM_OK) return st;
@@ -855,6 +860,7 @@ static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t
   p->core = c;
   p->device = dev;
   p->tnorm1 = norm1;
+  p->tnorm2 = std::sqrt(sumsq);
   const size_t P = size_t(1) << c.p_log2;
   void* z = nullptr;
   auto cleanup = [&]() {
@@ -907,6 +913,15 @@ static tm_status plan_create_impl(const tm_plan_desc* desc, const void* t, int t
                               static_cast<double*>(z), p->spec, c.mode == MODE_EXACT,
                               c.gfft ? c.p_log2 - c.g_q : 0, s));
   TM_HIP_PLAN(hipStreamSynchronize(s));
+  if (c.mode == MODE_REAL) {
+    // ||FFT_P(t)||_inf in FP64 (z holds the unscaled transform) for the
+    // results' error bound
+    std::vector<double> zh((size_t)2 * P);
+    TM_HIP_PLAN(hipMemcpy(zh.data(), z, (size_t)P * 16, hipMemcpyDeviceToHost));
+    double mx = 0.0;
+    for (size_t i = 0; i < (size_t)P; ++i) mx = std::max(mx, std::hypot(zh[2 * i], zh[2 * i + 1]));
+    p->tspec_max = mx;
+  }
   TM_HIP_PLAN(hipFree(z));
   z = nullptr;
 #undef TM_HIP_PLAN
@@ -1028,9 +1043,11 @@ static int cgemm_split(const Core& c) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(env, std::max(1, c.c_ks)));
 }
 
-// Product kernel choice (TM_CGEMM_KIND): 0 and 1 per row tile (the
-// default), 2 per instance wherever its LDS holds the operands (single
-// matches included).  Measured on 4096 uneven int8 instances (N up to 2^20,
+// Product kernel choice (TM_CGEMM_KIND): 0 automatic (batches of at least
+// 2048 row tiles one wave per row tile, else each row tile's band split over
+// a workgroup's waves), 1 always the split band, 2 per instance wherever its
+// LDS holds the operands (single matches included), 3 one wave per row tile
+// for every batch.  Measured on 4096 uneven int8 instances (N up to 2^20,
 // K up to 4096), the per-instance kernel's correlation stage took about
 // 600 us per batch against 390 us for prep, row-tile product and final
 // kernel: with up to 133 KB of LDS per instance a compute unit holds one or
@@ -1118,8 +1135,11 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   } else if (cc.cgemm) {
     const CgLaunch cl = cgemm_launch(2 * (int64_t)cc.c_lp, 2 * (int64_t)cc.c_lp, 1);
     TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
-    TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, (cc.c_rta + cc.c_rtb) * split,
-                                                        cc.c_nlcap, s); }));
+    if (split == 1 && cgemm_kind() == 3)
+      TM_HIP(timed_corr(s, [&] { return launch_cgemm_wave(tab, nullptr, 1, cc.c_rta + cc.c_rtb, cc.c_nlcap, s); }));
+    else
+      TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, (cc.c_rta + cc.c_rtb) * split,
+                                                          cc.c_nlcap, s); }));
     TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
   }
   else if (p->core.gfft) TM_HIP(launch_gfft(one, dev_one, s));
@@ -1212,7 +1232,7 @@ struct BatchPlan {
   std::vector<size_t> ws_off, acc_off;
   std::vector<int32_t> seg_chunks, nseg, order;
   size_t ws = 0, accb = 0, fold_lds = 0;
-  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, cps = 0, cp_max = 0, cgs = 0, cg_limbs_max = 0;
+  int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, cps = 0, cp_max = 0, cgs = 0, cg_limbs_max = 0, cg_tasks = 0;
   int32_t ncg_inst = 0;
   // device layout: [instance workspaces][results][user results][table][lists][combine records]
   size_t off_res = 0, off_ures = 0, off_tab = 0, tab_bytes = 0, off_lists = 0, list_bytes = 0, cmb_bytes = 0,
@@ -1260,10 +1280,9 @@ static tm_status plan_batch(int32_t count, const tm_plan* plans, bool dev_out, c
     return fail(TM_ERR_UNSUPPORTED, "batch too large");
   // product kernel of the GEMM-correlation instances: per row tile, or per
   // instance with its operands in LDS when asked for
-  int64_t cg_tasks = 0;
   for (int32_t i = 0; i < count; ++i)
-    if (plans[i]->core.cgemm) cg_tasks += plans[i]->core.c_rta + plans[i]->core.c_rtb;
-  b.use_inst = cgemm_kind() == 2 && cg_tasks > 0;
+    if (plans[i]->core.cgemm) b.cg_tasks += plans[i]->core.c_rta + plans[i]->core.c_rtb;
+  b.use_inst = cgemm_kind() == 2 && b.cg_tasks > 0;
   // the GEMM-correlation instances first: by product-kernel LDS class, the
   // largest first within a class (they start first); then the finish
   // launches grouped by (mode, FFT length) so each gets its own LDS size
@@ -1386,7 +1405,13 @@ static hipError_t launch_batch(const BatchPlan& b, const tm_plan* plans, const I
   } else if (ncg_inst > 0) {
     const CgLaunch cl = cgemm_launch(b.cps, b.cp_max, ncg_inst);
     if ((e = launch_cgemm_prep(tab, dlist, ncg_inst, cl.chunk, cl.prep_y, s)) != hipSuccess) return e;
-    e = corr([&] { return launch_cgemm_gemm(tab, dlist, ncg_inst, (int)b.cgs, (int)b.cg_limbs_max, s); });
+    // launches of many row tiles: one wave per row tile; else the band of
+    // each row tile split over the waves of a workgroup
+    const bool per_wave = cgemm_kind() == 3 || (cgemm_kind() == 0 && b.cg_tasks >= 2048);
+    e = corr([&] {
+      return per_wave ? launch_cgemm_wave(tab, dlist, ncg_inst, (int)b.cgs, (int)b.cg_limbs_max, s)
+                      : launch_cgemm_gemm(tab, dlist, ncg_inst, (int)b.cgs, (int)b.cg_limbs_max, s);
+    });
     if (e != hipSuccess) return e;
     if ((e = launch_cgemm_final(tab, dlist, ncg_inst, s)) != hipSuccess) return e;
   }

@@ -52,7 +52,8 @@ class Result(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_int64), ("m1_tilde", ctypes.c_int32),
                 ("m2_tilde", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("peak1", ctypes.c_double),
-                ("peak2", ctypes.c_double), ("score", ctypes.c_double)]
+                ("peak2", ctypes.c_double), ("score", ctypes.c_double),
+                ("err_bound", ctypes.c_double), ("reserved", ctypes.c_int64)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -66,12 +67,12 @@ class ServerStats(ctypes.Structure):
                 ("peak_held_bytes", ctypes.c_int64)]
 
 
-assert ctypes.sizeof(Result) == 48 and ctypes.sizeof(PlanDesc) == 48
+assert ctypes.sizeof(Result) == 64 and ctypes.sizeof(PlanDesc) == 48
 RESULT_BYTES = ctypes.sizeof(Result)
 
 RESULT_DTYPE = np.dtype([("shift", "<i8"), ("m1_tilde", "<i4"), ("m2_tilde", "<i4"),
                          ("n_candidates", "<i4"), ("flags", "<u4"), ("peak1", "<f8"),
-                         ("peak2", "<f8"), ("score", "<f8")])
+                         ("peak2", "<f8"), ("score", "<f8"), ("err_bound", "<f8"), ("reserved", "<i8")])
 
 
 class TMError(RuntimeError):
@@ -209,6 +210,7 @@ class MatchResult:
     peak1: float
     peak2: float
     score: float
+    err_bound: float = 0.0
 
     @property
     def nomatch(self) -> bool:
@@ -226,9 +228,9 @@ class MatchResult:
 def _row(r):
     if isinstance(r, np.void):
         return (int(r["shift"]), int(r["m1_tilde"]), int(r["m2_tilde"]), int(r["n_candidates"]),
-                int(r["flags"]), float(r["peak1"]), float(r["peak2"]), float(r["score"]))
+                int(r["flags"]), float(r["peak1"]), float(r["peak2"]), float(r["score"]), float(r["err_bound"]))
     return (int(r.shift), int(r.m1_tilde), int(r.m2_tilde), int(r.n_candidates), int(r.flags),
-            float(r.peak1), float(r.peak2), float(r.score))
+            float(r.peak1), float(r.peak2), float(r.score), float(r.err_bound))
 
 
 class Plan:
@@ -312,14 +314,14 @@ def _check_signal(plan: Plan, x):
 
 def _check_out(out, count: int):
     """`out` must be a contiguous CUDA uint8 tensor with room for `count`
-    48-byte results: the kernels write there without further checks."""
+    results: the kernels write there without further checks."""
     torch = _torch()
     if not isinstance(out, torch.Tensor) or not out.is_cuda:
         raise TypeError("out must be a CUDA (HIP) torch tensor")
     if out.dtype != torch.uint8 or not out.is_contiguous():
         raise TypeError("out must be a contiguous uint8 tensor")
-    if out.numel() < 48 * count:
-        raise ValueError("out holds %d bytes; %d results need %d" % (out.numel(), count, 48 * count))
+    if out.numel() < RESULT_BYTES * count:
+        raise ValueError("out holds %d bytes; %d results need %d" % (out.numel(), count, RESULT_BYTES * count))
 
 
 def match(plan: Plan, x, stream=None) -> MatchResult:
@@ -332,12 +334,12 @@ def match(plan: Plan, x, stream=None) -> MatchResult:
 
 def match_into(plan: Plan, x, out, index: int = 0, stream=None):
     """One match writing a device result: `out` is a CUDA uint8 tensor of
-    48*count bytes; nothing waits."""
+    RESULT_BYTES*count bytes; nothing waits."""
     _check_signal(plan, x)
     if index < 0:
         raise ValueError("index must be >= 0")
     _check_out(out, index + 1)
-    st = (_LIB or lib()).tm_match(plan.handle, x.data_ptr(), out.data_ptr() + 48 * index,
+    st = (_LIB or lib()).tm_match(plan.handle, x.data_ptr(), out.data_ptr() + RESULT_BYTES * index,
                                   _stream_handle(stream))
     if st != TM_OK:
         _check(st)
@@ -351,7 +353,7 @@ def match_noalloc(plan: Plan, x, out, index: int = 0, stream=None):
     if index < 0:
         raise ValueError("index must be >= 0")
     _check_out(out, index + 1)
-    _check(lib().tm_match_noalloc(plan.handle, x.data_ptr(), out.data_ptr() + 48 * index,
+    _check(lib().tm_match_noalloc(plan.handle, x.data_ptr(), out.data_ptr() + RESULT_BYTES * index,
                                   _stream_handle(stream)))
 
 
@@ -362,7 +364,7 @@ def results_from_device(out) -> List[MatchResult]:
 
 def match_batch(plans: Sequence[Plan], xs: Sequence, stream=None, out=None) -> Optional[List[MatchResult]]:
     """tm_match_batch.  With out=None the results come back to the host;
-    with a CUDA uint8 tensor of 48*count bytes they stay on the device."""
+    with a CUDA uint8 tensor of RESULT_BYTES*count bytes they stay on the device."""
     count = len(plans)
     if count != len(xs):
         raise ValueError("plans and xs differ in length")
@@ -394,7 +396,7 @@ class Batch:
         self._x = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in xs])
 
     def run(self, out, stream=None):
-        """out: CUDA uint8 tensor of 48*count bytes (device results, no wait)."""
+        """out: CUDA uint8 tensor of RESULT_BYTES*count bytes (device results, no wait)."""
         _check_out(out, self.count)
         _check(lib().tm_match_batch(self.count, self._p, self._x, out.data_ptr(),
                                     _stream_handle(stream)))
@@ -553,7 +555,7 @@ class Many:
         self._x = (ctypes.c_void_p * self.count)(*[x.data_ptr() for x in self.xs])
 
     def run(self, out, stream=None):
-        """out: CUDA uint8 tensor of 48*count bytes (device results, no wait)."""
+        """out: CUDA uint8 tensor of RESULT_BYTES*count bytes (device results, no wait)."""
         _check_out(out, self.count)
         _check(lib().tm_match_many(self.plan.handle, self.count, self._x, out.data_ptr(),
                                    _stream_handle(stream)))

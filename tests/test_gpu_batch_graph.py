@@ -46,7 +46,8 @@ def _mixed(count, seed):
     return plans, xs, insts
 
 
-@pytest.mark.parametrize("kind", ["0", "2"], ids=["row-tile product", "per-instance product"])
+@pytest.mark.parametrize("kind", ["0", "2", "3"], ids=["automatic product", "per-instance product",
+                                                      "wave per row tile"])
 def test_graph_replays_equal_eager(kind, monkeypatch):
     monkeypatch.setenv("TM_CGEMM_KIND", kind)
     plans, xs, insts = _mixed(40, 3)

@@ -35,9 +35,11 @@ def _case(*a):
 
 # ------------------------------------------------------------ 4-wave product
 
-# the product kernels a batch can run: per row tile with 4 waves (forced), and
-# per instance with its operands in LDS (forced onto single matches)
-KERNELS = {"row-tile 4 waves": ("TM_CGEMM_WAVES", "4"), "per instance": ("TM_CGEMM_KIND", "2")}
+# the product kernels a batch can run, each forced onto single matches: the
+# band of a row tile split over 4 waves, per instance with its operands in
+# LDS, and one wave per row tile
+KERNELS = {"row-tile 4 waves": ("TM_CGEMM_WAVES", "4"), "per instance": ("TM_CGEMM_KIND", "2"),
+           "wave per row tile": ("TM_CGEMM_KIND", "3")}
 
 
 @pytest.fixture(params=list(KERNELS))
@@ -130,7 +132,7 @@ def _row_tiles(m):
     return (rows + 15) // 16
 
 
-@pytest.mark.parametrize("kind", ["0", "2"], ids=["row-tile kernel (default)", "per-instance kernel"])
+@pytest.mark.parametrize("kind", ["1", "2", "3"], ids=["split band", "per-instance kernel", "wave per row tile"])
 def test_large_batch_four_wave_route(kind, monkeypatch):
     monkeypatch.setenv("TM_CGEMM_KIND", kind)
     insts = _uneven_batch(160, 11)
@@ -187,6 +189,15 @@ def test_precision_workload_full_size(store, name, bound):
           "argmax agrees", agree, "shift", res.shift, "oracle", ref.shift, "planted", inst.shift, flush=True)
     assert e_fft <= 1e-5
     assert e_r <= bound
+    # the result's own error bound holds for the transform of the stored folds
+    # and, with the storage rounding, against the FP64 folds (half storage:
+    # the FP32 fold sums' own rounding is far below the storage rounding)
+    d_same = max(np.max(np.abs(r1 - r1_same)), np.max(np.abs(r2 - r2_same)))
+    d_64 = max(np.max(np.abs(r1 - ref.r1)), np.max(np.abs(r2 - ref.r2)))
+    print("err_bound", res.err_bound, "transform error", d_same, "error vs fp64", d_64, flush=True)
+    assert 0 < res.err_bound and d_same <= res.err_bound
+    if store != tm.TM_F32:
+        assert d_64 <= res.err_bound
     if store != tm.TM_F32:                    # one rounding to 8 or 11 significant bits
         assert e_y <= 1.01 * bound / 8
     gap1 = O.top2_gap(ref.r1) / np.max(np.abs(ref.r1))

@@ -215,7 +215,7 @@ def test_device_output_and_repeat_determinism():
     inst = G.config1(3)
     plan = tm.Plan(inst.t, n=inst.n)
     x = to_device(inst.x)
-    out = torch.zeros(48 * 4, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * 4, dtype=torch.uint8, device="cuda")
     for i in range(4):
         tm.match_into(plan, x, out, i)
     rs = tm.results_from_device(out)
@@ -239,7 +239,7 @@ def test_result_buffer_is_checked_before_launch():
     inst = G.config1(1)
     plan = tm.Plan(inst.t, n=inst.n)
     x = to_device(inst.x)
-    small = torch.zeros(48 * 2, dtype=torch.uint8, device="cuda")
+    small = torch.zeros(tm.RESULT_BYTES * 2, dtype=torch.uint8, device="cuda")
     with pytest.raises(ValueError):
         tm.match_into(plan, x, small, 2)                 # slot past the end
     with pytest.raises(ValueError):
@@ -255,3 +255,16 @@ def test_result_buffer_is_checked_before_launch():
     assert torch.count_nonzero(small).item() == 0        # nothing was written
     tm.match_into(plan, x, small, 1)
     assert tm.results_from_device(small)[1] == tm.match(plan, x)
+
+
+def test_error_bound_reported_on_real_results_only():
+    inst = G.planted_gauss(300000, 900, 0.0, 64, 0)
+    res, y1, y2, r1, r2, plan = gpu_match(inst.x, inst.t)
+    ref1 = O.correlate_fft(y1, inst.t.astype(np.float64), plan.m1)
+    ref2 = O.correlate_fft(y2, inst.t.astype(np.float64), plan.m2)
+    err = max(np.max(np.abs(r1 - ref1)), np.max(np.abs(r2 - ref2)))
+    _print_case("error bound", res.err_bound, err)
+    assert 0 < err <= res.err_bound
+    exact = G.config1(2)
+    rx = tm.match(tm.Plan(exact.t, n=exact.n), to_device(exact.x))
+    assert rx.err_bound == 0.0 and rx.exact

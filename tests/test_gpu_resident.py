@@ -82,7 +82,7 @@ def test_many_streams_interleaved_signals():
     plan = tm.Plan(t, n=n)
     dx = [to_device(x) for x in xs]
     streams = [torch.cuda.Stream() for _ in range(12)]
-    out = torch.zeros(48 * 36, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * 36, dtype=torch.uint8, device="cuda")
     _case("12 streams x 3 rounds, 3 signals")
     torch.cuda.synchronize()
     for r in range(3):

@@ -81,7 +81,7 @@ def test_three_moduli_mixed_batch_and_outputs():
     xs = [to_device(s.x) for s in insts]
     _case("mixed batch")
     host = tm.match_batch(plans, xs)
-    dev = torch.zeros(48 * len(xs), dtype=torch.uint8, device="cuda")
+    dev = torch.zeros(tm.RESULT_BYTES * len(xs), dtype=torch.uint8, device="cuda")
     tm.match_batch(plans, xs, out=dev)
     assert tm.results_from_device(dev) == host
     assert host == [tm.match(p, x) for p, x in zip(plans, xs)]

@@ -45,7 +45,7 @@ def _plan(inst, flags):
 def test_two_calls_in_a_row_match_tm_match(label, flags, big, small):
     pb, ps = _plan(big, flags), _plan(small, flags)
     xb, xs = to_device(big.x), to_device(small.x)
-    out = torch.zeros(48 * 2, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * 2, dtype=torch.uint8, device="cuda")
     _case("noalloc", label)
     tm.match_noalloc(pb, xb, out, 0)
     tm.match_noalloc(ps, xs, out, 1)          # same stream, no wait in between
@@ -67,7 +67,7 @@ def test_real_and_global_fft_routes():
     pa, pb = tm.Plan(a.t, n=a.n), tm.Plan(b.t, n=b.n)
     assert pb.info["fft_global"] == 1
     xa, xb = to_device(a.x), to_device(b.x)
-    out = torch.zeros(48 * 2, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * 2, dtype=torch.uint8, device="cuda")
     _case("noalloc real + global fft")
     tm.match_noalloc(pb, xb, out, 0)          # larger workspace first
     tm.match_noalloc(pa, xa, out, 1)
@@ -82,7 +82,7 @@ def test_repeat_after_other_plans_clears_buckets():
     insts = [G.config1(i) for i in range(3)]
     plans = [tm.Plan(s.t, n=s.n) for s in insts]
     xs = [to_device(s.x) for s in insts]
-    out = torch.zeros(48 * 6, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(tm.RESULT_BYTES * 6, dtype=torch.uint8, device="cuda")
     _case("noalloc repeats")
     for rep in range(2):
         for i in range(3):
