@@ -137,6 +137,8 @@ constexpr int kFoldMaxRows = 256;       // tile rows R <= 256
 constexpr size_t kFoldLdsBudget = 60 * 1024;   // skewed tile bytes (two workgroups per CU)
 // streaming int8 fold (k_fold_s8)
 constexpr int kSegThreads = 256;
+// word 3 of a raw buffer resource on gfx950: 32-bit data format, untyped loads
+constexpr int kBufRsrcWord3 = 0x00020000;
 constexpr int kSegHalf = 128;                       // threads per modulus
 constexpr int kSegPiece = 16384;                    // bytes per LDS ring piece
 constexpr int kSegPieceChunks = kSegPiece / 16;

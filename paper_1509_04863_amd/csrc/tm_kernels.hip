@@ -308,22 +308,36 @@ __device__ __forceinline__ void fold_tile(const Inst& d, int lt, unsigned char* 
   }
 }
 
-__device__ __forceinline__ int find_inst_by_tile(const InstTable& tab, int tile) {
-  int lo = 0, hi = tab.count - 1;
+// The last instance whose first work unit (base_of) is <= w, over a table
+// sorted by it.  Every wave searches on its own, 64 probes per round: lane l
+// reads the base at lo + floor(l * span / 64), the ballot of "base <= w" is a
+// prefix of the lanes, and its last lane narrows [lo, hi] 64-fold, so 4096
+// instances take two rounds of one load each (a bisection takes twelve
+// dependent loads).  base_of(lo) <= w holds throughout (base_of(0) = 0).
+// The whole wave must be active.
+template <typename W, typename BaseOf>
+__device__ __forceinline__ int find_inst(int count, W w, BaseOf base_of) {
+  int lo = 0, hi = count - 1;
+  const int lane = (int)(threadIdx.x & 63);
   while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab.table[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+    const int span = hi - lo + 1;
+    const int pos = lo + (int)(((int64_t)lane * span) >> 6);
+    const uint64_t le = __ballot(base_of(pos) <= w);
+    const int last = 63 - __clzll((long long)le);     // lane 0 probes lo: le != 0
+    const int nlo = lo + (int)(((int64_t)last * span) >> 6);
+    const int nhi = last == 63 ? hi : lo + (int)(((int64_t)(last + 1) * span) >> 6) - 1;
+    lo = __builtin_amdgcn_readfirstlane(nlo);
+    hi = __builtin_amdgcn_readfirstlane(nhi);
   }
   return lo;
 }
 
+__device__ __forceinline__ int find_inst_by_tile(const InstTable& tab, int tile) {
+  return find_inst(tab.count, tile, [&](int i) { return tab.table[i].tile_base; });
+}
+
 __device__ __forceinline__ int find_inst_by_red(const InstTable& tab, int wg) {
-  int lo = 0, hi = tab.count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab.table[mid].red_base <= wg) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+  return find_inst(tab.count, wg, [&](int i) { return tab.table[i].red_base; });
 }
 
 __device__ __forceinline__ void fold_dispatch(const Inst& d, int lt, unsigned char* lds) {
@@ -364,17 +378,20 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(InstTable tab, int total_
 // --------------------------------------------------------------------------
 //
 // One workgroup folds one segment of x: a run of 16-byte chunks, addressed
-// from x rounded down to 16 bytes (d = x mod 16 bytes sit before x[0]).
+// from x rounded down to 16 bytes (d = x mod 16 bytes sit before x[0]).  A
+// row belongs to the segment holding its first byte.
+//
 // Chunks pass through a two-piece LDS ring whose first kSegLook bytes are
-// mirrored after it, so a row that starts in one piece is read whole.  Threads
-// 0..127 fold with modulus ma, threads 128..255 with mb.  Lane u owns buckets
-// 4u..4u+3 (plus 512 s for slot s): for each row it reads the two aligned
-// words that hold the row's bytes 4u..4u+3 and one v_perm per parity both
-// realigns them and spreads the even (odd) bytes into 16-bit lanes.  Bytes
-// enter LDS as x + 128 (bit 7 flipped; zero outside x) so the lane sums are
-// unsigned; the bias is removed when the literal folds are formed.  A segment
-// holds at most 256 rows of either modulus, so a 16-bit lane stays below
-// 256 * 255 < 2^16.  A row belongs to the segment holding its first byte.
+// mirrored after it, so a row that starts in one piece is read whole.  Two
+// register sets each hold a piece in flight: while piece j is folded, pieces
+// j + 2 and j + 3 are loading.  Threads 0..127 fold with modulus ma, threads
+// 128..255 with mb.  Lane u owns buckets 4u..4u+3 (plus 512 s for slot s):
+// for each row it reads the two aligned words that hold the row's bytes
+// 4u..4u+3 and one v_perm per parity both realigns them and spreads the even
+// (odd) bytes into 16-bit lanes.  Bytes enter LDS as x + 128 (bit 7 flipped;
+// zero outside x) so the lane sums are unsigned; the bias is removed when the
+// literal folds are formed.  A segment holds at most 256 rows of either
+// modulus, so a 16-bit lane stays below 256 * 255 < 2^16.
 
 // bytes [lo, hi) of a 16-byte chunk kept, the rest cleared
 __device__ __forceinline__ uint4 keep_bytes(uint4 v, int lo, int hi) {
@@ -389,6 +406,12 @@ __device__ __forceinline__ uint4 keep_bytes(uint4 v, int lo, int hi) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// where a segment's loads read: chunks from xseg on, load_bytes of them in x
+struct SegSrc {
+  uintptr_t xseg;    // address of the segment's first chunk
+  int load_bytes;    // bytes read from xseg on (staged chunks that hold x)
+};
+
 struct SegGeom {
   uintptr_t xc;      // x rounded down to 16 bytes
   int delta;         // x - xc
@@ -397,19 +420,51 @@ struct SegGeom {
   int64_t c_end;     // one past its last chunk
   int64_t c_stage;   // one past the last chunk staged (segment plus look-ahead)
   // the same bounds relative to c_begin, in 32 bits
-  uintptr_t xseg;    // address of chunk c_begin
   int stage_rel;     // chunks staged
   int x_rel;         // chunks of x from c_begin on (clamped)
   int first_rel;     // chunk 0 of x relative to c_begin (edge: bytes before x), or -1
   int last_rel;      // last chunk of x relative to c_begin (edge: bytes after x), or -1
+  SegSrc src;
 };
 
-__device__ __forceinline__ void seg_load(const SegGeom& g, int piece, uint4 (&v)[kSegLoads]) {
+// segment seg of signal d (the last one takes the tail)
+__device__ __forceinline__ void seg_geom(SegGeom& g, const Inst& d, int seg) {
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(d.x);
+  const int64_t cb = (int64_t)seg * d.seg_chunks;
+  g.xc = xa & ~(uintptr_t)15;
+  g.delta = (int)(xa & 15);
+  g.nch = (d.n + g.delta + 15) >> 4;
+  g.c_begin = cb;
+  g.c_end = seg == d.nseg - 1 ? g.nch : min(g.nch, cb + d.seg_chunks);
+  const int64_t mmax = max(d.va.m, d.vb.m);
+  g.c_stage = g.c_end + (mmax + 16 + 15) / 16;
+  g.stage_rel = (int)(g.c_stage - cb);
+  g.x_rel = (int)min(g.nch - cb, (int64_t)1 << 30);
+  g.first_rel = cb == 0 ? 0 : -1;
+  g.last_rel = g.nch - 1 - cb < g.stage_rel ? (int)(g.nch - 1 - cb) : -1;
+  g.src.xseg = g.xc + (uintptr_t)cb * 16;
+  g.src.load_bytes = 16 * max(0, min(g.stage_rel, g.x_rel));
+}
+
+// A piece's chunks through a buffer resource that starts at the piece and
+// ends at the last chunk staged from x: chunks past it read as zero without a
+// memory access, so every load is issued unconditionally.  The per-thread
+// offsets stay fixed and the piece moves only the (scalar) base, so issuing
+// the next loads writes no vector register that an earlier load still fills.
+__device__ __forceinline__ void seg_load(uintptr_t xseg, int load_bytes, int piece, uint4 (&v)[kSegLoads]) {
+  // the values are wave-uniform; readfirstlane keeps the resource in scalar
+  // registers (no per-lane loop around each load)
+  const int rel = piece * kSegPiece;
+  const int lim = __builtin_amdgcn_readfirstlane(max(0, load_bytes - rel));
+  const uintptr_t base = xseg + (uintptr_t)(unsigned)rel;
+  const uintptr_t ub = (uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base) |
+                       ((uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32)) << 32);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0, lim, kBufRsrcWord3);
 #pragma unroll
   for (int u = 0; u < kSegLoads; ++u) {
-    const int cr = piece * kSegPieceChunks + (int)threadIdx.x + u * kSegThreads;
-    const bool ok = cr < g.stage_rel && cr < g.x_rel;
-    v[u] = gload16(ok ? g.xseg + (uintptr_t)(unsigned)cr * 16 : g.xc);    // chunk 0 always holds x[0]
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, ((int)threadIdx.x + u * kSegThreads) * 16, 0, 0);
+    v[u] = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
@@ -449,31 +504,19 @@ __device__ __forceinline__ void seg_read_row(const unsigned char* lds, int abase
 template <int NSL>
 __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, unsigned char* lds) {
   const int tid = threadIdx.x;
+  SegGeom g;
+  seg_geom(g, d, seg);
   const int u0 = tid & (kSegHalf - 1);
   const int64_t N = d.n;
-  SegGeom g;
-  const uintptr_t xa = reinterpret_cast<uintptr_t>(d.x);
-  g.xc = xa & ~(uintptr_t)15;
-  g.delta = (int)(xa & 15);
-  g.nch = (N + g.delta + 15) >> 4;
-  g.c_begin = (int64_t)seg * d.seg_chunks;
-  g.c_end = seg == d.nseg - 1 ? g.nch : min(g.nch, g.c_begin + d.seg_chunks);   // the last takes the tail
-  const int64_t mmax = max(d.va.m, d.vb.m);
-  g.c_stage = g.c_end + (mmax + 16 + 15) / 16;
-  g.xseg = g.xc + (uintptr_t)g.c_begin * 16;
-  g.stage_rel = (int)(g.c_stage - g.c_begin);
-  g.x_rel = (int)min(g.nch - g.c_begin, (int64_t)1 << 30);
-  g.first_rel = g.c_begin == 0 ? 0 : -1;
-  g.last_rel = g.nch - 1 - g.c_begin < g.stage_rel ? (int)(g.nch - 1 - g.c_begin) : -1;
-  const int nproc = g.c_end > g.c_begin ? (int)((g.c_end - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks) : 0;
-  const int nstage = g.c_end > g.c_begin ? (int)((g.c_stage - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks) : 0;
+  const int nproc = (int)((g.c_end - g.c_begin + kSegPieceChunks - 1) / kSegPieceChunks);   // >= 1
 
   // this half's modulus (wave-uniform); row k spans bytes [kM + d, (k+1)M + d) from xc
   const int64_t M = half ? d.vb.m : d.va.m;
   const int64_t L = (N + M - 1) / M;
   const int64_t B0 = g.c_begin * 16, B1 = g.c_end * 16;
-  int64_t k = B0 > g.delta ? (B0 - g.delta + M - 1) / M : 0;
-  int64_t rb = k * M + g.delta;                 // first byte of row k
+  const int64_t k0 = B0 > g.delta ? (B0 - g.delta + M - 1) / M : 0;
+  int64_t rb = k0 * M + g.delta;                // first byte of the segment's next row
+  const int64_t last_start = (L - 1) * M + g.delta;   // first byte of row L - 1
   // the top slot also sums bytes past the row's end into lanes of buckets >= M:
   // those lanes stay below 2^16 like the others and are never flushed
 
@@ -481,17 +524,17 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
 #pragma unroll
   for (int s = 0; s < NSL; ++s) { lo[s] = 0; hi[s] = 0; }
 
-  // prologue: the first two pieces' loads in flight together; while piece
-  // j's rows are folded, the load of piece j + 2 is in flight
-  uint4 v[kSegLoads];
-  {
-    uint4 v1[kSegLoads];
-    if (nstage > 0) seg_load(g, 0, v);
-    if (nstage > 1) seg_load(g, 1, v1);
-    if (nstage > 0) seg_store(g, N, 0, v, lds);
-    if (nstage > 1) seg_store(g, N, 1, v1, lds);
-  }
-  if (nstage > 2) seg_load(g, 2, v);
+  // pieces past the staged end read nothing: every step issues the same
+  // loads, so the loads in flight keep one order in every pass of the loop
+  auto load_pos = [&](int p, uint4 (&v)[kSegLoads]) { seg_load(g.src.xseg, g.src.load_bytes, p, v); };
+
+  uint4 va[kSegLoads], vb[kSegLoads];
+  load_pos(0, va);
+  load_pos(1, vb);
+  seg_store(g, N, 0, va, lds);
+  seg_store(g, N, 1, vb, lds);
+  load_pos(2, va);
+  load_pos(3, vb);
   __syncthreads();
 
   // the rows that start in piece j (ring slot j & 1)
@@ -500,12 +543,13 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
     const int64_t Bend = min(Bp + kSegPiece, B1);
     const int ring = (j & 1) * kSegPiece;              // LDS offset of byte b: ring + (b - Bp)
     // rows starting in this piece (first byte in [Bp, Bend), row < L), counted
-    // once.  Row i starts at LDS offset rel + i M; its misalignment
-    // (rel + i M) mod 4 has period 4 in i, so four byte selectors and four
-    // word-aligned bases, computed once per piece, serve every group of four
-    // rows (no per-row scalar work beyond the group's offset)
-    int nr = 0;
-    if (k < L && rb < Bend) nr = (int)min(L - k, (Bend - rb + M - 1) / M);
+    // once: row rb + r M for r M < span (no division).  Row i starts at LDS
+    // offset rel + i M; its misalignment (rel + i M) mod 4 has period 4 in i,
+    // so four byte selectors and four word-aligned bases, computed once per
+    // piece, serve every group of four rows (no per-row scalar work beyond
+    // the group's offset)
+    const int64_t lim = min(Bend, last_start + 1);
+    const int span = lim > rb ? (int)(lim - rb) : 0;
     const int M32 = (int)M;
     const int rel = ring + (int)(rb - Bp);
     uint32_t se[4], so[4];
@@ -527,25 +571,32 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
         hi[s] += __builtin_amdgcn_perm(w1[s], w0[s], so[q]);
       }
     };
-    const int full = nr & ~3;
-    for (int r = 0; r < full; r += 4) {
+    int full = 0;
+    for (; (full + 3) * M32 < span; full += 4) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) row(q, r);
+      for (int q = 0; q < 4; ++q) row(q, full);
     }
-    const int rest = nr - full;
-    if (rest > 0) row(0, full);
-    if (rest > 1) row(1, full);
-    if (rest > 2) row(2, full);
-    k += nr;
+    int nr = full;
+    if (nr * M32 < span) { row(0, full); ++nr; }
+    if (nr * M32 < span) { row(1, full); ++nr; }
+    if (nr * M32 < span) { row(2, full); ++nr; }
     rb += (int64_t)nr * M;
   };
-  for (int j = 0; j < nproc; ++j) {
+  // Pieces go in pairs with no exit between the halves, so set A's loads are
+  // always older than set B's where the loop repeats, and waiting for set A
+  // leaves set B in flight.  A piece past the last holds no row start, so an
+  // odd count folds nothing in the last half; seg_store keeps only chunks
+  // below the staged end.
+  for (int j = 0; j < nproc; j += 2) {
     piece_rows(j);
     __syncthreads();
-    if (j + 2 < nstage) {
-      seg_store(g, N, j + 2, v, lds);
-      if (j + 3 < nstage) seg_load(g, j + 3, v);
-    }
+    seg_store(g, N, j + 2, va, lds);
+    load_pos(j + 4, va);
+    __syncthreads();
+    piece_rows(j + 1);
+    __syncthreads();
+    seg_store(g, N, j + 3, vb, lds);
+    load_pos(j + 5, vb);
     __syncthreads();
   }
 
@@ -567,12 +618,7 @@ __device__ __forceinline__ void fold_segment(const Inst& d, int seg, int half, u
 }
 
 __device__ __forceinline__ int find_inst_by_seg(const InstTable& tab, int seg) {
-  int lo = 0, hi = tab.count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab.table[mid].seg_base <= seg) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+  return find_inst(tab.count, seg, [&](int i) { return tab.table[i].seg_base; });
 }
 
 // one instantiation per word count of a row (ceil(M / 512) slots per lane)
@@ -686,12 +732,7 @@ __device__ __forceinline__ void band_task(const Inst& d, int task, Acc* dg) {
 }
 
 __device__ __forceinline__ int find_inst_by_band(const InstTable& tab, int wg) {
-  int lo = 0, hi = tab.count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab.table[mid].band_base <= wg) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+  return find_inst(tab.count, wg, [&](int i) { return tab.table[i].band_base; });
 }
 
 __device__ __forceinline__ void band_dispatch(const Inst& d, int wg, unsigned char* lds) {
@@ -3097,6 +3138,7 @@ hipError_t launch_noalloc_setup(const Inst& rec, Inst* dst, int* zero, int64_t n
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
+
 
 // Best effort: AMD devices accept dynamic LDS up to the per-workgroup limit
 // without an opt-in, so a refused attribute is not an error.
