@@ -144,13 +144,13 @@ struct Core {
   int fft_in_lds = 1;
 };
 
-// Segment length for a launch: about 8192 segments when the launch holds
-// much data (eight per resident workgroup: long enough to amortise each
-// segment's prologue and flush, short enough that the last ones to start
-// leave no long tail), never above the row limit.
+// Segment length for a launch: about 2048 segments (a few per resident
+// workgroup amortise each segment's prologue and flush) but at most 192 KiB,
+// so that the last segments to start leave no long tail when the signals
+// differ in size; never above the row limit.
 int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
   const int64_t cap = std::max<int64_t>(1, (int64_t)kSegMaxRows * std::min(c.ma, c.mb) / 16 - 1);
-  const int64_t want = launch_bytes / 16 / (1024 * 8);
+  const int64_t want = std::min<int64_t>(launch_bytes / 16 / 2048, (192 << 10) / 16);
   return std::min(cap, std::max<int64_t>(c.seg_chunks, want));
 }
 
