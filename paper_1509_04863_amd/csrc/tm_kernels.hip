@@ -736,7 +736,7 @@ __device__ __forceinline__ int find_inst_by_band(const InstTable& tab, int wg) {
 }
 
 __device__ __forceinline__ void band_dispatch(const Inst& d, int wg, unsigned char* lds) {
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar task indices
   const int task = wg * kBandWaves + wave;
   const int ntasks = d.va.nrb * d.va.ncb + (d.dual ? 0 : d.vb.nrb * d.vb.ncb);
   if (task >= ntasks) return;

@@ -266,6 +266,10 @@ tm_status compute_core(const tm_plan_desc* d, Core* c, bool t_i8, bool pair_of_t
   // 4-byte signals: band fold (views of 64-column bands, R rows per task);
   // everything else that the streaming int8 fold below does not take: tiles
   c->band = d->x_dtype == TM_F32 && env_int("TM_FOLD_BAND", 1) != 0;
+  // The band fold takes fold B of a consecutive pair as plain column sums of
+  // its own view (a second pass over x, mostly from cache): the diagonal sums
+  // of view A through LDS atomics took 3.4 times as long as both passes
+  if (c->band && env_int("TM_BAND_DIAG", 0) == 0) c->dual = 0;
   auto view_of = [&](int64_t m) { return c->band ? make_band_view(d->n, m) : make_view(d->n, m, eb); };
   c->va = view_of(c->ma);
   if (c->dual) {
