@@ -2533,6 +2533,28 @@ template <int NL>
 __device__ __forceinline__ void cg2_report(const Inst& d, int f, int rt, const int* red, const v4i_t (&acc)[NL][4],
                                            VI* tbest);
 
+// a raw buffer resource over [base, base + bytes) in scalar registers (base is
+// wave-uniform)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* base, uint32_t bytes) {
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t ub = (uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b) |
+                       ((uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0,
+                                           (int)__builtin_amdgcn_readfirstlane((int)bytes), kBufRsrcWord3);
+}
+
+__device__ __forceinline__ v4i_t buf_v4i(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return v4i_t{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+}
+
+// One wave: row tile rt of fold f over the whole band.  Every operand load is
+// a buffer load at a fixed per-lane offset plus a per-step scalar offset: B
+// chunk (step st, column tile nt) sits at 1024 st + boff[nt] in the template
+// copies (the copy shift of 64 st + j0 is the one of j0, since 64 st is a
+// multiple of 16), and digit l of A at l lp + 64 st + aoff.  The steps go in
+// pairs through two register sets (c_ks is a multiple of 4), so no register
+// moves separate the loads from the products.
 template <int NL>
 __device__ __forceinline__ void cgw_tile(const Inst& d, int f, int rt) {
   const int lane = threadIdx.x & 63;
@@ -2540,44 +2562,46 @@ __device__ __forceinline__ void cgw_tile(const Inst& d, int f, int rt) {
   const int M = f ? d.vb.m : d.va.m;
   const int ntc = min(4, (M - 1024 * rt + 15) >> 4);
   const int lp = d.c_lp, KS = d.c_ks;
-  const GAS int8_t* arow = G(d.ylimb) + (int64_t)f * d.c_nlcap * lp + 64 * (kCgRows * rt + c) + 16 * g;
-  const GAS int8_t* tsh = G(d.tsh);
-  auto ld_b = [&](int st, int nt) {
-    const int j = 64 * st + 16 * g - (16 * nt + c) + kCgPad;
-    const int sh = (-j) & 15;
-    return *reinterpret_cast<const GAS v4i_t*>(tsh + (((j + sh) >> 4) * 16 + sh) * 16);
+  const __amdgpu_buffer_rsrc_t ra =
+      uniform_rsrc(d.ylimb + (int64_t)f * d.c_nlcap * lp, (uint32_t)(d.c_nlcap * lp));
+  const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(d.tsh, (uint32_t)(16 * d.c_lt));
+  const int aoff = 64 * (kCgRows * rt + c) + 16 * g;
+  int boff[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int j0 = 16 * g - (16 * nt + c) + kCgPad;
+    boff[nt] = (j0 + 2 * ((-j0) & 15)) * 16;
+  }
+  auto load = [&](int st, v4i_t (&b)[4], v4i_t (&a)[NL]) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) b[nt] = buf_v4i(rb, boff[nt], 1024 * st);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) a[l] = buf_v4i(ra, aoff, l * lp + 64 * st);
   };
-  auto ld_a = [&](int st, int l) { return *reinterpret_cast<const GAS v4i_t*>(arow + (int64_t)l * lp + 64 * st); };
   v4i_t acc[NL][4];
 #pragma unroll
   for (int l = 0; l < NL; ++l)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
-  v4i_t bc[4], ac[NL];
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) bc[nt] = ld_b(0, nt);
-#pragma unroll
-  for (int l = 0; l < NL; ++l) ac[l] = ld_a(0, l);
-  for (int st = 0; st < KS; ++st) {
-    // the next step's operands are in flight during this step's products
-    v4i_t bn[4], an[NL];
-    const int sn = min(st + 1, KS - 1);
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) bn[nt] = ld_b(sn, nt);
-#pragma unroll
-    for (int l = 0; l < NL; ++l) an[l] = ld_a(sn, l);
+  auto mfma = [&](const v4i_t (&b)[4], const v4i_t (&a)[NL]) {
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       if (nt < ntc) {                         // uniform over the wave
 #pragma unroll
         for (int l = 0; l < NL; ++l)
-          acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ac[l], bc[nt], acc[l][nt], 0, 0, 0);
+          acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[l], b[nt], acc[l][nt], 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) bc[nt] = bn[nt];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) ac[l] = an[l];
+  };
+  v4i_t b0[4], a0[NL], b1[4], a1[NL];
+  load(0, b0, a0);
+  for (int st = 0; st < KS; st += 2) {
+    // the other set's step is in flight during each set's products; the last
+    // pass reloads the final step into set 0 (unused)
+    load(st + 1, b1, a1);
+    mfma(b0, a0);
+    load(min(st + 2, KS - 1), b0, a0);
+    mfma(b1, a1);
   }
   cg2_report<NL>(d, f, rt, nullptr, acc, nullptr);
 }
