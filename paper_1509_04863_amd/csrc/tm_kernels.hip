@@ -1961,6 +1961,22 @@ hipError_t launch_gfft(const Inst& host, const Inst* dev, hipStream_t s) {
 
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 
+// a raw buffer resource over [base, base + bytes) in scalar registers (base is
+// wave-uniform)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* base, uint32_t bytes) {
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t ub = (uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b) |
+                       ((uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0,
+                                           (int)__builtin_amdgcn_readfirstlane((int)bytes), kBufRsrcWord3);
+}
+
+__device__ __forceinline__ v4i_t buf_v4i(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return v4i_t{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+}
+
+
 __global__ void __launch_bounds__(256) k_many_prep(ManyArgs a) {
   const Inst& b = a.base;
   const int u = blockIdx.x * 256 + threadIdx.x;
@@ -2359,44 +2375,45 @@ __device__ __forceinline__ void cg_gemm_rows(const Inst& d, int f, int rt, int p
   const int qw = (hi - lo + W - 1) / W;
   const int st0 = lo + min(w * qw, hi - lo);
   const int q = max(0, min(qw, hi - st0));   // this wave's steps (may be 0)
-  const GAS int8_t* arow = G(d.ylimb) + (int64_t)f * d.c_nlcap * lp + 64 * (kCgRows * rt + c) + 16 * g;
-  const GAS int8_t* tsh = G(d.tsh);
-  // copies interleaved by 16-byte chunk: chunk m of copy sh at (16 m + sh) * 16,
-  // so the 16 lanes of a column tile read neighbouring chunks
-  auto ld_b = [&](int st, int nt) {
-    const int j = 64 * st + 16 * g - (16 * nt + c) + kCgPad;
-    const int sh = (-j) & 15;
-    return *reinterpret_cast<const GAS v4i_t*>(tsh + (((j + sh) >> 4) * 16 + sh) * 16);
+  // operands as in cgw_tile: buffer loads at fixed per-lane offsets (the
+  // template copies interleaved by 16-byte chunk, chunk m of copy sh at
+  // (16 m + sh) * 16, so the 16 lanes of a column tile read neighbouring
+  // chunks) with per-step scalar offsets, steps in pairs over two register
+  // sets; loads past the wave's share read the last step again, unused
+  const __amdgpu_buffer_rsrc_t ra =
+      uniform_rsrc(d.ylimb + (int64_t)f * d.c_nlcap * lp, (uint32_t)(d.c_nlcap * lp));
+  const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(d.tsh, (uint32_t)(16 * d.c_lt));
+  const int aoff = 64 * (kCgRows * rt + c) + 16 * g;
+  int boff[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int j0 = 16 * g - (16 * nt + c) + kCgPad;
+    boff[nt] = (j0 + 2 * ((-j0) & 15)) * 16;
+  }
+  auto load = [&](int st, v4i_t (&b)[4], v4i_t (&a)[NL]) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) b[nt] = buf_v4i(rb, boff[nt], 1024 * st);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) a[l] = buf_v4i(ra, aoff, l * lp + 64 * st);
   };
-  auto ld_a = [&](int st, int l) { return *reinterpret_cast<const GAS v4i_t*>(arow + (int64_t)l * lp + 64 * st); };
   v4i_t acc[NL][4];
 #pragma unroll
   for (int l = 0; l < NL; ++l)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
-  // the next step's operands are in flight during the current step's MFMAs
-  v4i_t bc[4], ac[NL];
-  const int sfirst = min(st0, KS - 1);
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) bc[nt] = ld_b(sfirst, nt);
-#pragma unroll
-  for (int l = 0; l < NL; ++l) ac[l] = ld_a(sfirst, l);
-  for (int i = 0; i < q; ++i) {
-    v4i_t bn[4], an[NL];
-    if (i + 1 < q) {
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) bn[nt] = ld_b(st0 + i + 1, nt);
-#pragma unroll
-      for (int l = 0; l < NL; ++l) an[l] = ld_a(st0 + i + 1, l);
-    }
+  auto mfma = [&](const v4i_t (&b)[4], const v4i_t (&a)[NL]) {
 #pragma unroll
     for (int l = 0; l < NL; ++l)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ac[l], bc[nt], acc[l][nt], 0, 0, 0);
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) bc[nt] = bn[nt];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) ac[l] = an[l];
+      for (int nt = 0; nt < 4; ++nt) acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[l], b[nt], acc[l][nt], 0, 0, 0);
+  };
+  v4i_t b0[4], a0[NL], b1[4], a1[NL];
+  load(min(st0, KS - 1), b0, a0);
+  for (int i = 0; i < q; i += 2) {
+    load(min(st0 + i + 1, KS - 1), b1, a1);
+    mfma(b0, a0);
+    load(min(st0 + i + 2, KS - 1), b0, a0);
+    if (i + 1 < q) mfma(b1, a1);             // uniform over the wave
   }
   cg_finish_rows<NL, W>(d, f, rt, M, acc, red);
 }
@@ -2532,21 +2549,6 @@ __global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_
 template <int NL>
 __device__ __forceinline__ void cg2_report(const Inst& d, int f, int rt, const int* red, const v4i_t (&acc)[NL][4],
                                            VI* tbest);
-
-// a raw buffer resource over [base, base + bytes) in scalar registers (base is
-// wave-uniform)
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* base, uint32_t bytes) {
-  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
-  const uintptr_t ub = (uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b) |
-                       ((uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32);
-  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0,
-                                           (int)__builtin_amdgcn_readfirstlane((int)bytes), kBufRsrcWord3);
-}
-
-__device__ __forceinline__ v4i_t buf_v4i(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  const auto w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
-  return v4i_t{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-}
 
 // One wave: row tile rt of fold f over the whole band.  Every operand load is
 // a buffer load at a fixed per-lane offset plus a per-step scalar offset: B
