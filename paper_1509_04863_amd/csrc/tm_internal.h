@@ -165,7 +165,6 @@ constexpr int kGfftMaxLog2 = 21;                    // P up to 2^21 (rows of <= 
 constexpr int kGfftMaxQ = 9;                        // column transforms of <= 512
 
 // shared-template correlation as an int8 MFMA GEMM (k_many_*)
-constexpr int kGemmPad = 128;                       // zero bytes around the template
 constexpr int kGemmTile = 64;                       // signals and shifts per workgroup
 constexpr int kGemmMaxLimbs = 3;                    // balanced base-128 digits of the folds
 

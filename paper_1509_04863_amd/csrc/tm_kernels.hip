@@ -2021,8 +2021,14 @@ __global__ void __launch_bounds__(256) k_many_prep(ManyArgs a) {
   }
 }
 
+// Wave `wave` of the workgroup: signals sg .. sg + 15 (rows) against shifts
+// k0 .. k0 + 63 of fold f.  The B operand comes from the plan's 16 interleaved
+// template copies (as in cgw_tile: step st, column tile nt at 1024 st +
+// boff[nt]), the digit rows of A through buffer loads at a fixed per-lane
+// offset plus a per-step scalar offset; two steps in flight over two register
+// sets (a load past the band reads the last step again, unused).
 template <int NL>
-__device__ __forceinline__ void many_gemm_tile(const ManyArgs& a, const int8_t* cs, int lt) {
+__device__ __forceinline__ void many_gemm_tile(const ManyArgs& a) {
   const Inst& b = a.base;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane & 15, g = lane >> 4;
@@ -2030,29 +2036,42 @@ __device__ __forceinline__ void many_gemm_tile(const ManyArgs& a, const int8_t* 
   const int M = f ? b.vb.m : b.va.m, K = b.k;
   const int k0 = blockIdx.y * kGemmTile;
   const int sg = blockIdx.x * kGemmTile + wave * 16;
-  const GAS int8_t* rowp[NL];
+  const int nst = (kGemmTile - 1 + K + 63) / 64;               // 64-deep steps of the band
+  const int64_t fold_bytes = (int64_t)kGemmMaxLimbs * a.rows * a.lp;
+  const __amdgpu_buffer_rsrc_t ra = uniform_rsrc(a.ylimb + (int64_t)f * fold_bytes, (uint32_t)fold_bytes);
+  const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(b.tsh, (uint32_t)(16 * b.c_lt));
+  const int aoff = (sg + c) * a.lp + 16 * g + k0;
+  const int limb_bytes = (int)(a.rows * a.lp);
+  int boff[4];
 #pragma unroll
-  for (int l = 0; l < NL; ++l)
-    rowp[l] = G(a.ylimb) + (((int64_t)f * kGemmMaxLimbs + l) * a.rows + sg + c) * a.lp + 16 * g;
+  for (int nt = 0; nt < 4; ++nt) {
+    const int j0 = 16 * g - (16 * nt + c) + kCgPad;
+    boff[nt] = (j0 + 2 * ((-j0) & 15)) * 16;
+  }
+  auto load = [&](int st, v4i_t (&bt)[4], v4i_t (&av)[NL]) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bt[nt] = buf_v4i(rb, boff[nt], 1024 * st);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) av[l] = buf_v4i(ra, aoff, l * limb_bytes + 64 * st);
+  };
   v4i_t acc[NL][4];
 #pragma unroll
   for (int l = 0; l < NL; ++l)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
-  for (int l0 = k0; l0 < k0 + kGemmTile - 1 + K; l0 += 64) {
-    v4i_t bt[4];
+  auto mfma = [&](const v4i_t (&bt)[4], const v4i_t (&av)[NL]) {
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int j = l0 + 16 * g - (k0 + 16 * nt + c) + kGemmPad;   // t index + pad
-      const int sh = (-j) & 15;
-      bt[nt] = *reinterpret_cast<const v4i_t*>(cs + sh * lt + j + sh);
-    }
+    for (int l = 0; l < NL; ++l)
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-      const v4i_t av = *reinterpret_cast<const GAS v4i_t*>(rowp[l] + l0);
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bt[nt], acc[l][nt], 0, 0, 0);
-    }
+      for (int nt = 0; nt < 4; ++nt) acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(av[l], bt[nt], acc[l][nt], 0, 0, 0);
+  };
+  v4i_t b0[4], a0[NL], b1[4], a1[NL];
+  load(0, b0, a0);
+  for (int st = 0; st < nst; st += 2) {
+    load(min(st + 1, nst - 1), b1, a1);
+    mfma(b0, a0);
+    load(min(st + 2, nst - 1), b0, a0);
+    if (st + 1 < nst) mfma(b1, a1);               // uniform
   }
   // lane holds rows (signals) 4g + j and column (shift) c of each 16 x 16 tile
 #pragma unroll
@@ -2081,18 +2100,6 @@ __device__ __forceinline__ void many_gemm_tile(const ManyArgs& a, const int8_t* 
 }
 
 __global__ void __launch_bounds__(256) k_many_gemm(ManyArgs a) {
-  extern __shared__ __align__(16) unsigned char lds[];
-  const Inst& b = a.base;
-  const int K = b.k;
-  const int lt = (K + 2 * kGemmPad + 32 + 15) & ~15;
-  int8_t* cs = reinterpret_cast<int8_t*>(lds);
-  const int8_t* t = reinterpret_cast<const int8_t*>(b.t);
-  for (int idx = threadIdx.x; idx < 16 * lt; idx += blockDim.x) {
-    const int sh = idx / lt, j = idx - sh * lt;
-    const int src = j - sh - kGemmPad;
-    cs[idx] = src >= 0 && src < K ? G(t)[src] : (int8_t)0;
-  }
-  __syncthreads();
   // limbs needed by this workgroup's 64 signals
   __shared__ int tmax;
   if (threadIdx.x == 0) tmax = 0;
@@ -2102,16 +2109,19 @@ __global__ void __launch_bounds__(256) k_many_gemm(ManyArgs a) {
     if (sig < a.count) atomicMax(&tmax, G(a.maxabs)[(int64_t)blockIdx.z * a.count + sig]);
   }
   __syncthreads();
+  const Inst& b = a.base;
   const int M = blockIdx.z ? b.vb.m : b.va.m;
   if ((int)blockIdx.y * kGemmTile >= M) return;
   const int mx = tmax;
   const int nl = mx < 64 ? 1 : (mx < 64 + 128 * 63 ? 2 : 3);
-  if (nl == 1) many_gemm_tile<1>(a, cs, lt);
-  else if (nl == 2) many_gemm_tile<2>(a, cs, lt);
-  else many_gemm_tile<3>(a, cs, lt);
+  if (nl == 1) many_gemm_tile<1>(a);
+  else if (nl == 2) many_gemm_tile<2>(a);
+  else many_gemm_tile<3>(a);
 }
 
-__global__ void __launch_bounds__(64) k_many_finish(ManyArgs a) {
+// One workgroup of four waves per signal: wave 0 reduces the block bests, all
+// clear the buckets and take part in the resolve and its re-score
+__global__ void __launch_bounds__(256) k_many_finish(ManyArgs a) {
   __shared__ __align__(16) unsigned char scratch[64 * 16];
   __shared__ VI fin[2];
   const int i = blockIdx.x;
@@ -2119,16 +2129,23 @@ __global__ void __launch_bounds__(64) k_many_finish(ManyArgs a) {
   d.x = a.xs[i];
   d.out = a.out + i;
   const int ma = d.va.m, mb = d.vb.m;
-  if (threadIdx.x < 2) {
-    const int f = threadIdx.x;
+  // each fold's block bests: lane b of wave 0 takes blocks b, b + 64, ...,
+  // then a wave argmax (the lowest shift on ties, as in one scan)
+#pragma unroll
+  for (int f = 0; f < 2 && threadIdx.x < 64; ++f) {
     const int nb = ((f ? mb : ma) + kGemmTile - 1) / kGemmTile;
     const double* pp = a.part + ((int64_t)f * a.count + i) * a.nkb * 2;
     VI best{-INFINITY, 0x7fffffff};
-    for (int blk = 0; blk < nb; ++blk) {
+    for (int blk = threadIdx.x; blk < nb; blk += 64) {
       const VI v{G(pp)[2 * blk], (int)G(pp)[2 * blk + 1]};
       if (vi_better(v, best)) best = v;
     }
-    fin[f] = best;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const VI other{__shfl_xor(best.v, o), __shfl_xor(best.i, o)};
+      if (vi_better(other, best)) best = other;
+    }
+    if (threadIdx.x == 0) fin[f] = best;
   }
   int* yp = a.yp + (int64_t)i * a.yp_stride;
   for (int s = threadIdx.x; s < ma + mb; s += blockDim.x) G(yp)[s] = 0;   // buckets consumed
@@ -2137,11 +2154,9 @@ __global__ void __launch_bounds__(64) k_many_finish(ManyArgs a) {
 }
 
 hipError_t launch_many(const ManyArgs& a, hipStream_t s) {
-  const int K = a.base.k;
-  const int lt = (K + 2 * kGemmPad + 32 + 15) & ~15;
   TM_LAUNCH(k_many_prep, dim3((a.lp + 255) / 256, a.count, 2), dim3(256), 0, s, a);
-  TM_LAUNCH(k_many_gemm, dim3((unsigned)(a.rows / kGemmTile), a.nkb, 2), dim3(256), (size_t)16 * lt, s, a);
-  TM_LAUNCH(k_many_finish, dim3(a.count), dim3(64), 0, s, a);
+  TM_LAUNCH(k_many_gemm, dim3((unsigned)(a.rows / kGemmTile), a.nkb, 2), dim3(256), 0, s, a);
+  TM_LAUNCH(k_many_finish, dim3(a.count), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

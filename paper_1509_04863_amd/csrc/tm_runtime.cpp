@@ -1634,7 +1634,9 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
     if (st != TM_OK) return fail(st, "signal " + std::to_string(i) + ": " + g_err);
   }
   const Core& c = p->core;
-  const bool gemm = c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.mode == MODE_EXACT && c.k <= (1 << 14) &&
+  // the shared GEMM reads the plan's template copies (exact plans of the
+  // int8 product route)
+  const bool gemm = c.cgemm && c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.mode == MODE_EXACT && c.k <= (1 << 14) &&
                     std::max(c.va.l, c.vb.l) <= (1 << 13) && !(p->desc.flags & TM_F_FFT) && c.top_t == 1 &&
                     !c.three &&
                     env_int("TM_MANY_BATCH", 0) == 0;
