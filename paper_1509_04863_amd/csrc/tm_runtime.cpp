@@ -406,6 +406,16 @@ struct StreamPool {
   hipEvent_t staged[2] = {nullptr, nullptr};   // completes when that buffer's copy is done
   bool staged_pending[2] = {false, false};
   int next = 0;
+  // the instance table the last batch left in `dev`, with what it was built
+  // from: a batch of the same plans, signals and results on the same memory
+  // finds it there and uploads nothing (any other use of `dev` clears it)
+  bool tab_valid = false;
+  std::vector<tm_plan> tab_plans;
+  std::vector<const void*> tab_xs;
+  const void* tab_out = nullptr;
+  const void* tab_dev = nullptr;
+  const void* tab_acc = nullptr;
+  std::vector<Inst> tab_host;
 };
 
 std::mutex g_mu;
@@ -582,6 +592,7 @@ hipError_t stream_pool_release(int dev, hipStream_t s, bool keep_entry) {
   StreamPool& p = it->second;
   hipError_t err = hipStreamSynchronize(s);     // nothing on the stream may still use the pool
   auto note = [&](hipError_t e) { if (err == hipSuccess) err = e; };
+  p.tab_valid = false;
   if (p.dev) note(hipFree(p.dev));
   if (p.acc) note(hipFree(p.acc));
   p.dev = p.acc = nullptr;
@@ -1085,6 +1096,7 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   const bool dev_out = is_device_pointer(out);
   std::lock_guard<std::mutex> lock(g_mu);
   StreamPool& pool = g_pools[{p->device, s}];
+  pool.tab_valid = false;                // the workspace is reused below
   st = ensure_device(pool, p->core.ws_bytes, s);
   if (st != TM_OK) return st;
   const int split = p->core.cgemm ? cgemm_split(p->core) : 1;
@@ -1292,19 +1304,35 @@ static tm_status plan_batch(int32_t count, const tm_plan* plans, bool dev_out, c
   // largest first within a class (they start first); then the finish
   // launches grouped by (mode, FFT length) so each gets its own LDS size
   b.order.resize(count);
-  for (int32_t i = 0; i < count; ++i) b.order[i] = i;
   const bool use_inst = b.use_inst;
-  std::stable_sort(b.order.begin(), b.order.end(), [&](int32_t x, int32_t y) {
-    const Core& ca = plans[x]->core;
-    const Core& cb = plans[y]->core;
-    if (ca.cgemm != cb.cgemm) return ca.cgemm > cb.cgemm;
-    if (ca.cgemm && use_inst) {
-      const int ka = cg_class(ca), kb = cg_class(cb);
-      if (ka != kb) return ka < kb;
-      return (int64_t)ca.k * (ca.ma + ca.mb) > (int64_t)cb.k * (cb.ma + cb.mb);
+  if (!use_inst) {
+    // a stable counting sort on a small key (product route first, then the
+    // finish launches by mode and FFT length): one pass over the plans
+    // instead of a comparison sort that revisits every plan log(count) times
+    constexpr int kKeys = 2 + 2 * 32;
+    std::vector<int32_t> key((size_t)count);
+    int32_t start[kKeys + 1] = {};
+    for (int32_t i = 0; i < count; ++i) {
+      const Core& c = plans[i]->core;
+      key[i] = c.cgemm ? 0 : 1 + (c.mode != 0 ? 32 : 0) + std::min(c.p_log2, 31);
+      ++start[key[i] + 1];
     }
-    return ca.mode != cb.mode ? ca.mode < cb.mode : ca.p_log2 < cb.p_log2;
-  });
+    for (int k = 0; k < kKeys; ++k) start[k + 1] += start[k];
+    for (int32_t i = 0; i < count; ++i) b.order[start[key[i]]++] = i;
+  } else {
+    for (int32_t i = 0; i < count; ++i) b.order[i] = i;
+    std::stable_sort(b.order.begin(), b.order.end(), [&](int32_t x, int32_t y) {
+      const Core& ca = plans[x]->core;
+      const Core& cb = plans[y]->core;
+      if (ca.cgemm != cb.cgemm) return ca.cgemm > cb.cgemm;
+      if (ca.cgemm) {
+        const int ka = cg_class(ca), kb = cg_class(cb);
+        if (ka != kb) return ka < kb;
+        return (int64_t)ca.k * (ca.ma + ca.mb) > (int64_t)cb.k * (cb.ma + cb.mb);
+      }
+      return ca.mode != cb.mode ? ca.mode < cb.mode : ca.p_log2 < cb.p_log2;
+    });
+  }
   while (b.ncg_inst < count && plans[b.order[b.ncg_inst]]->core.cgemm) ++b.ncg_inst;
   b.off_res = align256(b.ws);
   // combined user results staged on the device when out is host memory
@@ -1456,18 +1484,38 @@ static tm_status run_batch(int32_t count, const tm_plan* plans, const void* cons
   if (st != TM_OK) return st;
   st = ensure_acc(pool, b.accb, s);
   if (st != TM_OK) return st;
-  int slot = 0;
-  st = ensure_host(pool, b.tab_bytes + b.list_bytes + b.cmb_bytes, &slot);
-  if (st != TM_OK) return st;
   char* base = static_cast<char*>(pool.dev);
-  Inst* host_tab = static_cast<Inst*>(pool.host[slot]);
-  int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + b.tab_bytes);
-  if (cmb) std::memcpy(static_cast<char*>(pool.host[slot]) + b.tab_bytes + b.list_bytes, cmb->data(), b.cmb_bytes);
-  fill_batch(b, plans, xs, out, base, static_cast<char*>(pool.acc), host_tab, host_list);
-  TM_HIP(hipMemcpyAsync(base + b.off_tab, pool.host[slot], b.tab_bytes + b.list_bytes + b.cmb_bytes,
-                        hipMemcpyHostToDevice, s));
-  TM_HIP(hipEventRecord(pool.staged[slot], s));
-  pool.staged_pending[slot] = true;
+  const bool reuse = !cmb && pool.tab_valid && pool.tab_dev == pool.dev && pool.tab_acc == pool.acc &&
+                     pool.tab_out == out && pool.tab_plans.size() == (size_t)count &&
+                     std::equal(plans, plans + count, pool.tab_plans.begin()) &&
+                     std::equal(xs, xs + count, pool.tab_xs.begin());
+  const Inst* host_tab = nullptr;
+  if (reuse) {
+    host_tab = pool.tab_host.data();
+  } else {
+    pool.tab_valid = false;
+    int slot = 0;
+    st = ensure_host(pool, b.tab_bytes + b.list_bytes + b.cmb_bytes, &slot);
+    if (st != TM_OK) return st;
+    Inst* tab = static_cast<Inst*>(pool.host[slot]);
+    int32_t* host_list = reinterpret_cast<int32_t*>(static_cast<char*>(pool.host[slot]) + b.tab_bytes);
+    if (cmb) std::memcpy(static_cast<char*>(pool.host[slot]) + b.tab_bytes + b.list_bytes, cmb->data(), b.cmb_bytes);
+    fill_batch(b, plans, xs, out, base, static_cast<char*>(pool.acc), tab, host_list);
+    TM_HIP(hipMemcpyAsync(base + b.off_tab, pool.host[slot], b.tab_bytes + b.list_bytes + b.cmb_bytes,
+                          hipMemcpyHostToDevice, s));
+    TM_HIP(hipEventRecord(pool.staged[slot], s));
+    pool.staged_pending[slot] = true;
+    host_tab = tab;
+    if (!cmb) {
+      pool.tab_host.assign(tab, tab + count);
+      pool.tab_plans.assign(plans, plans + count);
+      pool.tab_xs.assign(xs, xs + count);
+      pool.tab_out = out;
+      pool.tab_dev = pool.dev;
+      pool.tab_acc = pool.acc;
+      pool.tab_valid = true;
+    }
+  }
   pool.acc_dirty = true;                 // until every kernel that restores the buckets is enqueued
   TM_HIP(launch_batch(b, plans, host_tab, base, out, cmb, s, true));
   pool.acc_dirty = false;
@@ -1663,6 +1711,7 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
 
   std::lock_guard<std::mutex> lock(g_mu);
   StreamPool& pool = g_pools[{p->device, s}];
+  pool.tab_valid = false;                // the workspace is reused below
   st = ensure_device(pool, total, s);
   if (st != TM_OK) return st;
   st = ensure_acc(pool, c.acc_bytes * (size_t)count, s);

@@ -113,3 +113,27 @@ def test_graph_refusals():
     parr3 = (tm.ctypes.c_void_p * 1)(three.handle.value)
     st = tm.lib().tm_batch_create(1, parr3, xarr, out.data_ptr(), None, tm.ctypes.byref(handle))
     assert st == tm.TM_ERR_UNSUPPORTED
+
+
+def test_eager_batch_table_follows_the_arguments():
+    """tm_match_batch keeps the last batch's instance table on the device and
+    skips its upload when plans, signals and results are the same: a batch with
+    other signals, a subset, or single matches in between on the same stream
+    must still get their own results."""
+    insts = [G.planted_pm1(1 << 16, 512, 101, i, flip_frac=0.05) for i in range(24)]
+    plans = [tm.Plan(s.t, n=s.n) for s in insts]
+    xs = [to_device(s.x) for s in insts]
+    _case("eager table reuse")
+    first = tm.match_batch(plans, xs)
+    for r, inst, p in zip(first, insts, plans):
+        ref = O.ftm(inst.x, inst.t, p.m1, p.m2)
+        assert (r.shift, r.m1_tilde, r.m2_tilde, r.n_candidates) == \
+            (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
+    assert tm.match_batch(plans, xs) == first                      # the same table again
+    swapped = xs[::-1]
+    other = tm.match_batch(plans, swapped)                         # same plans, other signals
+    single = [tm.match(p, x) for p, x in zip(plans, swapped)]      # single matches on the stream
+    assert other == single
+    assert tm.match_batch(plans, xs) == first                      # after the single matches
+    assert tm.match_batch(plans[:10], xs[:10]) == first[:10]       # a subset
+    assert tm.match_batch(plans, xs) == first
