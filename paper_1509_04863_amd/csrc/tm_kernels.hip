@@ -451,6 +451,8 @@ __device__ __forceinline__ void seg_geom(SegGeom& g, const Inst& d, int seg) {
 // memory access, so every load is issued unconditionally.  The per-thread
 // offsets stay fixed and the piece moves only the (scalar) base, so issuing
 // the next loads writes no vector register that an earlier load still fills.
+// x is read once, so the loads carry the non-temporal hint (aux bit 1): the
+// streamed bytes do not displace what the caches hold for other work.
 __device__ __forceinline__ void seg_load(uintptr_t xseg, int load_bytes, int piece, uint4 (&v)[kSegLoads]) {
   // the values are wave-uniform; readfirstlane keeps the resource in scalar
   // registers (no per-lane loop around each load)
@@ -463,7 +465,7 @@ __device__ __forceinline__ void seg_load(uintptr_t xseg, int load_bytes, int pie
       __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(ub), 0, lim, kBufRsrcWord3);
 #pragma unroll
   for (int u = 0; u < kSegLoads; ++u) {
-    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, ((int)threadIdx.x + u * kSegThreads) * 16, 0, 0);
+    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, ((int)threadIdx.x + u * kSegThreads) * 16, 0, 2);
     v[u] = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
