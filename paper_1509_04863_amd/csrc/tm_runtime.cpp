@@ -150,7 +150,8 @@ struct Core {
 // differ in size; never above the row limit.
 int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
   const int64_t cap = std::max<int64_t>(1, (int64_t)kSegMaxRows * std::min(c.ma, c.mb) / 16 - 1);
-  const int64_t want = std::min<int64_t>(launch_bytes / 16 / 2048, (192 << 10) / 16);
+  const int64_t cap_kib = std::max<int64_t>(1, env_int("TM_SEG_LAUNCH_KIB", 192));
+  const int64_t want = std::min<int64_t>(launch_bytes / 16 / 2048, (cap_kib << 10) / 16);
   return std::min(cap, std::max<int64_t>(c.seg_chunks, want));
 }
 
