@@ -43,8 +43,8 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1509_04863_amd", "csrc", "tm_kernels.hip
 # HBM bytes per launch (FETCH_SIZE + WRITE_SIZE from rocprofv3 --pmc, each
 # scaled by a plain copy's reading; summaries under profiles/), valid only for
 # the kernel source they were taken on: `traffic` is null for any other.
-TRAFFIC_SRC_SHA = "81339db050b73867"
-TRAFFIC_BYTES = {"k_fold_s8/config3": 1634396476, "corr/config3": 248232090}
+TRAFFIC_SRC_SHA = "71d1c2c85fdac485"
+TRAFFIC_BYTES = {"k_fold_s8/config3": 1609355586, "corr/config3": 248262485}
 
 
 def kernels_sha() -> str:

@@ -1167,7 +1167,8 @@ __device__ __forceinline__ double score_at(const Inst& d, int64_t c, void* scrat
   const int64_t N = d.n;
   if (d.mode == MODE_EXACT) {
     long long acc = 0;
-#pragma unroll 4
+    // 16 pairs of loads in flight per thread: K <= 4096 in one round trip
+#pragma unroll 16
     for (int j = threadIdx.x; j < d.k; j += blockDim.x) {
       const int64_t xi = c + j < N ? c + j : c + j - N;   // c < N, j < K <= N
       acc += (long long)ld_int<Tt>(d.t, j) * (long long)ld_int<Tin>(d.x, xi);
@@ -1308,7 +1309,7 @@ __device__ __forceinline__ FinRed block_finred(FinRed mine, FinRed* scratch) {
 // the given residues of fold A and fold B (one each for step 9 itself; the
 // runners-up for top-T re-scoring), the union re-scored by (Tx)_c, and the
 // result record.
-template <typename Tin>
+template <typename Tin, bool T8 = false>
 __device__ __forceinline__ void resolve_lists(const Inst& d, const VI* A, int na, const VI* B, int nb, uint32_t flags,
                               void* scratch, double err_bound = 0.0) {
   const int tid = threadIdx.x;
@@ -1352,7 +1353,9 @@ __device__ __forceinline__ void resolve_lists(const Inst& d, const VI* A, int na
   int64_t best = -1;
   double best_score = 0.0;
   for (int i = 0; i < nc; ++i) {
-    const double sc = score_any_t<Tin>(d, cand[i], scratch);
+    double sc;
+    if constexpr (T8) sc = score_at<Tin, int8_t>(d, cand[i], scratch);
+    else sc = score_any_t<Tin>(d, cand[i], scratch);
     if (i == 0 || sc > best_score) { best = cand[i]; best_score = sc; }
   }
   if (nc == 0) flags |= TM_R_NOMATCH;
@@ -1373,10 +1376,10 @@ __device__ __forceinline__ void resolve_lists(const Inst& d, const VI* A, int na
   }
 }
 
-template <typename Tin>
+template <typename Tin, bool T8 = false>
 __device__ __forceinline__ void resolve_and_report(const Inst& d, VI amax, VI bmax, uint32_t flags, void* scratch,
                                                    double err_bound = 0.0) {
-  resolve_lists<Tin>(d, &amax, 1, &bmax, 1, flags, scratch, err_bound);
+  resolve_lists<Tin, T8>(d, &amax, 1, &bmax, 1, flags, scratch, err_bound);
 }
 
 // Error bound of a real plan's correlations (FP32 transform of 2^stages
@@ -2152,7 +2155,7 @@ __global__ void __launch_bounds__(256) k_many_finish(ManyArgs a) {
   int* yp = a.yp + (int64_t)i * a.yp_stride;
   for (int s = threadIdx.x; s < ma + mb; s += blockDim.x) G(yp)[s] = 0;   // buckets consumed
   __syncthreads();
-  resolve_and_report<int8_t>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+  resolve_and_report<int8_t, true>(d, fin[0], fin[1], TM_R_EXACT, scratch);
 }
 
 hipError_t launch_many(const ManyArgs& a, hipStream_t s) {
@@ -2199,7 +2202,7 @@ int cgemm_limbs_for(int64_t maxabs) { return cg_limbs(maxabs); }
 // then fold B): Algorithm 1 step 3 with Section 2's indices (the zero-padded
 // variant keeps the periodic bucket sums), their digits, the intermediates and
 // each fold's largest |y|
-template <typename Tin>
+template <typename Tin, bool GENERAL>
 __device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
   __shared__ int wmax[2][kCgPrepThreads / 64];
   // everything the loop needs in registers: its global stores could alias the
@@ -2207,7 +2210,6 @@ __device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
   const int lp = d.c_lp, nlc = d.c_nlcap;
   const int ma = d.va.m, mb = d.vb.m, K = d.k;
   const int64_t N = d.n, La = d.va.l, Lb = d.vb.l;
-  const bool general = N < (int64_t)max(ma, mb);
   const bool sfold = d.sfold != 0, zpad = d.zpad != 0;
   const int rhoA = (int)(N - (La - 1) * ma), rhoB = (int)(N - (Lb - 1) * mb);
   const int biasA = sfold ? 128 * ((int)La - 1) : 0, biasB = sfold ? 128 * ((int)Lb - 1) : 0;
@@ -2219,41 +2221,68 @@ __device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
   GAS int* cmax = G(d.cmax);
   int mx[2] = {0, 0};
   const int e1 = min(e0 + chunk, 2 * lp);
-  // four consecutive entries per thread (a fold's 4-aligned entries never
-  // straddle the folds: lp is a multiple of 256), one 4-byte store per digit
-  for (int e4 = e0 + 4 * (int)threadIdx.x; e4 < e1; e4 += 4 * kCgPrepThreads) {
-    const int f = e4 >= lp ? 1 : 0;
-    const int M = f ? mb : ma;
-    const int rho = f ? rhoB : rhoA;
-    double* dy = f ? dyB : dyA;
-    int val[4];
+  // a trip: four entries per thread, kCgPrepThreads apart, so that every load
+  // and store instruction of a wave covers consecutive entries (one or two
+  // cache lines).  Every load of a trip is issued first, at valid addresses
+  // (index 0 where an entry does not use one), so one wait covers them all:
+  // the debug and digit stores could alias the loads as far as the compiler
+  // knows and would otherwise order later loads after them.  Without GENERAL
+  // (N >= M) the x indices stay below 2 M and use int32.
+  constexpr int U = 4;
+  const int n32 = (int)min<int64_t>(N, 0x7fffffff);
+  for (int eb = e0 + (int)threadIdx.x; eb < e1; eb += U * kCgPrepThreads) {
+    int val[U], xw[U], xe[U], xs[U];
+    bool in[U], wrap[U], ext[U];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u = e4 + i - f * lp;
-      int v = 0;
-      if (u < M + K - 1) {
-        const int s = u < M ? u : u - M;
-        v = yp[(f ? ma : 0) + s];
-        if (sfold) v -= (f ? biasB : biasA) + (s < rho ? 128 : 0);
-        if (!zpad) {
-          if (s >= rho) v += ld_int<Tin>(x, mod_small((int64_t)(s - rho), N, general));
-          if (u >= M) v += ld_int<Tin>(x, mod_small((int64_t)s + M - rho, N, general)) - ld_int<Tin>(x, s);
-        }
-        if (dy) G(dy)[u] = (double)v;
+    for (int i = 0; i < U; ++i) {
+      const int e = eb + i * kCgPrepThreads;
+      const int f = e >= lp ? 1 : 0;
+      const int M = f ? mb : ma;
+      const int rho = f ? rhoB : rhoA;
+      const int u = e - f * lp;
+      in[i] = e < e1 && u < M + K - 1;
+      const int s = !in[i] ? 0 : (u < M ? u : u - M);
+      wrap[i] = !zpad && in[i] && s >= rho;
+      ext[i] = !zpad && in[i] && u >= M;
+      val[i] = yp[(f ? ma : 0) + s];
+      int64_t iw, ie;
+      if constexpr (GENERAL) {
+        iw = mod_small((int64_t)(s - rho), N, true);
+        ie = mod_small((int64_t)s + M - rho, N, true);
+      } else {
+        const int t = s + M - rho;                  // < 2 M
+        iw = s - rho;                               // < M <= N
+        ie = t >= n32 ? t - n32 : t;
       }
+      xw[i] = ld_int<Tin>(x, wrap[i] ? iw : 0);
+      xe[i] = ld_int<Tin>(x, ext[i] ? ie : 0);
+      xs[i] = ld_int<Tin>(x, ext[i] ? s : 0);
+      if (sfold) val[i] -= (f ? biasB : biasA) + (s < rho ? 128 : 0);
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+      const int e = eb + i * kCgPrepThreads;
+      const int f = e >= lp ? 1 : 0;
+      int v = in[i] ? val[i] : 0;
+      v += (wrap[i] ? xw[i] : 0) + (ext[i] ? xe[i] - xs[i] : 0);
       val[i] = v;
       mx[f] = max(mx[f], v < 0 ? -v : v);
     }
-    GAS uint32_t* dst = reinterpret_cast<GAS uint32_t*>(limb + (int64_t)f * nlc * lp + (e4 - f * lp));
-    for (int l = 0; l < nlc; ++l) {
-      uint32_t w = 0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int digit = ((val[i] + 64) & 127) - 64;
-        val[i] = (val[i] - digit) >> 7;
-        w |= (uint32_t)(uint8_t)(int8_t)digit << (8 * i);
+    for (int i = 0; i < U; ++i) {
+      const int e = eb + i * kCgPrepThreads;
+      if (e >= e1) break;
+      const int f = e >= lp ? 1 : 0;
+      const int u = e - f * lp;
+      double* dy = f ? dyB : dyA;
+      if (dy && in[i]) G(dy)[u] = (double)val[i];
+      GAS int8_t* dst = limb + (int64_t)f * nlc * lp + u;
+      int v = val[i];
+      for (int l = 0; l < nlc; ++l) {
+        const int digit = ((v + 64) & 127) - 64;
+        v = (v - digit) >> 7;
+        dst[(int64_t)l * lp] = (int8_t)digit;
       }
-      dst[(int64_t)l * (lp >> 2)] = w;
     }
   }
 #pragma unroll
@@ -2272,13 +2301,24 @@ __device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
   }
 }
 
+// the loop without int64 remainders (no branches between an entry's loads)
+// unless N < M, where a fold's indices can wrap more than once
 __device__ __forceinline__ void cg_prep_dispatch(const Inst& d, int e0, int chunk) {
   if (e0 >= 2 * d.c_lp) return;
+  if (d.n < (int64_t)max(d.va.m, d.vb.m)) {
+    switch (d.x_dtype) {
+      case TM_I8: cg_prep_chunk<int8_t, true>(d, e0, chunk); break;
+      case TM_F32: cg_prep_chunk<float, true>(d, e0, chunk); break;
+      case TM_BF16: cg_prep_chunk<bf16_t, true>(d, e0, chunk); break;
+      default: cg_prep_chunk<f16_t, true>(d, e0, chunk); break;
+    }
+    return;
+  }
   switch (d.x_dtype) {
-    case TM_I8: cg_prep_chunk<int8_t>(d, e0, chunk); break;
-    case TM_F32: cg_prep_chunk<float>(d, e0, chunk); break;
-    case TM_BF16: cg_prep_chunk<bf16_t>(d, e0, chunk); break;
-    default: cg_prep_chunk<f16_t>(d, e0, chunk); break;
+    case TM_I8: cg_prep_chunk<int8_t, false>(d, e0, chunk); break;
+    case TM_F32: cg_prep_chunk<float, false>(d, e0, chunk); break;
+    case TM_BF16: cg_prep_chunk<bf16_t, false>(d, e0, chunk); break;
+    default: cg_prep_chunk<f16_t, false>(d, e0, chunk); break;
   }
 }
 
@@ -2464,13 +2504,15 @@ __global__ void __launch_bounds__(64 * W) k_cgemm(InstTable tab, const int32_t* 
   else cg_gemm_dispatch<MAXNL, W>(tab.resident(), blockIdx.y, red);
 }
 
-template <typename Tin>
+// LEAN: int8 signal and template, one workgroup per band, no top-T (the
+// common batch; fewer registers, so more workgroups resident)
+template <typename Tin, bool LEAN = false>
 __device__ __forceinline__ void cg_final(const Inst& d) {
   __shared__ __align__(16) unsigned char scratch[16 * 16];
   __shared__ VI fin[2];
   __shared__ VI wbest[4];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (d.c_split > 1) {
+  if (!LEAN && d.c_split > 1) {
     // split band: r of each fold from the accumulators (cleared as read)
     for (int f = 0; f < 2; ++f) {
       const int M = f ? d.vb.m : d.va.m;
@@ -2534,8 +2576,8 @@ __device__ __forceinline__ void cg_final(const Inst& d) {
   for (int s = threadIdx.x; s < nz; s += blockDim.x) G(d.yp)[s] = 0;
   if (threadIdx.x < 2) G(d.cmax)[threadIdx.x] = 0;
   __syncthreads();
-  if (d.top_t > 1) resolve_top_t<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
-  else resolve_and_report<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+  if (!LEAN && d.top_t > 1) resolve_top_t<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
+  else resolve_and_report<Tin, LEAN>(d, fin[0], fin[1], TM_R_EXACT, scratch);
 }
 
 __device__ __forceinline__ void cg_final_dispatch(const Inst& d) {
@@ -2547,9 +2589,11 @@ __device__ __forceinline__ void cg_final_dispatch(const Inst& d) {
   }
 }
 
+template <bool LEAN>
 __global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_t* list) {
-  if (list) cg_final_dispatch(tab.table[list[blockIdx.x]]);
-  else cg_final_dispatch(tab.resident());
+  const Inst& d = list ? tab.table[list[blockIdx.x]] : tab.resident();
+  if constexpr (LEAN) cg_final<int8_t, true>(d);
+  else cg_final_dispatch(d);
 }
 
 // --------------------------------------------------------------------------
@@ -2641,6 +2685,147 @@ __global__ void __launch_bounds__(256) k_cgemm_wave(InstTable tab, const int32_t
     case 4: if constexpr (MAXNL >= 4) cgw_tile<4>(d, f, rt); break;
     default: if constexpr (MAXNL >= 5) cgw_tile<5>(d, f, rt); break;
   }
+}
+
+// The same product with the template copies staged once per workgroup in an
+// LDS ring instead of being fetched by every wave: the four waves of a
+// workgroup (row tiles of one instance) read the same B operand each step,
+// and through the vector L1 that reading, not the matrix cores, set the
+// pace.  Step st reads bytes 1024 st + boff (boff in [1040, 3312)), i.e. the
+// 1 KiB blocks st+1 .. st+3 of the copies; block b sits in ring slot b mod
+// 32.  The prologue stages blocks 0 .. 15; phase p (steps 8p .. 8p+7) needs
+// blocks up to 8p+10, and while it runs the workgroup fetches blocks
+// 8p+16 .. 8p+23 into registers (their slots last held blocks no later than
+// 8p-9), writes them at the end of the phase and meets at one barrier.  Each wave's 64 lanes read one
+// contiguous KiB per column tile, so the LDS reads are free of bank
+// conflicts.  Waves past the instance's row tiles take part in the staging
+// and the barriers only.
+constexpr int kRingBlocks = 32;        // 32 KiB of LDS per workgroup
+constexpr int kRingPhase = 8;          // steps per phase (one barrier)
+
+template <int NL>
+__device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, unsigned char* ring) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int c = lane & 15, g = lane >> 4;
+  const bool active = task < ntask;                // uniform over the wave
+  const int f = task >= d.c_rta ? 1 : 0;
+  const int rt = task - f * d.c_rta;
+  const int M = f ? d.vb.m : d.va.m;
+  const int ntc = active ? min(4, (M - 1024 * rt + 15) >> 4) : 0;
+  const int lp = d.c_lp, KS = d.c_ks;
+  const __amdgpu_buffer_rsrc_t ra =
+      uniform_rsrc(d.ylimb + (int64_t)f * d.c_nlcap * lp, (uint32_t)(d.c_nlcap * lp));
+  const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(d.tsh, (uint32_t)(16 * d.c_lt));
+  const int aoff = 64 * (kCgRows * rt + c) + 16 * g;
+  int boff[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int j0 = 16 * g - (16 * nt + c) + kCgPad;
+    boff[nt] = (j0 + 2 * ((-j0) & 15)) * 16;
+  }
+  // staging: thread tid moves 16 bytes at 16 tid and 16 tid + 4096 of each
+  // 8 KiB group of blocks (bytes past the copies read as zero)
+  auto stage_load = [&](int blk0, v4i_t (&v)[2]) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) v[r] = buf_v4i(rb, 16 * tid + 4096 * r, 1024 * blk0);
+  };
+  auto stage_store = [&](int blk0, const v4i_t (&v)[2]) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int b = blk0 + 4 * r + (tid >> 6);
+      *reinterpret_cast<v4i_t*>(ring + ((b & (kRingBlocks - 1)) << 10) + 16 * (tid & 63)) = v[r];
+    }
+  };
+  // prologue: blocks 0 .. 15
+  {
+    v4i_t v0[2], v1[2];
+    stage_load(0, v0);
+    stage_load(8, v1);
+    stage_store(0, v0);
+    stage_store(8, v1);
+  }
+  __syncthreads();
+  v4i_t acc[NL][4];
+#pragma unroll
+  for (int l = 0; l < NL; ++l)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
+  auto load_a = [&](int st, v4i_t (&a)[NL]) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) a[l] = buf_v4i(ra, aoff, l * lp + 64 * st);
+  };
+  auto read_b = [&](int st, v4i_t (&b)[4]) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      b[nt] = *reinterpret_cast<const v4i_t*>(ring + ((1024 * st + boff[nt]) & (kRingBlocks * 1024 - 1)));
+  };
+  auto step = [&](const v4i_t (&a)[NL], const v4i_t (&b)[4]) {
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      if (nt < ntc) {                              // uniform over the wave
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+          acc[l][nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[l], b[nt], acc[l][nt], 0, 0, 0);
+      }
+    }
+  };
+  // A (global) and B (ring) of the next step are read while the products of
+  // the current one run: two register sets, steps in pairs.  The B read of
+  // the step after a phase touches blocks staged before that phase.
+  v4i_t a0[NL], a1[NL], b0[4], b1[4];
+  if (active) {
+    load_a(0, a0);
+    read_b(0, b0);
+  }
+  for (int p0 = 0; p0 < KS; p0 += kRingPhase) {
+    v4i_t nx[2];
+    stage_load(p0 + 16, nx);
+    if (active) {
+      // the phase's steps in pairs (KS is a multiple of 4; a phase holds 8 or,
+      // last, 4 steps); the last pair reloads the final step (unused)
+      const int pe = min(p0 + kRingPhase, KS);
+      for (int st = p0; st < pe; st += 2) {
+        load_a(st + 1, a1);
+        read_b(st + 1, b1);
+        step(a0, b0);
+        const int sn = min(st + 2, KS - 1);
+        load_a(sn, a0);
+        read_b(sn, b0);
+        step(a1, b1);
+      }
+    }
+    stage_store(p0 + 16, nx);
+    __syncthreads();
+  }
+  if (active) cg2_report<NL>(d, f, rt, nullptr, acc, nullptr);
+}
+
+// grid (instances, groups of four row tiles); one row tile per wave, the
+// digit count of the group's folds taken for all four waves (the extra
+// digits of a fold that needs fewer are zero rows)
+template <int MAXNL>
+__global__ void __launch_bounds__(256) k_cgemm_ring(InstTable tab, const int32_t* list) {
+  __shared__ __align__(16) unsigned char ring[kRingBlocks * 1024];
+  const Inst& d = list ? tab.table[list[blockIdx.x]] : tab.resident();
+  const int ntask = d.c_rta + d.c_rtb;
+  const int t0 = blockIdx.y * 4;
+  if (t0 >= ntask) return;                         // the whole workgroup
+  const int t1 = min(t0 + 3, ntask - 1);
+  const int f0 = t0 >= d.c_rta ? 1 : 0, f1 = t1 >= d.c_rta ? 1 : 0;
+  const int mx = max(G(d.cmax)[f0], G(d.cmax)[f1]);
+  const int nl = min(min(cg_limbs(mx), d.c_nlcap), MAXNL);
+  const int task = __builtin_amdgcn_readfirstlane(t0 + (int)(threadIdx.x >> 6));
+  switch (nl) {
+    case 1: cgr_tile<1>(d, task, ntask, ring); break;
+    case 2: cgr_tile<2>(d, task, ntask, ring); break;
+    default: cgr_tile<3>(d, task, ntask, ring); break;
+  }
+}
+
+hipError_t launch_cgemm_ring(const InstTable& tab, const int32_t* list, int count, int gemm_y, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  TM_LAUNCH(k_cgemm_ring<3>, dim3(count, (gemm_y + 3) / 4), dim3(256), 0, s, tab, list);
+  return hipGetLastError();
 }
 
 hipError_t launch_cgemm_wave(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
@@ -2977,9 +3162,10 @@ hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int coun
   return hipGetLastError();
 }
 
-hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s) {
+hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s, bool lean) {
   if (count <= 0) return hipSuccess;
-  TM_LAUNCH(k_cgemm_final, dim3(count), dim3(256), 0, s, tab, list);
+  if (lean) TM_LAUNCH(k_cgemm_final<true>, dim3(count), dim3(256), 0, s, tab, list);
+  else TM_LAUNCH(k_cgemm_final<false>, dim3(count), dim3(256), 0, s, tab, list);
   return hipGetLastError();
 }
 

@@ -148,6 +148,11 @@ struct Core {
 // workgroup amortise each segment's prologue and flush) but at most 192 KiB,
 // so that the last segments to start leave no long tail when the signals
 // differ in size; never above the row limit.
+// the product route's final kernel without the dtype and top-T branches
+static bool cg_lean_core(const Core& c) {
+  return c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.top_t == 1;
+}
+
 int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
   const int64_t cap = std::max<int64_t>(1, (int64_t)kSegMaxRows * std::min(c.ma, c.mb) / 16 - 1);
   const int64_t cap_kib = std::max<int64_t>(1, env_int("TM_SEG_LAUNCH_KIB", 192));
@@ -161,7 +166,8 @@ int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
 struct CgLaunch { int chunk; int prep_y; };
 CgLaunch cgemm_launch(int64_t total_entries, int64_t max_entries, int64_t count) {
   (void)count;
-  int64_t chunk = std::max<int64_t>(1024, align_up(ceil_div(total_entries, 4096), 1024));
+  const int64_t wgs = std::max<int64_t>(1, env_int("TM_CG_PREP_WGS", 4096));
+  int64_t chunk = std::max<int64_t>(1024, align_up(ceil_div(total_entries, wgs), 1024));
   chunk = std::min(chunk, align_up(max_entries, 1024));
   return CgLaunch{(int)chunk, (int)ceil_div(max_entries, chunk)};
 }
@@ -1153,12 +1159,14 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   } else if (cc.cgemm) {
     const CgLaunch cl = cgemm_launch(2 * (int64_t)cc.c_lp, 2 * (int64_t)cc.c_lp, 1);
     TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
-    if (split == 1 && cgemm_kind() == 3)
+    if (split == 1 && cgemm_kind() == 4 && cc.c_nlcap <= 3)
+      TM_HIP(timed_corr(s, [&] { return launch_cgemm_ring(tab, nullptr, 1, cc.c_rta + cc.c_rtb, s); }));
+    else if (split == 1 && (cgemm_kind() == 3 || cgemm_kind() == 4))
       TM_HIP(timed_corr(s, [&] { return launch_cgemm_wave(tab, nullptr, 1, cc.c_rta + cc.c_rtb, cc.c_nlcap, s); }));
     else
       TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, (cc.c_rta + cc.c_rtb) * split,
                                                           cc.c_nlcap, s); }));
-    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
+    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s, split == 1 && cg_lean_core(cc)));
   }
   else if (p->core.gfft) TM_HIP(launch_gfft(one, dev_one, s));
   else TM_HIP(timed_corr(s, [&] { return launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2,
@@ -1230,7 +1238,7 @@ tm_status tm_match_noalloc(tm_plan p, const void* x, tm_result* out, void* strea
     const CgLaunch cl = cgemm_launch(2 * (int64_t)c.c_lp, 2 * (int64_t)c.c_lp, 1);
     TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
     TM_HIP(launch_cgemm_gemm(tab, nullptr, 1, c.c_rta + c.c_rtb, c.c_nlcap, s));
-    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s));
+    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s, cg_lean_core(c)));
   } else if (c.gfft) {
     TM_HIP(launch_gfft(one, dev_one, s));
   } else {
@@ -1252,6 +1260,7 @@ struct BatchPlan {
   size_t ws = 0, accb = 0, fold_lds = 0;
   int64_t tiles = 0, chunks = 0, segs = 0, bands = 0, cps = 0, cp_max = 0, cgs = 0, cg_limbs_max = 0, cg_tasks = 0;
   int32_t ncg_inst = 0;
+  bool cg_lean = true;   // every product instance: int8 signal and template, top_t 1
   // device layout: [instance workspaces][results][user results][table][lists][combine records]
   size_t off_res = 0, off_ures = 0, off_tab = 0, tab_bytes = 0, off_lists = 0, list_bytes = 0, cmb_bytes = 0,
          total = 0;
@@ -1298,8 +1307,12 @@ static tm_status plan_batch(int32_t count, const tm_plan* plans, bool dev_out, c
     return fail(TM_ERR_UNSUPPORTED, "batch too large");
   // product kernel of the GEMM-correlation instances: per row tile, or per
   // instance with its operands in LDS when asked for
-  for (int32_t i = 0; i < count; ++i)
-    if (plans[i]->core.cgemm) b.cg_tasks += plans[i]->core.c_rta + plans[i]->core.c_rtb;
+  for (int32_t i = 0; i < count; ++i) {
+    const Core& c = plans[i]->core;
+    if (!c.cgemm) continue;
+    b.cg_tasks += c.c_rta + c.c_rtb;
+    b.cg_lean = b.cg_lean && c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.top_t == 1;
+  }
   b.use_inst = cgemm_kind() == 2 && b.cg_tasks > 0;
   // the GEMM-correlation instances first: by product-kernel LDS class, the
   // largest first within a class (they start first); then the finish
@@ -1434,20 +1447,23 @@ static hipError_t launch_batch(const BatchPlan& b, const tm_plan* plans, const I
       }
       const int32_t n_rest = ncg_inst - n_inst;
       if ((e = launch_cgemm_gemm(tab, dlist + n_inst, n_rest, (int)gy, (int)nl, s)) != hipSuccess) return e;
-      if ((e = launch_cgemm_final(tab, dlist + n_inst, n_rest, s)) != hipSuccess) return e;
+      if ((e = launch_cgemm_final(tab, dlist + n_inst, n_rest, s, b.cg_lean)) != hipSuccess) return e;
     }
   } else if (ncg_inst > 0) {
     const CgLaunch cl = cgemm_launch(b.cps, b.cp_max, ncg_inst);
     if ((e = launch_cgemm_prep(tab, dlist, ncg_inst, cl.chunk, cl.prep_y, s)) != hipSuccess) return e;
     // launches of many row tiles: one wave per row tile; else the band of
     // each row tile split over the waves of a workgroup
-    const bool per_wave = cgemm_kind() == 3 || (cgemm_kind() == 0 && b.cg_tasks >= 2048);
+    const bool per_wave = cgemm_kind() == 3 || cgemm_kind() == 4 || (cgemm_kind() == 0 && b.cg_tasks >= 2048);
+    // the LDS-ring variant of the per-wave kernel for digit counts up to 3
+    const bool ring = per_wave && b.cg_limbs_max <= 3 && cgemm_kind() != 3;
     e = corr([&] {
+      if (ring) return launch_cgemm_ring(tab, dlist, ncg_inst, (int)b.cgs, s);
       return per_wave ? launch_cgemm_wave(tab, dlist, ncg_inst, (int)b.cgs, (int)b.cg_limbs_max, s)
                       : launch_cgemm_gemm(tab, dlist, ncg_inst, (int)b.cgs, (int)b.cg_limbs_max, s);
     });
     if (e != hipSuccess) return e;
-    if ((e = launch_cgemm_final(tab, dlist, ncg_inst, s)) != hipSuccess) return e;
+    if ((e = launch_cgemm_final(tab, dlist, ncg_inst, s, b.cg_lean)) != hipSuccess) return e;
   }
   for (int32_t g0 = ncg_inst; g0 < b.count;) {
     const Core& c0 = plans[order[g0]]->core;

@@ -46,8 +46,8 @@ def _mixed(count, seed):
     return plans, xs, insts
 
 
-@pytest.mark.parametrize("kind", ["0", "2", "3"], ids=["automatic product", "per-instance product",
-                                                      "wave per row tile"])
+@pytest.mark.parametrize("kind", ["0", "2", "3", "4"], ids=["automatic product", "per-instance product",
+                                                           "wave per row tile", "LDS ring"])
 def test_graph_replays_equal_eager(kind, monkeypatch):
     monkeypatch.setenv("TM_CGEMM_KIND", kind)
     plans, xs, insts = _mixed(40, 3)

@@ -39,7 +39,7 @@ def _case(*a):
 # band of a row tile split over 4 waves, per instance with its operands in
 # LDS, and one wave per row tile
 KERNELS = {"row-tile 4 waves": ("TM_CGEMM_WAVES", "4"), "per instance": ("TM_CGEMM_KIND", "2"),
-           "wave per row tile": ("TM_CGEMM_KIND", "3")}
+           "wave per row tile": ("TM_CGEMM_KIND", "3"), "wave per row tile, LDS ring": ("TM_CGEMM_KIND", "4")}
 
 
 @pytest.fixture(params=list(KERNELS))
@@ -132,7 +132,8 @@ def _row_tiles(m):
     return (rows + 15) // 16
 
 
-@pytest.mark.parametrize("kind", ["1", "2", "3"], ids=["split band", "per-instance kernel", "wave per row tile"])
+@pytest.mark.parametrize("kind", ["1", "2", "3", "4"],
+                         ids=["split band", "per-instance kernel", "wave per row tile", "LDS ring"])
 def test_large_batch_four_wave_route(kind, monkeypatch):
     monkeypatch.setenv("TM_CGEMM_KIND", kind)
     insts = _uneven_batch(160, 11)
