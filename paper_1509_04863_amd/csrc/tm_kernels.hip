@@ -2687,25 +2687,37 @@ __global__ void __launch_bounds__(256) k_cgemm_wave(InstTable tab, const int32_t
   }
 }
 
-// The same product with the template copies staged once per workgroup in an
-// LDS ring instead of being fetched by every wave: the four waves of a
-// workgroup (row tiles of one instance) read the same B operand each step,
-// and through the vector L1 that reading, not the matrix cores, set the
-// pace.  Step st reads bytes 1024 st + boff (boff in [1040, 3312)), i.e. the
-// 1 KiB blocks st+1 .. st+3 of the copies; block b sits in ring slot b mod
-// 32.  The prologue stages blocks 0 .. 15; phase p (steps 8p .. 8p+7) needs
-// blocks up to 8p+10, and while it runs the workgroup fetches blocks
-// 8p+16 .. 8p+23 into registers (their slots last held blocks no later than
-// 8p-9), writes them at the end of the phase and meets at one barrier.  Each wave's 64 lanes read one
-// contiguous KiB per column tile, so the LDS reads are free of bank
-// conflicts.  Waves past the instance's row tiles take part in the staging
-// and the barriers only.
-constexpr int kRingBlocks = 32;        // 32 KiB of LDS per workgroup
-constexpr int kRingPhase = 8;          // steps per phase (one barrier)
+// The same product with both operands staged in LDS rings a phase ahead of
+// their use.  The template copies (B) are read alike by the four waves of a
+// workgroup (row tiles of one instance) and are staged once per workgroup;
+// each wave's digit rows (A) slide by one row per step, so a wave stages
+// only the 4 new rows of each digit per phase.  Fetching both straight from
+// memory every step left each wave waiting on its loads (the matrix cores
+// ran at about a quarter of their rate).
+//
+// B: step st reads bytes 1024 st + boff (boff in [1040, 3312)) of the
+// copies, i.e. 1 KiB blocks st+1 .. st+3; block b sits in slot b mod 16.
+// The prologue stages blocks 0 .. 11; phase p (steps 4p .. 4p+3, plus the
+// early read of step 4p+4) reads blocks up to 4p+7 while the workgroup
+// fetches blocks 4p+12 .. 4p+15, writes them at the end of the phase (their
+// slots last held blocks up to 4p-1) and meets at one barrier.
+// A: lane (c, g) of step st reads row R0 + c + st (R0 = 16 rt), bytes 16 g ..
+// 16 g + 15, of each digit row; row r sits in slot r mod 32 of the wave's
+// ring for that digit.  The prologue stages rows R0 .. R0+31; phase p reads
+// rows up to R0+4p+19 while the wave fetches rows R0+4p+32 .. R0+4p+35 and
+// writes them at the end of the phase over rows R0+4p .. R0+4p+3.
+// Every wave reads one contiguous KiB per operand tile, so the LDS reads are
+// free of bank conflicts.  Waves past the instance's row tiles take part in
+// the staging of B and the barriers only.
+constexpr int kRingB = 16;             // B slots of 1 KiB
+constexpr int kRingA = 32;             // A slots of one 64-byte row per digit
+constexpr int kRingPhase = 4;          // steps per phase (c_ks is a multiple of 4)
+constexpr int kRingMaxNL = 3;
+constexpr int kRingLds = kRingB * 1024 + 4 * kRingMaxNL * kRingA * 64;
 
 template <int NL>
-__device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, unsigned char* ring) {
-  const int tid = threadIdx.x, lane = tid & 63;
+__device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, unsigned char* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const bool active = task < ntask;                // uniform over the wave
   const int f = task >= d.c_rta ? 1 : 0;
@@ -2713,36 +2725,41 @@ __device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, uns
   const int M = f ? d.vb.m : d.va.m;
   const int ntc = active ? min(4, (M - 1024 * rt + 15) >> 4) : 0;
   const int lp = d.c_lp, KS = d.c_ks;
+  const int R0 = kCgRows * rt;
   const __amdgpu_buffer_rsrc_t ra =
       uniform_rsrc(d.ylimb + (int64_t)f * d.c_nlcap * lp, (uint32_t)(d.c_nlcap * lp));
   const __amdgpu_buffer_rsrc_t rb = uniform_rsrc(d.tsh, (uint32_t)(16 * d.c_lt));
-  const int aoff = 64 * (kCgRows * rt + c) + 16 * g;
+  unsigned char* ringb = lds;
+  unsigned char* ringa = lds + kRingB * 1024 + w * (kRingMaxNL * kRingA * 64);
   int boff[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     const int j0 = 16 * g - (16 * nt + c) + kCgPad;
     boff[nt] = (j0 + 2 * ((-j0) & 15)) * 16;
   }
-  // staging: thread tid moves 16 bytes at 16 tid and 16 tid + 4096 of each
-  // 8 KiB group of blocks (bytes past the copies read as zero)
-  auto stage_load = [&](int blk0, v4i_t (&v)[2]) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) v[r] = buf_v4i(rb, 16 * tid + 4096 * r, 1024 * blk0);
-  };
-  auto stage_store = [&](int blk0, const v4i_t (&v)[2]) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int b = blk0 + 4 * r + (tid >> 6);
-      *reinterpret_cast<v4i_t*>(ring + ((b & (kRingBlocks - 1)) << 10) + 16 * (tid & 63)) = v[r];
-    }
-  };
-  // prologue: blocks 0 .. 15
+  // prologue: B blocks 0 .. 11 (three 4 KiB rounds of the workgroup), A rows
+  // R0 .. R0+31 of each digit (two 1 KiB rounds of the wave)
   {
-    v4i_t v0[2], v1[2];
-    stage_load(0, v0);
-    stage_load(8, v1);
-    stage_store(0, v0);
-    stage_store(8, v1);
+    v4i_t vb[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) vb[r] = buf_v4i(rb, 16 * tid, 4096 * r);
+    v4i_t va[NL][2];
+    if (active)
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) va[l][q] = buf_v4i(ra, 16 * lane, l * lp + 64 * R0 + 1024 * q);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) *reinterpret_cast<v4i_t*>(ringb + 4096 * r + 16 * tid) = vb[r];
+    if (active)
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int row = R0 + 16 * q + (lane >> 2);
+          *reinterpret_cast<v4i_t*>(ringa + l * (kRingA * 64) + ((row & (kRingA - 1)) << 6) + 16 * (lane & 3)) =
+              va[l][q];
+        }
   }
   __syncthreads();
   v4i_t acc[NL][4];
@@ -2750,14 +2767,15 @@ __device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, uns
   for (int l = 0; l < NL; ++l)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[l][nt] = v4i_t{0, 0, 0, 0};
-  auto load_a = [&](int st, v4i_t (&a)[NL]) {
+  auto read_a = [&](int st, v4i_t (&a)[NL]) {
+    const int off = (((R0 + c + st) & (kRingA - 1)) << 6) + 16 * g;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) a[l] = buf_v4i(ra, aoff, l * lp + 64 * st);
+    for (int l = 0; l < NL; ++l) a[l] = *reinterpret_cast<const v4i_t*>(ringa + l * (kRingA * 64) + off);
   };
   auto read_b = [&](int st, v4i_t (&b)[4]) {
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
-      b[nt] = *reinterpret_cast<const v4i_t*>(ring + ((1024 * st + boff[nt]) & (kRingBlocks * 1024 - 1)));
+      b[nt] = *reinterpret_cast<const v4i_t*>(ringb + ((1024 * st + boff[nt]) & (kRingB * 1024 - 1)));
   };
   auto step = [&](const v4i_t (&a)[NL], const v4i_t (&b)[4]) {
 #pragma unroll
@@ -2769,32 +2787,40 @@ __device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, uns
       }
     }
   };
-  // A (global) and B (ring) of the next step are read while the products of
-  // the current one run: two register sets, steps in pairs.  The B read of
-  // the step after a phase touches blocks staged before that phase.
+  // the operands of the next step are read while the products of the
+  // current one run: two register sets, steps in pairs
   v4i_t a0[NL], a1[NL], b0[4], b1[4];
   if (active) {
-    load_a(0, a0);
+    read_a(0, a0);
     read_b(0, b0);
   }
   for (int p0 = 0; p0 < KS; p0 += kRingPhase) {
-    v4i_t nx[2];
-    stage_load(p0 + 16, nx);
+    // B blocks p0+12 .. p0+15 (one 4 KiB round); A rows R0+p0+32 .. +35
+    const v4i_t nb = buf_v4i(rb, 16 * tid, 1024 * (p0 + 12));
+    int na[NL];
+    if (active)
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        na[l] = (int)__builtin_amdgcn_raw_buffer_load_b32(ra, 4 * lane, l * lp + 64 * (R0 + p0 + 32), 0);
     if (active) {
-      // the phase's steps in pairs (KS is a multiple of 4; a phase holds 8 or,
-      // last, 4 steps); the last pair reloads the final step (unused)
-      const int pe = min(p0 + kRingPhase, KS);
-      for (int st = p0; st < pe; st += 2) {
-        load_a(st + 1, a1);
+#pragma unroll
+      for (int st = p0; st < p0 + kRingPhase; st += 2) {
+        read_a(st + 1, a1);
         read_b(st + 1, b1);
         step(a0, b0);
         const int sn = min(st + 2, KS - 1);
-        load_a(sn, a0);
+        read_a(sn, a0);
         read_b(sn, b0);
         step(a1, b1);
       }
     }
-    stage_store(p0 + 16, nx);
+    *reinterpret_cast<v4i_t*>(ringb + (((p0 + 12) & (kRingB - 1)) << 10) + 16 * tid) = nb;
+    if (active) {
+      const int row = R0 + p0 + 32 + (lane >> 4);
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        *reinterpret_cast<int*>(ringa + l * (kRingA * 64) + ((row & (kRingA - 1)) << 6) + 4 * (lane & 15)) = na[l];
+    }
     __syncthreads();
   }
   if (active) cg2_report<NL>(d, f, rt, nullptr, acc, nullptr);
@@ -2805,7 +2831,8 @@ __device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, uns
 // digits of a fold that needs fewer are zero rows)
 template <int MAXNL>
 __global__ void __launch_bounds__(256) k_cgemm_ring(InstTable tab, const int32_t* list) {
-  __shared__ __align__(16) unsigned char ring[kRingBlocks * 1024];
+  static_assert(MAXNL <= kRingMaxNL, "ring sized for three digits");
+  __shared__ __align__(16) unsigned char lds[kRingLds];
   const Inst& d = list ? tab.table[list[blockIdx.x]] : tab.resident();
   const int ntask = d.c_rta + d.c_rtb;
   const int t0 = blockIdx.y * 4;
@@ -2816,9 +2843,9 @@ __global__ void __launch_bounds__(256) k_cgemm_ring(InstTable tab, const int32_t
   const int nl = min(min(cg_limbs(mx), d.c_nlcap), MAXNL);
   const int task = __builtin_amdgcn_readfirstlane(t0 + (int)(threadIdx.x >> 6));
   switch (nl) {
-    case 1: cgr_tile<1>(d, task, ntask, ring); break;
-    case 2: cgr_tile<2>(d, task, ntask, ring); break;
-    default: cgr_tile<3>(d, task, ntask, ring); break;
+    case 1: cgr_tile<1>(d, task, ntask, lds); break;
+    case 2: cgr_tile<2>(d, task, ntask, lds); break;
+    default: cgr_tile<3>(d, task, ntask, lds); break;
   }
 }
 
