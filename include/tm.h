@@ -268,11 +268,14 @@ tm_status tm_batch_destroy(tm_batch batch);
 /*
  * tm_match_many -- one template, `count` signals of the plan's N (Algorithm 1
  * per signal).  xs is a host array of count device pointers; out holds count
- * results (host or device, as tm_match).  For exact int8 plans (K <= 2^14,
- * folds of at most 2^13 rows) the correlations of all signals are one banded
- * Toeplitz product computed with int8 MFMA (the folds split into base-128 int8
- * digits, exact int32/int64 sums); every result equals tm_match's bit for bit.
- * Other plans run as tm_match_batch with the plan repeated.
+ * results (host or device, as tm_match); every result equals tm_match's bit
+ * for bit.  By default it runs as tm_match_batch with the plan repeated (for
+ * exact int8 plans: one int8 MFMA product per signal, its template copies
+ * staged once per workgroup).  With the environment variable TM_MANY_GEMM=1,
+ * exact int8 plans (K <= 2^14, folds of at most 2^13 rows) instead take one
+ * banded Toeplitz product over all signals (the folds split into base-128
+ * int8 digits, exact int32/int64 sums), which reads the template once per
+ * signal tile; at N = 2^18, K = 1024 it is the slower of the two.
  */
 tm_status tm_match_many(tm_plan plan, int32_t count, const void* const* xs, tm_result* out, void* stream);
 

@@ -2203,24 +2203,23 @@ int cgemm_limbs_for(int64_t maxabs) { return cg_limbs(maxabs); }
 // variant keeps the periodic bucket sums), their digits, the intermediates and
 // each fold's largest |y|
 template <typename Tin, bool GENERAL>
-__device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
-  __shared__ int wmax[2][kCgPrepThreads / 64];
-  // everything the loop needs in registers: its global stores could alias the
-  // instance table as far as the compiler knows
-  const int lp = d.c_lp, nlc = d.c_nlcap;
-  const int ma = d.va.m, mb = d.vb.m, K = d.k;
-  const int64_t N = d.n, La = d.va.l, Lb = d.vb.l;
+__device__ void cg_prep_chunk(const Inst& d, int f, int e0, int chunk) {
+  __shared__ int wmax[kCgPrepThreads / 64];
+  // everything the loop needs in registers (its global stores could alias
+  // the instance table as far as the compiler knows), the fold's values
+  // uniform over the workgroup
+  const int lp = d.c_lp, nlc = d.c_nlcap, K = d.k;
+  const int M = f ? d.vb.m : d.va.m;
+  const int64_t N = d.n, L = f ? d.vb.l : d.va.l;
   const bool sfold = d.sfold != 0, zpad = d.zpad != 0;
-  const int rhoA = (int)(N - (La - 1) * ma), rhoB = (int)(N - (Lb - 1) * mb);
-  const int biasA = sfold ? 128 * ((int)La - 1) : 0, biasB = sfold ? 128 * ((int)Lb - 1) : 0;
-  const GAS int* yp = G(d.yp);
+  const int rho = (int)(N - (L - 1) * M);
+  const int bias = sfold ? 128 * ((int)L - 1) : 0;
+  const GAS int* yp = G(d.yp) + (f ? d.va.m : 0);
   const void* x = d.x;
-  double* dyA = d.swapped ? d.dbg_y2 : d.dbg_y1;
-  double* dyB = d.swapped ? d.dbg_y1 : d.dbg_y2;
-  GAS int8_t* limb = G(d.ylimb);
-  GAS int* cmax = G(d.cmax);
-  int mx[2] = {0, 0};
-  const int e1 = min(e0 + chunk, 2 * lp);
+  double* dy = (f != d.swapped) ? d.dbg_y2 : d.dbg_y1;
+  GAS int8_t* limb = G(d.ylimb) + (int64_t)f * nlc * lp;
+  int mx = 0;
+  const int e1 = min(e0 + chunk, lp);
   // a trip: four entries per thread, kCgPrepThreads apart, so that every load
   // and store instruction of a wave covers consecutive entries (one or two
   // cache lines).  Every load of a trip is issued first, at valid addresses
@@ -2235,16 +2234,12 @@ __device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
     bool in[U], wrap[U], ext[U];
 #pragma unroll
     for (int i = 0; i < U; ++i) {
-      const int e = eb + i * kCgPrepThreads;
-      const int f = e >= lp ? 1 : 0;
-      const int M = f ? mb : ma;
-      const int rho = f ? rhoB : rhoA;
-      const int u = e - f * lp;
-      in[i] = e < e1 && u < M + K - 1;
+      const int u = eb + i * kCgPrepThreads;
+      in[i] = u < e1 && u < M + K - 1;
       const int s = !in[i] ? 0 : (u < M ? u : u - M);
       wrap[i] = !zpad && in[i] && s >= rho;
       ext[i] = !zpad && in[i] && u >= M;
-      val[i] = yp[(f ? ma : 0) + s];
+      val[i] = yp[s];
       int64_t iw, ie;
       if constexpr (GENERAL) {
         iw = mod_small((int64_t)(s - rho), N, true);
@@ -2257,77 +2252,69 @@ __device__ void cg_prep_chunk(const Inst& d, int e0, int chunk) {
       xw[i] = ld_int<Tin>(x, wrap[i] ? iw : 0);
       xe[i] = ld_int<Tin>(x, ext[i] ? ie : 0);
       xs[i] = ld_int<Tin>(x, ext[i] ? s : 0);
-      if (sfold) val[i] -= (f ? biasB : biasA) + (s < rho ? 128 : 0);
+      if (sfold) val[i] -= bias + (s < rho ? 128 : 0);
     }
 #pragma unroll
     for (int i = 0; i < U; ++i) {
-      const int e = eb + i * kCgPrepThreads;
-      const int f = e >= lp ? 1 : 0;
       int v = in[i] ? val[i] : 0;
       v += (wrap[i] ? xw[i] : 0) + (ext[i] ? xe[i] - xs[i] : 0);
       val[i] = v;
-      mx[f] = max(mx[f], v < 0 ? -v : v);
+      mx = max(mx, v < 0 ? -v : v);
     }
 #pragma unroll
     for (int i = 0; i < U; ++i) {
-      const int e = eb + i * kCgPrepThreads;
-      if (e >= e1) break;
-      const int f = e >= lp ? 1 : 0;
-      const int u = e - f * lp;
-      double* dy = f ? dyB : dyA;
+      const int u = eb + i * kCgPrepThreads;
+      if (u >= e1) break;
       if (dy && in[i]) G(dy)[u] = (double)val[i];
-      GAS int8_t* dst = limb + (int64_t)f * nlc * lp + u;
       int v = val[i];
       for (int l = 0; l < nlc; ++l) {
-        const int digit = ((v + 64) & 127) - 64;
-        v = (v - digit) >> 7;
-        dst[(int64_t)l * lp] = (int8_t)digit;
+        const int t = v + 64;                       // balanced base-128 digit
+        limb[(int64_t)l * lp + u] = (int8_t)((t & 127) - 64);
+        v = t >> 7;
       }
     }
   }
 #pragma unroll
-  for (int f = 0; f < 2; ++f) {
-    int m = mx[f];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) wmax[f][threadIdx.x >> 6] = m;
-  }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
   __syncthreads();
-  if (threadIdx.x < 2) {
-    const int f = threadIdx.x;
-    int m = wmax[f][0];
-    for (int w = 1; w < kCgPrepThreads / 64; ++w) m = max(m, wmax[f][w]);
-    if (m) __hip_atomic_fetch_max(cmax + f, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    int m = wmax[0];
+    for (int w = 1; w < kCgPrepThreads / 64; ++w) m = max(m, wmax[w]);
+    if (m) __hip_atomic_fetch_max(G(d.cmax) + f, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 // the loop without int64 remainders (no branches between an entry's loads)
 // unless N < M, where a fold's indices can wrap more than once
-__device__ __forceinline__ void cg_prep_dispatch(const Inst& d, int e0, int chunk) {
-  if (e0 >= 2 * d.c_lp) return;
+__device__ __forceinline__ void cg_prep_dispatch(const Inst& d, int f, int e0, int chunk) {
+  if (e0 >= d.c_lp) return;
   if (d.n < (int64_t)max(d.va.m, d.vb.m)) {
     switch (d.x_dtype) {
-      case TM_I8: cg_prep_chunk<int8_t, true>(d, e0, chunk); break;
-      case TM_F32: cg_prep_chunk<float, true>(d, e0, chunk); break;
-      case TM_BF16: cg_prep_chunk<bf16_t, true>(d, e0, chunk); break;
-      default: cg_prep_chunk<f16_t, true>(d, e0, chunk); break;
+      case TM_I8: cg_prep_chunk<int8_t, true>(d, f, e0, chunk); break;
+      case TM_F32: cg_prep_chunk<float, true>(d, f, e0, chunk); break;
+      case TM_BF16: cg_prep_chunk<bf16_t, true>(d, f, e0, chunk); break;
+      default: cg_prep_chunk<f16_t, true>(d, f, e0, chunk); break;
     }
     return;
   }
   switch (d.x_dtype) {
-    case TM_I8: cg_prep_chunk<int8_t, false>(d, e0, chunk); break;
-    case TM_F32: cg_prep_chunk<float, false>(d, e0, chunk); break;
-    case TM_BF16: cg_prep_chunk<bf16_t, false>(d, e0, chunk); break;
-    default: cg_prep_chunk<f16_t, false>(d, e0, chunk); break;
+    case TM_I8: cg_prep_chunk<int8_t, false>(d, f, e0, chunk); break;
+    case TM_F32: cg_prep_chunk<float, false>(d, f, e0, chunk); break;
+    case TM_BF16: cg_prep_chunk<bf16_t, false>(d, f, e0, chunk); break;
+    default: cg_prep_chunk<f16_t, false>(d, f, e0, chunk); break;
   }
 }
 
-// grid (instances, chunks): blockIdx.x picks the instance from the list,
-// blockIdx.y its chunk of `chunk` entries
+// grid (instances, 2 x chunks per fold): blockIdx.x picks the instance from
+// the list; the first half of blockIdx.y covers fold A, the second fold B,
+// `chunk` entries each
 __global__ void __launch_bounds__(kCgPrepThreads) k_cgemm_prep(InstTable tab, const int32_t* list, int chunk) {
-  const int e0 = blockIdx.y * chunk;
-  if (list) cg_prep_dispatch(tab.table[list[blockIdx.x]], e0, chunk);
-  else cg_prep_dispatch(tab.resident(), e0, chunk);
+  const int cpf = gridDim.y >> 1;
+  const int f = (int)blockIdx.y >= cpf ? 1 : 0;
+  const int e0 = ((int)blockIdx.y - f * cpf) * chunk;
+  if (list) cg_prep_dispatch(tab.table[list[blockIdx.x]], f, e0, chunk);
+  else cg_prep_dispatch(tab.resident(), f, e0, chunk);
 }
 
 // The W parts of a workgroup's 16 x 64 tile summed in LDS (int64; with 8

@@ -161,15 +161,17 @@ int64_t launch_seg_chunks(const Core& c, int64_t launch_bytes) {
 }
 
 // Literal-fold entries per prep workgroup: about 4096 workgroups over the
-// launch's entries, at least 1024 (four per thread) and at most one
-// instance's pair of folds; grid rows = chunks of the largest instance.
+// launch's entries (TM_CG_PREP_WGS), at least 1024 (four per thread) and at
+// most one fold; grid rows = 2 x the chunks of the largest instance's fold
+// (fold A's chunks, then fold B's).  max_entries: the largest 2 c_lp.
 struct CgLaunch { int chunk; int prep_y; };
 CgLaunch cgemm_launch(int64_t total_entries, int64_t max_entries, int64_t count) {
   (void)count;
   const int64_t wgs = std::max<int64_t>(1, env_int("TM_CG_PREP_WGS", 4096));
+  const int64_t fold_max = ceil_div(max_entries, 2);
   int64_t chunk = std::max<int64_t>(1024, align_up(ceil_div(total_entries, wgs), 1024));
-  chunk = std::min(chunk, align_up(max_entries, 1024));
-  return CgLaunch{(int)chunk, (int)ceil_div(max_entries, chunk)};
+  chunk = std::min(chunk, align_up(fold_max, 1024));
+  return CgLaunch{(int)chunk, (int)(2 * ceil_div(fold_max, chunk))};
 }
 
 // t_i8: every template value is an integer in [-128, 127] (known for int8
@@ -1684,10 +1686,10 @@ tm_status tm_match_batch(int32_t count, const tm_plan* plans, const void* const*
   return run_batch((int32_t)ep.size(), ep.data(), ex.data(), out, stream, &cmb);
 }
 
-// One template, many signals of the plan's N: the signals' folds form the
-// rows of one int8 MFMA GEMM against the shared template (exact int8 plans
-// with K <= 2^14 and folds of at most 2^13 rows, not TM_F_FFT); other plans,
-// or TM_MANY_BATCH=1, take tm_match_batch (independent matches).
+// One template, many signals of the plan's N: tm_match_batch with the plan
+// repeated (independent matches); with TM_MANY_GEMM=1 the signals' folds form
+// the rows of one int8 MFMA GEMM against the shared template instead (exact
+// int8 plans with K <= 2^14 and folds of at most 2^13 rows, not TM_F_FFT).
 tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_result* out, void* stream) {
   if (!p || count < 0) return fail(TM_ERR_INVALID, "null plan or negative count");
   if (count == 0) return TM_OK;
@@ -1700,11 +1702,12 @@ tm_status tm_match_many(tm_plan p, int32_t count, const void* const* xs, tm_resu
   }
   const Core& c = p->core;
   // the shared GEMM reads the plan's template copies (exact plans of the
-  // int8 product route)
+  // int8 product route), when asked for: the batch of per-signal products
+  // is the faster route at the shapes measured
   const bool gemm = c.cgemm && c.x_dtype == TM_I8 && c.t_dtype == TM_I8 && c.mode == MODE_EXACT && c.k <= (1 << 14) &&
                     std::max(c.va.l, c.vb.l) <= (1 << 13) && !(p->desc.flags & TM_F_FFT) && c.top_t == 1 &&
                     !c.three &&
-                    env_int("TM_MANY_BATCH", 0) == 0;
+                    env_int("TM_MANY_GEMM", 0) == 1;
   if (!gemm) {
     std::vector<tm_plan> plans((size_t)count, p);
     return tm_match_batch(count, plans.data(), xs, out, stream);

@@ -20,6 +20,13 @@ def _case(*a):
     print("case:", *a, flush=True)
 
 
+@pytest.fixture(autouse=True)
+def shared_gemm(monkeypatch):
+    # tm_match_many's shared-template GEMM (its default is the batch of
+    # per-signal products, covered by the batch tests and compared below)
+    monkeypatch.setenv("TM_MANY_GEMM", "1")
+
+
 def _check_many(insts, plan, oracle_every=7):
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
     many = tm.Many(plan, xs).match()
@@ -81,6 +88,6 @@ def test_fft_and_gemm_paths_agree(monkeypatch):
     xs = [torch.from_numpy(s.x).cuda() for s in insts]
     shared = tm.Many(plan, xs).match()
     fft = tm.Many(tm.Plan(insts[0].t, n=1 << 16, flags=tm.TM_F_FFT), xs).match()
-    monkeypatch.setenv("TM_MANY_BATCH", "1")
+    monkeypatch.setenv("TM_MANY_GEMM", "0")
     per_instance = tm.Many(plan, xs).match()
     assert shared == fft == per_instance
