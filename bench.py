@@ -8,7 +8,8 @@ more than the 256 MB memory-side cache holds).  Other workloads: config1
 match per launch), config4 (request server: open-loop p50/p99 at the offered
 rate and saturation vs plain launch), config5a (N = 2^24 fp32, K = 2^14 at
 -3 dB with FP32/BF16/FP16 fold storage, error against FP64), config5b (1024
-signals sharing one template: int8 MFMA GEMM vs the FFT path).
+signals sharing one template: tm_match_many's per-signal int8 products against
+its shared-template GEMM and the FFT path).
 
 Prints one JSON line: whole-job matches/s over the timed steps; per-step
 times (HIP events on the launch stream); `roofline` for the dominant kernel
@@ -43,8 +44,8 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1509_04863_amd", "csrc", "tm_kernels.hip
 # HBM bytes per launch (FETCH_SIZE + WRITE_SIZE from rocprofv3 --pmc, each
 # scaled by a plain copy's reading; summaries under profiles/), valid only for
 # the kernel source they were taken on: `traffic` is null for any other.
-TRAFFIC_SRC_SHA = "99e0ec1b5b9e3d14"
-TRAFFIC_BYTES = {"k_fold_s8/config3": 1609312080, "corr/config3": 269115607}
+TRAFFIC_SRC_SHA = "f3c1433b157717fb"
+TRAFFIC_BYTES = {"k_fold_s8/config3": 1609289015, "corr/config3": 269103690}
 
 
 def kernels_sha() -> str:
