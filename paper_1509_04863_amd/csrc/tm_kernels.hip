@@ -2815,9 +2815,12 @@ __device__ __forceinline__ void cgr_tile(const Inst& d, int task, int ntask, uns
 
 // grid (instances, groups of four row tiles); one row tile per wave, the
 // digit count of the group's folds taken for all four waves (the extra
-// digits of a fold that needs fewer are zero rows)
+// digits of a fold that needs fewer are zero rows).  Four waves per SIMD
+// (128 registers; the LDS allows four workgroups per compute unit): the
+// kernel waits on latency, and the fourth wave is worth more than the few
+// spilled registers of the three-digit variant.
 template <int MAXNL>
-__global__ void __launch_bounds__(256) k_cgemm_ring(InstTable tab, const int32_t* list) {
+__global__ void __launch_bounds__(256, 4) k_cgemm_ring(InstTable tab, const int32_t* list) {
   static_assert(MAXNL <= kRingMaxNL, "ring sized for three digits");
   __shared__ __align__(16) unsigned char lds[kRingLds];
   const Inst& d = list ? tab.table[list[blockIdx.x]] : tab.resident();
