@@ -149,3 +149,40 @@ def test_band_split_over_workgroups(split, top_t, monkeypatch):
     assert (res.m1_tilde, res.m2_tilde) == (ref.m1_tilde, ref.m2_tilde)
     plain = tm.match(plan, to_device(x))
     assert plain == res
+
+
+@pytest.mark.parametrize("kind", ["0", "4"], ids=["automatic product", "LDS ring"])
+def test_batch_mixes_digit_counts(kind, monkeypatch):
+    # one batch whose instances need 1, 2 and 3 digits (the ring kernel takes
+    # the digit count per workgroup, and a workgroup may hold row tiles of
+    # both folds): every result equals the single match and the oracle's
+    monkeypatch.setenv("TM_CGEMM_KIND", kind)
+    rng = np.random.default_rng(77)
+    plans, xs, refs = [], [], []
+    for i in range(18):
+        n = int(rng.integers(40000, 300000))
+        k = int(rng.choice([300, 700, 1500, 2600]))
+        if i % 3 == 0:
+            x = rng.integers(-1, 2, n).astype(np.int8)         # small folds
+            t = rng.choice(np.array([-1, 1], dtype=np.int8), k)
+        elif i % 3 == 1:
+            x = rng.choice(np.array([-1, 1], dtype=np.int8), n)
+            t = rng.choice(np.array([-1, 1], dtype=np.int8), k)
+        else:
+            x = rng.integers(-128, 128, n).astype(np.int8)     # three digits
+            x[: n // 3] = 127
+            t = rng.integers(-128, 128, k).astype(np.int8)
+        plans.append(tm.Plan(t, n=n))
+        xs.append(to_device(x))
+        refs.append((x, t))
+    assert all(p.info["corr_gemm"] for p in plans)
+    _case("mixed digit counts", kind, len(plans))
+    batch = tm.match_batch(plans, xs)
+    monkeypatch.setenv("TM_CGEMM_KIND", "0")
+    single = [tm.match(p, x) for p, x in zip(plans, xs)]
+    assert batch == single
+    for (x, t), p, r in list(zip(refs, plans, batch))[::2]:
+        ref = O.ftm(x, t, p.m1, p.m2)
+        assert (r.shift, r.m1_tilde, r.m2_tilde, r.n_candidates) == \
+            (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
+        assert r.peak1 == float(ref.peak1) and r.peak2 == float(ref.peak2)
