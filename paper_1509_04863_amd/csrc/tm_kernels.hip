@@ -19,10 +19,12 @@
 //   k_fold_s8 / k_fold_band   streaming fold of int8 signals through an LDS
 //              ring, band fold of 4-byte signals (both moduli in one pass).
 //   k_gfft_*   the FFT correlation through global memory for P above LDS.
-//   k_cgemm_prep / k_cgemm / k_cgemm_final   exact plans with an int8-valued
-//              template: the correlation of steps 4-6 computed directly as an
-//              int8 MFMA product of the literal folds' base-128 digits with
-//              the banded Toeplitz block of t, argmax, resolve.
+//   k_cgemm_prep / k_cgemm / k_cgemm_wave / k_cgemm_ring / k_cgemm_final
+//              exact plans with an int8-valued template: the correlation of
+//              steps 4-6 computed directly as an int8 MFMA product of the
+//              literal folds' base-128 digits with the banded Toeplitz block
+//              of t (row tiles per workgroup, per wave, or per wave with both
+//              operands staged in LDS rings), argmax, resolve.
 //   k_many_*   one template, many signals: one GEMM against the template.
 //   k_combine3 three moduli: intersection of the three candidate sets.
 //   k_twiddles FP64 twiddles exp(-2 pi i e / P) (stored FP64 or FP32).
