@@ -257,12 +257,14 @@ hipError_t launch_cgemm_prep(const InstTable& tab, const int32_t* list, int coun
 hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,
                              hipStream_t s);
 // int8 batches: the per-wave product with the template copies staged in an
-// LDS ring per workgroup (digit counts up to 3)
+// LDS ring per workgroup (digit counts up to 3); it also returns the
+// instances' bucket zones to zero (the final kernel then takes yp_done)
 hipError_t launch_cgemm_ring(const InstTable& tab, const int32_t* list, int count, int gemm_y, hipStream_t s);
 // lean: every listed instance has an int8 signal and template, top_t 1 and
-// an unsplit band
+// an unsplit band; yp_done: the product kernel (k_cgemm_ring) has already
+// cleared the instances' bucket zones
 hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s,
-                              bool lean = false);
+                              bool lean = false, bool yp_done = false);
 // batches: one wave per row tile over the whole band (gemm_y row tiles per
 // instance at most, four per workgroup), per-column-tile bests to cpart
 hipError_t launch_cgemm_wave(const InstTable& tab, const int32_t* list, int count, int gemm_y, int max_limbs,

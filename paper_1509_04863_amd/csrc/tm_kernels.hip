@@ -2494,8 +2494,9 @@ __global__ void __launch_bounds__(64 * W) k_cgemm(InstTable tab, const int32_t* 
 }
 
 // LEAN: int8 signal and template, one workgroup per band, no top-T (the
-// common batch; fewer registers, so more workgroups resident)
-template <typename Tin, bool LEAN = false>
+// common batch; fewer registers, so more workgroups resident).  YP_DONE: the
+// product kernel has already returned the bucket zone to zero.
+template <typename Tin, bool LEAN = false, bool YP_DONE = false>
 __device__ __forceinline__ void cg_final(const Inst& d) {
   __shared__ __align__(16) unsigned char scratch[16 * 16];
   __shared__ VI fin[2];
@@ -2561,8 +2562,10 @@ __device__ __forceinline__ void cg_final(const Inst& d) {
     if (lane == 0) fin[f] = best;
   }
   // the buckets and the fold maxima have been consumed: back to zero
-  const int nz = d.va.m + d.vb.m;
-  for (int s = threadIdx.x; s < nz; s += blockDim.x) G(d.yp)[s] = 0;
+  if constexpr (!YP_DONE) {
+    const int nz = d.va.m + d.vb.m;
+    for (int s = threadIdx.x; s < nz; s += blockDim.x) G(d.yp)[s] = 0;
+  }
   if (threadIdx.x < 2) G(d.cmax)[threadIdx.x] = 0;
   __syncthreads();
   if (!LEAN && d.top_t > 1) resolve_top_t<Tin>(d, fin[0], fin[1], TM_R_EXACT, scratch);
@@ -2578,10 +2581,10 @@ __device__ __forceinline__ void cg_final_dispatch(const Inst& d) {
   }
 }
 
-template <bool LEAN>
+template <bool LEAN, bool YP_DONE>
 __global__ void __launch_bounds__(256) k_cgemm_final(InstTable tab, const int32_t* list) {
   const Inst& d = list ? tab.table[list[blockIdx.x]] : tab.resident();
-  if constexpr (LEAN) cg_final<int8_t, true>(d);
+  if constexpr (LEAN) cg_final<int8_t, true, YP_DONE>(d);
   else cg_final_dispatch(d);
 }
 
@@ -2838,6 +2841,13 @@ __global__ void __launch_bounds__(256, 4) k_cgemm_ring(InstTable tab, const int3
     case 1: cgr_tile<1>(d, task, ntask, lds); break;
     case 2: cgr_tile<2>(d, task, ntask, lds); break;
     default: cgr_tile<3>(d, task, ntask, lds); break;
+  }
+  // the instance's bucket zone has been consumed (by the prep kernel): the
+  // first workgroup returns it to zero here, where the stores overlap the
+  // other workgroups' products, instead of in the final kernel
+  if (blockIdx.y == 0) {
+    const int nz = d.va.m + d.vb.m;
+    for (int s = threadIdx.x; s < nz; s += blockDim.x) G(d.yp)[s] = 0;
   }
 }
 
@@ -3181,10 +3191,13 @@ hipError_t launch_cgemm_gemm(const InstTable& tab, const int32_t* list, int coun
   return hipGetLastError();
 }
 
-hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s, bool lean) {
+hipError_t launch_cgemm_final(const InstTable& tab, const int32_t* list, int count, hipStream_t s, bool lean,
+                              bool yp_done) {
   if (count <= 0) return hipSuccess;
-  if (lean) TM_LAUNCH(k_cgemm_final<true>, dim3(count), dim3(256), 0, s, tab, list);
-  else TM_LAUNCH(k_cgemm_final<false>, dim3(count), dim3(256), 0, s, tab, list);
+  if (lean && yp_done) TM_LAUNCH((k_cgemm_final<true, true>), dim3(count), dim3(256), 0, s, tab, list);
+  else if (lean) TM_LAUNCH((k_cgemm_final<true, false>), dim3(count), dim3(256), 0, s, tab, list);
+  else if (yp_done) TM_LAUNCH((k_cgemm_final<false, true>), dim3(count), dim3(256), 0, s, tab, list);
+  else TM_LAUNCH((k_cgemm_final<false, false>), dim3(count), dim3(256), 0, s, tab, list);
   return hipGetLastError();
 }
 

@@ -1161,14 +1161,15 @@ static tm_status match_one(tm_plan p, const void* x, tm_result* out, double* y1,
   } else if (cc.cgemm) {
     const CgLaunch cl = cgemm_launch(2 * (int64_t)cc.c_lp, 2 * (int64_t)cc.c_lp, 1);
     TM_HIP(launch_cgemm_prep(tab, nullptr, 1, cl.chunk, cl.prep_y, s));
-    if (split == 1 && cgemm_kind() == 4 && cc.c_nlcap <= 3)
+    const bool ring = split == 1 && cgemm_kind() == 4 && cc.c_nlcap <= 3;
+    if (ring)
       TM_HIP(timed_corr(s, [&] { return launch_cgemm_ring(tab, nullptr, 1, cc.c_rta + cc.c_rtb, s); }));
     else if (split == 1 && (cgemm_kind() == 3 || cgemm_kind() == 4))
       TM_HIP(timed_corr(s, [&] { return launch_cgemm_wave(tab, nullptr, 1, cc.c_rta + cc.c_rtb, cc.c_nlcap, s); }));
     else
       TM_HIP(timed_corr(s, [&] { return launch_cgemm_gemm(tab, nullptr, 1, (cc.c_rta + cc.c_rtb) * split,
                                                           cc.c_nlcap, s); }));
-    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s, split == 1 && cg_lean_core(cc)));
+    TM_HIP(launch_cgemm_final(tab, nullptr, 1, s, split == 1 && cg_lean_core(cc), ring));
   }
   else if (p->core.gfft) TM_HIP(launch_gfft(one, dev_one, s));
   else TM_HIP(timed_corr(s, [&] { return launch_finish(tab, nullptr, 1, p->core.mode, p->core.p_log2,
@@ -1465,7 +1466,7 @@ static hipError_t launch_batch(const BatchPlan& b, const tm_plan* plans, const I
                       : launch_cgemm_gemm(tab, dlist, ncg_inst, (int)b.cgs, (int)b.cg_limbs_max, s);
     });
     if (e != hipSuccess) return e;
-    if ((e = launch_cgemm_final(tab, dlist, ncg_inst, s, b.cg_lean)) != hipSuccess) return e;
+    if ((e = launch_cgemm_final(tab, dlist, ncg_inst, s, b.cg_lean, ring)) != hipSuccess) return e;
   }
   for (int32_t g0 = ncg_inst; g0 < b.count;) {
     const Core& c0 = plans[order[g0]]->core;
