@@ -44,8 +44,8 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1509_04863_amd", "csrc", "tm_kernels.hip
 # HBM bytes per launch (FETCH_SIZE + WRITE_SIZE from rocprofv3 --pmc, each
 # scaled by a plain copy's reading; summaries under profiles/), valid only for
 # the kernel source they were taken on: `traffic` is null for any other.
-TRAFFIC_SRC_SHA = "217ba92e0144a5b0"
-TRAFFIC_BYTES = {"k_fold_s8/config3": 1609321060, "corr/config3": 276129085}
+TRAFFIC_SRC_SHA = "34199b9ee538f0be"
+TRAFFIC_BYTES = {"k_fold_s8/config3": 1609298807, "corr/config3": 326735633}
 
 
 def kernels_sha() -> str:
