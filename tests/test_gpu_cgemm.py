@@ -186,3 +186,31 @@ def test_batch_mixes_digit_counts(kind, monkeypatch):
         assert (r.shift, r.m1_tilde, r.m2_tilde, r.n_candidates) == \
             (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
         assert r.peak1 == float(ref.peak1) and r.peak2 == float(ref.peak2)
+
+
+@pytest.mark.parametrize("kind", ["3", "4"], ids=["wave per row tile", "LDS ring"])
+def test_batch_top_t_on_per_wave_kernels(kind, monkeypatch):
+    # top-T re-scoring in a batch on the per-wave product kernels (the ring
+    # kernel clears the bucket zone itself, the final kernel then takes the
+    # top-T branch): equal to single matches and to the oracle
+    monkeypatch.setenv("TM_CGEMM_KIND", kind)
+    rng = np.random.default_rng(5 + int(kind))
+    plans, xs, refs = [], [], []
+    for i in range(8):
+        n = int(rng.integers(50000, 200000))
+        k = int(rng.choice([400, 1100, 2000]))
+        x = rng.integers(-128, 128, n).astype(np.int8)
+        t = rng.integers(-3, 4, k).astype(np.int8)
+        at = int(rng.integers(0, n - k))
+        x[at:at + k] = t
+        plans.append(tm.Plan(t, n=n, top_t=3))
+        xs.append(to_device(x))
+        refs.append((x, t))
+    _case("batch top_t", kind, len(plans))
+    batch = tm.match_batch(plans, xs)
+    monkeypatch.setenv("TM_CGEMM_KIND", "0")
+    assert batch == [tm.match(p, x) for p, x in zip(plans, xs)]
+    for (x, t), p, r in zip(refs, plans, batch):
+        ref = O.ftm(x, t, p.m1, p.m2, top_t=3)
+        assert (r.shift, r.m1_tilde, r.m2_tilde, r.n_candidates) == \
+            (ref.shift, ref.m1_tilde, ref.m2_tilde, ref.n_candidates)
